@@ -1,0 +1,109 @@
+"""Plant plausible mistakes in the CPU oracle and check that a pin catches each.
+
+Each case patches one oracle function with a wrong variant (wrong projector
+sign, missing boundary phase, wrong mass normalisation, no trace removal,
+flipped clover sign, a leaf built from the wrong links, a reversed leaf, a
+Laplacian sign slip, a conjugate on the wrong factor of the projection, a
+missing gamma5 in the adjoint) and asserts that the named pin now fails.
+Everything runs on the CPU; nothing here touches the GPU library.
+"""
+import numpy as np
+import pytest
+
+from oracle import dirac, laph
+import test_oracle_pins as pins
+
+_orig_hop = dirac.hop
+_orig_fs = dirac.field_strength
+_orig_ps = dirac.plaquette_sum
+_orig_ct = dirac.clover_term
+
+
+def _hop_flipped(U, psi, antiperiodic_t=True, dagger=False):
+    return _orig_hop(U, psi, antiperiodic_t, not dagger)
+
+
+def _hop_periodic(U, psi, antiperiodic_t=True, dagger=False):
+    return _orig_hop(U, psi, False, dagger)
+
+
+def _fs_no_trace(U, mu, nu):
+    q = dirac.plaquette_sum(U, mu, nu)
+    return (q - dirac.dag(q)) / 8.0
+
+
+def _ct_flipped(U, csw):
+    return -_orig_ct(U, csw)
+
+
+def _ps_wrong_link(U, mu, nu):
+    um, un = U[..., mu, :, :], U[..., nu, :, :]
+    s = dirac.site_shift
+    dag = dirac.dag
+    um_m = s(um, mu, -1)
+    un_n = s(un, nu, -1)
+    leaf1 = um @ s(un, mu, +1) @ dag(s(um, nu, +1)) @ dag(un)
+    leaf2 = un @ dag(s(um, nu, +1)) @ dag(s(un, mu, -1)) @ um_m      # U_mu(x+nu): wrong site
+    leaf3 = dag(um_m) @ dag(s(un_n, mu, -1)) @ s(um_m, nu, -1) @ un_n
+    leaf4 = dag(un_n) @ s(um, nu, -1) @ s(un_n, mu, +1) @ dag(um)
+    return leaf1 + leaf2 + leaf3 + leaf4
+
+
+def _ps_reversed_leaf(U, mu, nu):
+    um, un = U[..., mu, :, :], U[..., nu, :, :]
+    s = dirac.site_shift
+    dag = dirac.dag
+    leaf1 = um @ s(un, mu, +1) @ dag(s(um, nu, +1)) @ dag(un)
+    q = _orig_ps(U, mu, nu)
+    return q - leaf1 + dag(leaf1)
+
+
+class _WrongMass(dirac.WilsonClover):
+    def __init__(self, U, m0, csw=1.0, antiperiodic_t=True):
+        super().__init__(U, 2 * m0, csw, antiperiodic_t)
+
+
+def _neg_lap_wrong_sign(U3, f):
+    out = 6.0 * f
+    for k in range(3):
+        ax = -2 - k
+        uk = U3[..., k, :, :]
+        ub = np.roll(uk, +1, axis=-3 - k)
+        out = out + np.matmul(uk, np.roll(f, -1, axis=ax)[..., None])[..., 0]
+        out = out + np.matmul(dirac.dag(ub), np.roll(f, +1, axis=ax)[..., None])[..., 0]
+    return out
+
+
+def _project_conj_x(V, X, nev_src):
+    lt, nev, lz, ly, lx, _ = V.shape
+    Xr = X.reshape(nev_src, 4, lt, lz, ly, lx, 4, 3)
+    return np.einsum("tlzyxa,kctzyxba->tlkbc", V, np.conj(Xr))
+
+
+def _adjoint_no_g5(D, V, b, t_sink, tol=1e-13):
+    from oracle.solvers import bicgstab
+    L, X, tau = laph.loss_of_sources(D, V, b, t_sink, tol)
+    gx = laph.tau_cotangent_to_X(V, 2.0 * tau[t_sink], t_sink, X.shape)
+    Z, _ = bicgstab(D.apply, gx, tol=tol)
+    return L, Z, -float(np.sum(np.real(np.conj(Z) * X))), X
+
+
+CASES = [
+    ("hop projector sign", dirac, "hop", _hop_flipped, pins.test_free_field_plane_wave),
+    ("no antiperiodic phase", dirac, "hop", _hop_periodic, pins.test_free_field_propagator_closed_form),
+    ("mass normalisation", dirac, "WilsonClover", _WrongMass, pins.test_free_field_plane_wave),
+    ("no trace removal", dirac, "field_strength", _fs_no_trace, pins.test_clover_constant_flux_traceless_and_sign),
+    ("clover sign", dirac, "clover_term", _ct_flipped, pins.test_clover_constant_flux_traceless_and_sign),
+    ("leaf from wrong link", dirac, "plaquette_sum", _ps_wrong_link, pins.test_gauge_covariance_of_D_and_laplacian),
+    ("reversed leaf", dirac, "plaquette_sum", _ps_reversed_leaf, pins.test_clover_constant_flux_eigenvalues),
+    ("laplacian sign", laph, "neg_laplacian_apply", _neg_lap_wrong_sign, pins.test_free_laplacian_spectrum),
+    ("projection conjugate", laph, "project", _project_conj_x, pins.test_free_field_perambulator_and_mass_derivative),
+    ("adjoint without gamma5", laph, "adjoint_gradients", _adjoint_no_g5, pins.test_adjoint_gradients_vs_fd),
+]
+
+
+@pytest.mark.parametrize("name,mod,attr,bad,pin", CASES, ids=[c[0] for c in CASES])
+def test_pin_catches_planted_mistake(monkeypatch, name, mod, attr, bad, pin):
+    monkeypatch.setattr(mod, attr, bad)
+    with pytest.raises(AssertionError):
+        pin()
