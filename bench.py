@@ -1,0 +1,185 @@
+"""Benchmark of the LapH perambulator path on one MI355X.
+
+A step is one perambulator for one source time: 4 * nev spin-diluted LapH
+sources solved by the batched mixed-precision (FP16-with-norm inner, FP64
+reliable updates) even-odd BiCGStab to a full-lattice residual of 1e-10, then
+projected with the FP64 matrix-core GEMM onto the LapH vectors of every sink
+timeslice.  The default workload is the 32^3 x 64 headline case (nev = 64,
+256 RHS per source time, source times 0, 16, 32, 48 in turn); inputs are
+seeded synthetic fields already resident in HBM when the timed region starts.
+
+Prints one JSON line.  Only one GPU: ``--gpus N`` with N > 1 exits.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import laph_synth as ls  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+# FP32 vector peak without packed-FP32 instructions (the build disables them):
+# 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz
+ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# flops per output site and RHS of a fused stage: 8 hops x 180 (projection 24,
+# two SU(3) x colour-vector products 132, spin reconstruction 24) + two Hermitian
+# 6x6 clover blocks 2 x 252
+STAGE_FLOPS_PER_SITE_RHS = 8 * 180 + 2 * 252
+
+
+def stage_bytes_per_site(prec, n_rhs, stage):
+    """Algorithmic HBM bytes per output site of one launch of a fused stage.
+
+    Each input spinor, output spinor (and, stage 2, the xpay input p and the
+    shadow residual r^ of the fused <r^, v>) is moved once per RHS; the links
+    (8 per output site) and the clover inverse of the output site once per launch."""
+    sp = {"f64": 192, "f32": 96, "f16n": 52}[prec]
+    link = {"f64": 144, "f32": 48, "f16n": 24}[prec]
+    clov = {"f64": 576, "f32": 288, "f16n": 288}[prec]
+    per_rhs = sp * (2 if stage == 1 else 4)
+    return n_rhs * per_rhs + 8 * link + clov
+
+
+def cpu_baseline(cfg, dims, seconds_budget=20.0):
+    """The FP64 oracle timed on the host: full-lattice BiCGStab iterations on the
+    headline lattice for one LapH source, scaled to RHS/s with the iteration count
+    the oracle needs for 1e-10 on the same parameters (measured on 8^3 x 16)."""
+    from oracle import dirac, laph as olaph, solvers
+    m0, csw = cfg["masses"][0], cfg["csw"]
+    # iteration count at the same mass and gauge parameters on a small lattice
+    small = (8, 8, 8, 16)
+    Us = ls.gauge_field(small, cfg["seed_u"])
+    Vs = ls.orthonormal_laph_vectors(small, 1, cfg["seed_v"])
+    Ds = dirac.WilsonClover(Us, m0, csw)
+    _, info = solvers.bicgstab(Ds.apply, olaph.laph_sources(Vs, 0)[:1], tol=1e-10)
+    n_it = int(info["iters"][0])
+    # full-size iterations, bounded
+    U = ls.gauge_field(dims, cfg["seed_u"])
+    V1 = ls.orthonormal_laph_vectors(dims, 1, cfg["seed_v"])
+    D = dirac.WilsonClover(U, m0, csw)
+    b = olaph.laph_sources(V1, 0)[:1]
+    D.apply(b)  # first touch
+    t = time.perf_counter()
+    k = 0
+    while True:
+        k += 1
+        solvers.bicgstab(D.apply, b, tol=1e-30, maxiter=1, max_restarts=0)
+        if time.perf_counter() - t > seconds_budget * 0.5 or k >= 8:
+            break
+    per_iter = (time.perf_counter() - t) / k   # one BiCGStab iteration incl. its true-residual check
+    rhs_per_s = 1.0 / (per_iter * n_it)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": rhs_per_s, "unit": "RHS/s", "cores": cores, "kind": "oracle",
+            "sample": "%d full-lattice FP64 BiCGStab iterations (1 RHS) at %s, scaled by the %d iterations "
+                      "the oracle needs for 1e-10 at m0=%g (measured on 8^3x16)" % (k, "x".join(map(str, dims)),
+                                                                                  n_it, m0)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c4")
+    ap.add_argument("--prec", default="f16n")
+    ap.add_argument("--chunk", type=int, default=128)
+    ap.add_argument("--rhs-tile", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the perambulator path is measured on one MI355X "
+              "(independent RHS batches would shard across GPUs with no collective; see DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2510_26313_amd as laph
+
+    cfg = ls.CONFIGS[args.config]
+    dims = cfg["dims"]
+    nev = cfg["nev"]
+    m0 = cfg["masses"][0]
+    tol = 1e-10
+    t_setup = time.perf_counter()
+    U = ls.gauge_field(dims, cfg["seed_u"])
+    V = ls.orthonormal_laph_vectors(dims, nev, cfg["seed_v"])
+    lat = laph.Lattice(dims)
+    lat.load_gauge(torch.from_numpy(U).cuda())
+    del U
+    lat.set_masses([m0], cfg["csw"])
+    Vd = torch.from_numpy(V).cuda()
+    del V
+    params = laph.default_params(inner_prec=args.prec, batched=1, chunk=args.chunk, rhs_tile=args.rhs_tile)
+    setup_s = time.perf_counter() - t_setup
+    t0s = cfg["t0s"]
+
+    for i in range(args.warmup):
+        lat.perambulator_raw(Vd, t0s[i % len(t0s)], 0, tol, params)
+    torch.cuda.synchronize()
+    stats_all = []
+    ms_solve = ms_proj = 0.0
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        tau, st = lat.perambulator_raw(Vd, t0s[i % len(t0s)], 0, tol, params)
+        tm = lat.timings()
+        ms_solve += tm["solve_ms"]
+        ms_proj += tm["project_ms"]
+        stats_all += st
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    n_rhs = args.steps * 4 * nev
+    value = n_rhs / elapsed
+    worst = max(s["true_res"] for s in stats_all)
+    assert all(s["status"] == "converged" for s in stats_all) and worst <= tol, worst
+
+    # dominant kernels: the two fused stencil stages, timed with HIP events on the lattice stream
+    ms1, ms2 = lat.time_stages(args.prec, args.chunk, args.rhs_tile, 0, reps=20)
+    vh = int(np.prod(dims)) // 2
+    b1 = stage_bytes_per_site(args.prec, args.chunk, 1) * vh
+    gbs1 = b1 / (ms1 * 1e-3) / 1e9
+    fl1 = STAGE_FLOPS_PER_SITE_RHS * args.chunk * vh
+    tfl1 = fl1 / (ms1 * 1e-3) / 1e12
+    if tfl1 / ALU_PEAK_TFLOPS >= gbs1 / HBM_PEAK_GBS:
+        roofline = {"bound": "alu", "achieved": round(tfl1, 3), "peak": round(ALU_PEAK_TFLOPS, 1),
+                    "unit": "TFLOP/s", "frac": round(tfl1 / ALU_PEAK_TFLOPS, 4), "traffic": None}
+    else:
+        roofline = {"bound": "hbm", "achieved": round(gbs1, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs1 / HBM_PEAK_GBS, 4), "traffic": None}
+    roofline.update({"kernel": "stage_kernel (stage 1: A_oo^-1 H_oe, %s, rhs tile %d, %d RHS)"
+                               % (args.prec, args.rhs_tile, args.chunk),
+                     "ms_per_launch": round(ms1, 4), "algorithmic_bytes": b1, "hbm_gbs": round(gbs1, 1),
+                     "hbm_frac": round(gbs1 / HBM_PEAK_GBS, 4), "tflops": round(tfl1, 3),
+                     "stage2_ms_per_launch": round(ms2, 4)})
+
+    out = {
+        "metric": "perambulator RHS solved/s at rel. residual 1e-10; Dslash HBM GB/s vs peak",
+        "value": round(value, 3), "unit": "RHS/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f16n/f32 inner, f64 outer", "data": "synthetic",
+        "config": {"workload": "LapH perambulators %s, nev=%d, 4 source times x %d spin-diluted RHS, "
+                               "m0=%g, c_sw=%g, batched BiCGStab chunks of %d, tol 1e-10, projection on "
+                               "all %d sinks" % ("x".join(map(str, dims)), nev, 4 * nev, m0, cfg["csw"],
+                                                  args.chunk, dims[3]),
+                   "lattice": "x".join(map(str, dims)), "nev": nev, "rhs_per_step": 4 * nev,
+                   "inner_prec": args.prec, "chunk": args.chunk, "rhs_tile": args.rhs_tile},
+        "roofline": roofline,
+        "detail": {"solve_ms": round(ms_solve, 1), "project_ms": round(ms_proj, 1),
+                   "max_true_res": worst, "mean_iters": float(np.mean([s["iters"] for s in stats_all])),
+                   "mean_updates": float(np.mean([s["updates"] for s in stats_all])),
+                   "setup_s": round(setup_s, 1)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, dims, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,207 @@
+/*
+ * laph.h -- C ABI of the MI355X (gfx950) LapH perambulator library.
+ *
+ * What it computes (paper: Sec. "Current state-of-the-art", Sec. "LapH",
+ * Sec. "QUDA", Sec. "Eigenvector Projection", Sec. "Batched Linear Solves"):
+ * quark propagators X = D(m0)^-1 b from spin-diluted LapH sources b, and the
+ * perambulators tau = V^dagger D(m0)^-1 V obtained by projecting every solution
+ * onto the LapH vectors V of every sink timeslice.  The paper names the Dirac
+ * matrix but not its form; this library implements the Wilson-clover matrix
+ *
+ *   D = A - 1/2 H,   (H psi)(x) = sum_mu [ eta+ (1 - gamma_mu) U_mu(x) psi(x+mu)
+ *                                        + eta- (1 + gamma_mu) U_mu(x-mu)^+ psi(x-mu) ]
+ *   A = (4 + m0) + c_sw (i/2) sum_{mu<nu} sigma_munu F_munu   (two 6x6 Hermitian chiral blocks)
+ *
+ * in the DeGrand-Rossi chiral gamma basis, F_munu the traceless anti-Hermitian
+ * four-leaf clover, periodic links, and fermion hops across the time boundary
+ * multiplied by -1 when the context is created with t_antiperiodic = 1.
+ *
+ * Conventions shared by every call
+ *  - Every pointer argument is a DEVICE pointer unless its name ends in _host.
+ *  - The library never allocates device memory: the caller provides the
+ *    context state buffer (laph_attach_state) and a per-call workspace for the
+ *    solver entry points.  Buffers are owned by the caller and must stay alive
+ *    until the call's work on the context stream has finished.
+ *  - All work is enqueued on the stream given to laph_create.  laph_solve and
+ *    laph_perambulator synchronise that stream before returning (they return
+ *    host statistics); every other call is asynchronous.
+ *  - Inputs are never modified.  No call aborts or throws: each returns a
+ *    laph_status and, on failure, a message readable with laph_last_error().
+ *  - Canonical (boundary) layouts, C order, complex128 as interleaved (re, im):
+ *      gauge   U  [Lt][Lz][Ly][Lx][mu=4][3][3]
+ *      spinor  psi[nrhs][Lt][Lz][Ly][Lx][spin=4][colour=3]
+ *      LapH    V  [Lt][nev][Lz][Ly][Lx][3]        (V[t][l] = l-th vector of timeslice t)
+ *      tau        [Lt][nev][nev][4][4]            (tau[t][l][k][beta][alpha], sink t, l, beta;
+ *                                                 source k, alpha; RHS index r = 4k + alpha)
+ *  - Internal layouts (used by laph_apply_dslash / laph_apply_clover) are
+ *    even-odd structure-of-arrays per right-hand side; laph_field_bytes gives
+ *    their size and laph_pack_spinor / laph_unpack_spinor convert.
+ */
+#ifndef LAPH_H
+#define LAPH_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct laph_ctx_s *laph_ctx;
+
+typedef enum {
+    LAPH_OK = 0,
+    LAPH_ERR_INVALID = 1,    /* bad argument, shape, pointer or gauge field */
+    LAPH_ERR_HIP = 2,        /* HIP runtime error (message holds the HIP error string) */
+    LAPH_ERR_WORKSPACE = 3,  /* state or workspace missing or too small */
+    LAPH_ERR_NOCONV = 4,     /* some RHS missed the tolerance within maxiter (X, stats still written) */
+    LAPH_ERR_BREAKDOWN = 5,  /* BiCGStab broke down more often than the restart budget allows */
+    LAPH_ERR_NONFINITE = 6   /* a source or an iterate became NaN/Inf (that RHS only) */
+} laph_status;
+
+/* Storage precision of internal fields and of the solver's inner iterations. */
+typedef enum {
+    LAPH_F64 = 0,   /* FP64 storage, FP64 arithmetic */
+    LAPH_F32 = 1,   /* FP32 storage, FP32 arithmetic */
+    LAPH_F16N = 2   /* IEEE binary16 storage scaled by one FP32 norm per site and RHS
+                       (n = max |v| over the 24 reals, codes = fp16(v * (1/n))),
+                       FP32 arithmetic; gauge links in binary16 */
+} laph_prec;
+
+/* Per-RHS solver outcome (laph_rhs_stats.status). */
+enum { LAPH_RHS_ACTIVE = 0, LAPH_RHS_CONVERGED = 1, LAPH_RHS_NOCONV = 2,
+       LAPH_RHS_BREAKDOWN = 3, LAPH_RHS_NONFINITE = 4 };
+
+typedef struct {
+    int inner_prec;    /* laph_prec of the Krylov iterations (FP64 reliable updates always) */
+    int batched;       /* 1: all RHS in one solver invocation; 0: one RHS after another */
+    double delta;      /* reliable update when |r_inner| < delta * |r| at the last update;
+                          <= 0 picks 0.1 (F16N), 0.01 (F32), 0 (F64: update only at the end) */
+    int maxiter;       /* per RHS; <= 0 picks 10000 */
+    int graph_iters;   /* iterations per captured HIP graph between host polls; <= 0 picks 8 */
+    int use_graph;     /* 1: replay captured HIP graphs; 0: plain launches */
+    int dagger;        /* 1: solve D^dagger x = b (= gamma5 D gamma5 x = b) */
+    int use_x0;        /* 1: start from the contents of X instead of zero */
+    int rhs_tile;      /* RHS per Dslash thread tile (1, 2 or 4); <= 0: autotuned */
+    int chunk;         /* laph_perambulator: RHS per solver batch; <= 0: largest that fits */
+} laph_solve_params;
+
+typedef struct {
+    int status;        /* LAPH_RHS_* */
+    int iters;         /* Krylov iterations */
+    int updates;       /* FP64 reliable updates */
+    int restarts;      /* breakdown restarts */
+    double true_res;   /* ||b - D x|| / ||b|| on the full lattice, FP64, at exit */
+} laph_rhs_stats;
+
+/* Fill *p with the defaults described above. */
+void laph_default_params(laph_solve_params *p);
+
+/* Create a context for an Lx x Ly x Lz x Lt lattice (dims[0..3]); every extent
+ * must be even and >= 4.  n_mass_max bounds the number of masses laph_set_clover
+ * may hold.  hip_stream is a hipStream_t (NULL = the default stream).  The
+ * context owns no device memory until laph_attach_state. */
+laph_status laph_create(laph_ctx *out, const int dims[4], int t_antiperiodic,
+                        int n_mass_max, void *hip_stream);
+laph_status laph_destroy(laph_ctx ctx);
+
+/* Message of the last failure on the calling thread (valid until the next call). */
+const char *laph_last_error(void);
+
+/* Device bytes for the context state (gauge copies in FP64 / FP32 / FP16 and
+ * the clover term and its inverses for n_mass_max masses), and attach a
+ * caller-owned buffer of at least that size (256-byte aligned). */
+size_t laph_state_bytes(laph_ctx ctx);
+laph_status laph_attach_state(laph_ctx ctx, void *dev, size_t bytes);
+
+/* Load the gauge field (canonical layout, device).  Fails with INVALID if any
+ * link is further than 1e-10 from SU(3) (|U U^+ - 1| or |det U - 1|). */
+laph_status laph_load_gauge(laph_ctx ctx, const double *U);
+
+/* Build the clover term from the loaded links and, for each of the n_mass
+ * masses m0_host[i], the FP64 and FP32 inverses of its two chiral blocks per
+ * site.  INVALID if a block is not positive definite (e.g. 4 + m0 too small). */
+laph_status laph_set_clover(laph_ctx ctx, double csw, int n_mass, const double *m0_host);
+
+/* Bytes of an internal spinor field of nrhs right-hand sides, one parity
+ * (parity_only = 1) or both. */
+size_t laph_field_bytes(laph_ctx ctx, int prec, int nrhs, int parity_only);
+
+/* Canonical complex128 <-> internal layout.  parity = 0 or 1 converts that
+ * parity (internal field parity-only), parity = -1 both (internal full field). */
+laph_status laph_pack_spinor(laph_ctx ctx, void *out, const double *in, int prec, int nrhs, int parity);
+laph_status laph_unpack_spinor(laph_ctx ctx, double *out, const void *in, int prec, int nrhs, int parity);
+
+/* out = H_{p, 1-p} in on internal parity-only fields (p = out_parity): the bare
+ * hopping sum without the -1/2 and without the clover term; dagger = 1 applies
+ * gamma5 H gamma5.  Single-application accuracy: FP64 ~1e-15, FP32 ~1e-7 relative. */
+laph_status laph_apply_dslash(laph_ctx ctx, void *out, const void *in, int out_parity,
+                              int prec, int nrhs, int dagger);
+
+/* out = A (inverse = 0) or A^-1 (inverse = 1) on internal parity-only fields of
+ * the given parity, with the mass laph_set_clover stored at mass_idx. */
+laph_status laph_apply_clover(laph_ctx ctx, void *out, const void *in, int parity, int mass_idx,
+                              int inverse, int prec, int nrhs);
+
+/* out = D in (dagger = 0) or D^dagger in, FP64, canonical layout, full lattice.
+ * work must hold laph_field_bytes(ctx, LAPH_F64, 2, 0) bytes. */
+laph_status laph_apply_D(laph_ctx ctx, double *out, const double *in, int mass_idx, int nrhs,
+                         int dagger, void *work, size_t work_bytes);
+
+/* Workspace for laph_solve with nrhs right-hand sides. */
+size_t laph_solve_workspace_bytes(laph_ctx ctx, int nrhs, const laph_solve_params *p);
+
+/* Solve D(m0[mass_idx_host[r]]) X_r = B_r for r < nrhs (canonical layouts) by
+ * even-odd preconditioned BiCGStab with inner iterations in p->inner_prec,
+ * FP64 reliable updates and FP64 inner products, until the FP64 full-lattice
+ * residual ||B_r - D X_r|| <= tol ||B_r||.  stats_host (nrhs entries, may be
+ * NULL) receives the per-RHS outcome.  Returns NOCONV / BREAKDOWN / NONFINITE
+ * if any RHS ended that way; X is written in every case. */
+laph_status laph_solve(laph_ctx ctx, double *X, const double *B, int nrhs,
+                       const int *mass_idx_host, double tol, const laph_solve_params *p,
+                       laph_rhs_stats *stats_host, void *work, size_t work_bytes);
+
+/* Workspace for laph_perambulator with nev LapH vectors per timeslice. */
+size_t laph_perambulator_workspace_bytes(laph_ctx ctx, int nev, const laph_solve_params *p);
+
+/* tau[t][l][k][beta][alpha] = sum_{x,a} conj(V_l(x,t)_a) X^(4k+alpha)(x,t)_(beta,a)
+ * for every sink timeslice t, with X^(4k+alpha) = D(m0[mass_idx])^-1 b^(4k+alpha)
+ * and b^(4k+alpha)(x,t)_(s,a) = delta_{t,t0} delta_{s,alpha} V_k(x,t0)_a.  The
+ * 4*nev solves run in batches of p->chunk RHS; solutions are projected with an
+ * FP64 matrix-core GEMM and never stored whole.  stats_host: 4*nev entries. */
+laph_status laph_perambulator(laph_ctx ctx, double *tau, const double *V, int nev, int t0,
+                              int mass_idx, double tol, const laph_solve_params *p,
+                              laph_rhs_stats *stats_host, void *work, size_t work_bytes);
+
+/* Building blocks of the perambulator, exposed for the differentiable wrapper:
+ *  laph_make_sources: B (canonical, 4*nev RHS) = spin-diluted sources at t0;
+ *  laph_project:      tau (as above) from solutions X (canonical, 4*nev_src RHS);
+ *  laph_project_adjoint: G_X (canonical, 4*nev_src RHS) = sum_l V_l(x,t) Gtau[t][l][k][beta][alpha]
+ *                     at every t (the adjoint of laph_project).
+ * work for laph_project / laph_project_adjoint: laph_project_workspace_bytes. */
+laph_status laph_make_sources(laph_ctx ctx, double *B, const double *V, int nev, int t0);
+size_t laph_project_workspace_bytes(laph_ctx ctx, int nev, int nev_src);
+laph_status laph_project(laph_ctx ctx, double *tau, const double *X, const double *V, int nev,
+                         int nev_src, void *work, size_t work_bytes);
+laph_status laph_project_adjoint(laph_ctx ctx, double *GX, const double *Gtau, const double *V,
+                                 int nev, int nev_src);
+
+/* Milliseconds of the last laph_solve / laph_perambulator split as
+ * [0] total, [1] solve, [2] projection (HIP events on the context stream). */
+laph_status laph_last_timings(laph_ctx ctx, double *ms_host3);
+
+/* Measurement of the solver's two fused stencil kernels on synthetic fields:
+ * launches the inner-iteration stages of M_hat exactly as the batched solver
+ * does for nrhs right-hand sides of one mass (mass_idx) in tiles of rhs_tile --
+ * stage 1: t_o = A_oo^-1 H_oe p_e;  stage 2: v_e = p_e - 1/4 A_ee^-1 H_eo t_o with
+ * the fused <r^, v> partial sums -- each reps times, and returns the average
+ * duration of one launch in ms_host2[0] (stage 1) and ms_host2[1] (stage 2),
+ * measured with HIP events on the context stream.  The fields hold a fixed
+ * byte pattern; work must hold laph_time_stages_workspace_bytes bytes. */
+size_t laph_time_stages_workspace_bytes(laph_ctx ctx, int prec, int nrhs, int rhs_tile);
+laph_status laph_time_stages(laph_ctx ctx, int prec, int nrhs, int rhs_tile, int mass_idx, int reps,
+                             void *work, size_t work_bytes, double *ms_host2);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LAPH_H */

@@ -1,0 +1,328 @@
+"""Python binding of liblaph: a context class and differentiable wrappers.
+
+Every computation runs in the HIP library; this module only allocates device
+buffers with PyTorch, passes pointers and the current HIP stream, and turns
+status codes into exceptions.  Tensors are complex128 on the GPU in the
+canonical layouts documented in ``include/laph.h``.
+"""
+import contextlib
+import ctypes
+
+import torch
+
+from . import _lib as L
+
+# the library's two chiral signs of gamma5 = diag(1, 1, -1, -1) are not needed
+# here: the adjoint solve is the library's dagger solve (D^dagger = gamma5 D gamma5)
+
+
+def default_params(**kw):
+    lib = L.load()
+    p = L.SolveParams()
+    lib.laph_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if k == "inner_prec" and isinstance(v, str):
+            v = L.PREC[v]
+        if not hasattr(p, k):
+            raise TypeError("unknown solver parameter %r" % k)
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check_tensor(t, shape, name):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_cuda:
+        raise TypeError("%s must be a complex128 CUDA tensor" % name)
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+
+
+def _stats_list(arr, n):
+    return [dict(status=L.RHS_STATUS.get(arr[i].status, arr[i].status), iters=arr[i].iters,
+                 updates=arr[i].updates, restarts=arr[i].restarts, true_res=arr[i].true_res)
+            for i in range(n)]
+
+
+class Lattice:
+    """A lattice context: gauge field, clover term for a set of masses, solver state.
+
+    dims = (Lx, Ly, Lz, Lt); t_antiperiodic selects the fermion time boundary."""
+
+    def __init__(self, dims, t_antiperiodic=True, n_mass_max=8, device="cuda"):
+        self.lib = L.load()
+        self.dims = tuple(int(d) for d in dims)
+        self.device = torch.device(device)
+        # a stream of its own (default priority): HIP graphs cannot be captured on
+        # the legacy default stream; calls order themselves against the caller's stream
+        self.stream = torch.cuda.Stream(self.device)
+        self.ctx = ctypes.c_void_p()
+        d = (ctypes.c_int * 4)(*self.dims)
+        L.check(self.lib.laph_create(ctypes.byref(self.ctx), d, int(bool(t_antiperiodic)), int(n_mass_max),
+                                     ctypes.c_void_p(self.stream.cuda_stream)))
+        nbytes = self.lib.laph_state_bytes(self.ctx)
+        self._state = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self._state.data_ptr()) % 256
+        L.check(self._run(self.lib.laph_attach_state, self.ctx, ctypes.c_void_p(self._state.data_ptr() + off), nbytes))
+        self.masses = ()
+        self.csw = None
+        lx, ly, lz, lt = self.dims
+        self.volume = lx * ly * lz * lt
+
+    @contextlib.contextmanager
+    def _on_stream(self):
+        cur = torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
+        try:
+            yield
+        finally:
+            cur.wait_stream(self.stream)
+
+    def _run(self, fn, *args):
+        with self._on_stream():
+            return fn(*args)
+
+    def __del__(self):
+        try:
+            if self.ctx:
+                self.lib.laph_destroy(self.ctx)
+                self.ctx = ctypes.c_void_p()
+        except Exception:
+            pass
+
+    # -- shapes -------------------------------------------------------------------
+    def gauge_shape(self):
+        lx, ly, lz, lt = self.dims
+        return (lt, lz, ly, lx, 4, 3, 3)
+
+    def spinor_shape(self, nrhs):
+        lx, ly, lz, lt = self.dims
+        return (nrhs, lt, lz, ly, lx, 4, 3)
+
+    def laph_shape(self, nev):
+        lx, ly, lz, lt = self.dims
+        return (lt, nev, lz, ly, lx, 3)
+
+    def _workspace(self, nbytes):
+        return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
+
+    # -- setup ----------------------------------------------------------------------
+    def load_gauge(self, U):
+        _check_tensor(U, self.gauge_shape(), "U")
+        L.check(self._run(self.lib.laph_load_gauge, self.ctx, _ptr(U)))
+        self.masses = ()
+
+    def set_masses(self, masses, csw=1.0):
+        masses = tuple(float(m) for m in masses)
+        if masses == self.masses and csw == self.csw:
+            return
+        arr = (ctypes.c_double * len(masses))(*masses)
+        L.check(self._run(self.lib.laph_set_clover, self.ctx, float(csw), len(masses), arr))
+        self.masses = masses
+        self.csw = csw
+
+    def mass_index(self, m0):
+        return self.masses.index(float(m0))
+
+    # -- internal-layout operators ----------------------------------------------------
+    def field_bytes(self, prec, nrhs, parity_only=True):
+        return self.lib.laph_field_bytes(self.ctx, L.PREC[prec], nrhs, int(parity_only))
+
+    def pack(self, psi, prec="f64", parity=-1):
+        n = psi.shape[0]
+        _check_tensor(psi, self.spinor_shape(n), "psi")
+        out = self._workspace(self.field_bytes(prec, n, parity >= 0))
+        L.check(self._run(self.lib.laph_pack_spinor, self.ctx, _ptr(out), _ptr(psi), L.PREC[prec], n, parity))
+        return out
+
+    def unpack(self, buf, nrhs, prec="f64", parity=-1):
+        out = torch.zeros(self.spinor_shape(nrhs), dtype=torch.complex128, device=self.device)
+        L.check(self._run(self.lib.laph_unpack_spinor, self.ctx, _ptr(out), _ptr(buf), L.PREC[prec], nrhs, parity))
+        return out
+
+    def apply_dslash(self, buf_in, nrhs, out_parity, prec="f64", dagger=False):
+        out = self._workspace(self.field_bytes(prec, nrhs, True))
+        L.check(self._run(self.lib.laph_apply_dslash, self.ctx, _ptr(out), _ptr(buf_in), out_parity, L.PREC[prec], nrhs,
+                                           int(dagger)))
+        return out
+
+    def apply_clover(self, buf_in, nrhs, parity, mass_idx=0, inverse=False, prec="f64"):
+        out = self._workspace(self.field_bytes(prec, nrhs, True))
+        L.check(self._run(self.lib.laph_apply_clover, self.ctx, _ptr(out), _ptr(buf_in), parity, mass_idx, int(inverse),
+                                           L.PREC[prec], nrhs))
+        return out
+
+    def apply_D(self, psi, mass_idx=0, dagger=False):
+        n = psi.shape[0]
+        _check_tensor(psi, self.spinor_shape(n), "psi")
+        out = torch.empty_like(psi)
+        w = self._workspace(self.field_bytes("f64", 2, False))
+        L.check(self._run(self.lib.laph_apply_D, self.ctx, _ptr(out), _ptr(psi), mass_idx, n, int(dagger), _ptr(w),
+                                      w.numel()))
+        return out
+
+    # -- solves ------------------------------------------------------------------------
+    def solve_raw(self, B, mass_idx, tol=1e-10, params=None, X0=None, raise_on_noconv=True):
+        """X = D^-1 B (or D^dagger^-1 B with params.dagger) for every RHS; returns (X, stats)."""
+        n = B.shape[0]
+        _check_tensor(B, self.spinor_shape(n), "B")
+        p = params if params is not None else default_params()
+        if isinstance(mass_idx, int):
+            mass_idx = [mass_idx] * n
+        mi = (ctypes.c_int * n)(*mass_idx)
+        if X0 is not None:
+            _check_tensor(X0, self.spinor_shape(n), "X0")
+            X = X0.clone()
+            p.use_x0 = 1
+        else:
+            X = torch.empty_like(B)
+            p.use_x0 = 0
+        w = self._workspace(self.lib.laph_solve_workspace_bytes(self.ctx, n, ctypes.byref(p)))
+        stats = (L.RhsStats * n)()
+        st = self._run(self.lib.laph_solve, self.ctx, _ptr(X), _ptr(B), n, mi, float(tol), ctypes.byref(p), stats,
+                                 _ptr(w), w.numel())
+        sl = _stats_list(stats, n)
+        if st != L.LAPH_OK and (raise_on_noconv or st != L.LAPH_ERR_NOCONV):
+            L.check(st, sl)
+        return X, sl
+
+    def perambulator_raw(self, V, t0, mass_idx=0, tol=1e-10, params=None):
+        """tau[t][l][k][beta][alpha] for sources at t0 (fused solve + projection)."""
+        nev = V.shape[1]
+        _check_tensor(V, self.laph_shape(nev), "V")
+        p = params if params is not None else default_params()
+        lt = self.dims[3]
+        tau = torch.zeros((lt, nev, nev, 4, 4), dtype=torch.complex128, device=self.device)
+        w = self._workspace(self.lib.laph_perambulator_workspace_bytes(self.ctx, nev, ctypes.byref(p)))
+        stats = (L.RhsStats * (4 * nev))()
+        st = self._run(self.lib.laph_perambulator, self.ctx, _ptr(tau), _ptr(V), nev, int(t0), int(mass_idx), float(tol),
+                                        ctypes.byref(p), stats, _ptr(w), w.numel())
+        sl = _stats_list(stats, 4 * nev)
+        L.check(st, sl)
+        return tau, sl
+
+    def perambulator_workspace_bytes(self, nev, params):
+        return self.lib.laph_perambulator_workspace_bytes(self.ctx, nev, ctypes.byref(params))
+
+    def timings(self):
+        ms = (ctypes.c_double * 3)()
+        L.check(self.lib.laph_last_timings(self.ctx, ms))
+        return dict(total_ms=ms[0], solve_ms=ms[1], project_ms=ms[2])
+
+    def time_stages(self, prec, nrhs, rhs_tile=4, mass_idx=0, reps=20):
+        """Average ms per launch of the solver's two fused stencil stages (HIP events)."""
+        w = self._workspace(self.lib.laph_time_stages_workspace_bytes(self.ctx, L.PREC[prec], nrhs, rhs_tile))
+        ms = (ctypes.c_double * 2)()
+        L.check(self._run(self.lib.laph_time_stages, self.ctx, L.PREC[prec], nrhs, rhs_tile, mass_idx, reps,
+                          _ptr(w), w.numel(), ms))
+        return ms[0], ms[1]
+
+    def make_sources(self, V, t0):
+        nev = V.shape[1]
+        _check_tensor(V, self.laph_shape(nev), "V")
+        B = torch.empty(self.spinor_shape(4 * nev), dtype=torch.complex128, device=self.device)
+        L.check(self._run(self.lib.laph_make_sources, self.ctx, _ptr(B), _ptr(V), nev, int(t0)))
+        return B
+
+    def project_raw(self, X, V):
+        nev = V.shape[1]
+        _check_tensor(V, self.laph_shape(nev), "V")
+        n = X.shape[0]
+        if n % 4:
+            raise ValueError("X must hold 4 * nev_src right-hand sides")
+        _check_tensor(X, self.spinor_shape(n), "X")
+        lt = self.dims[3]
+        tau = torch.zeros((lt, nev, n // 4, 4, 4), dtype=torch.complex128, device=self.device)
+        w = self._workspace(self.lib.laph_project_workspace_bytes(self.ctx, nev, n // 4))
+        L.check(self._run(self.lib.laph_project, self.ctx, _ptr(tau), _ptr(X), _ptr(V), nev, n // 4, _ptr(w), w.numel()))
+        return tau
+
+    def project_adjoint_raw(self, G_tau, V):
+        nev = V.shape[1]
+        nsrc = G_tau.shape[2]
+        G_tau = G_tau.contiguous()
+        _check_tensor(G_tau, (self.dims[3], nev, nsrc, 4, 4), "G_tau")
+        GX = torch.empty(self.spinor_shape(4 * nsrc), dtype=torch.complex128, device=self.device)
+        L.check(self._run(self.lib.laph_project_adjoint, self.ctx, _ptr(GX), _ptr(G_tau), _ptr(V), nev, nsrc))
+        return GX
+
+
+# ---------------------------------------------------------------------------
+# differentiable wrappers
+# ---------------------------------------------------------------------------
+
+class _SolveFn(torch.autograd.Function):
+    """X = D(m0)^-1 B.  Backward: Z = D(m0)^-dagger G_X (the library's dagger solve,
+    D^dagger = gamma5 D gamma5), grad_B = Z, grad_m0 = -sum Re<Z, X>."""
+
+    @staticmethod
+    def forward(ctx, lat, B, m0, tol, params_kw):
+        m = float(m0.detach().cpu())
+        lat.set_masses((m,), lat.csw if lat.csw is not None else 1.0)
+        p = default_params(**params_kw)
+        X, stats = lat.solve_raw(B.detach().contiguous(), 0, tol, p)
+        ctx.lat, ctx.tol, ctx.kw, ctx.m = lat, tol, params_kw, m
+        ctx.save_for_backward(X)
+        ctx.stats = stats
+        return X
+
+    @staticmethod
+    def backward(ctx, gX):
+        (X,) = ctx.saved_tensors
+        lat = ctx.lat
+        lat.set_masses((ctx.m,), lat.csw if lat.csw is not None else 1.0)
+        kw = dict(ctx.kw)
+        kw["dagger"] = 1
+        Z, _ = lat.solve_raw(gX.contiguous(), 0, ctx.tol, default_params(**kw))
+        g_m0 = -torch.sum(torch.real(torch.conj(Z) * X))
+        return None, Z, g_m0.to(torch.float64).reshape(()), None, None
+
+
+class _ProjectFn(torch.autograd.Function):
+    """tau = V^dagger X on every sink timeslice; backward G_X = V G_tau (V is a constant)."""
+
+    @staticmethod
+    def forward(ctx, lat, X, V):
+        ctx.lat = lat
+        ctx.save_for_backward(V)
+        return lat.project_raw(X.detach().contiguous(), V)
+
+    @staticmethod
+    def backward(ctx, g_tau):
+        (V,) = ctx.saved_tensors
+        return None, ctx.lat.project_adjoint_raw(g_tau, V), None
+
+
+def solve(lat, B, m0, tol=1e-10, csw=None, **params):
+    """Differentiable X = D(m0)^-1 B (gradients for B and the scalar tensor m0)."""
+    if csw is not None:
+        lat.csw = csw
+    if not isinstance(m0, torch.Tensor):
+        m0 = torch.tensor(float(m0), dtype=torch.float64)
+    return _SolveFn.apply(lat, B, m0, tol, params)
+
+
+def project(lat, X, V):
+    """Differentiable tau = V^dagger X (gradient for X)."""
+    return _ProjectFn.apply(lat, X, V)
+
+
+def perambulator(lat, V, t0, m0, tol=1e-10, csw=1.0, **params):
+    """tau = V^dagger D(m0)^-1 V from spin-diluted sources at t0.
+
+    Without autograd this is the library's fused call (solutions streamed in
+    batches, never stored whole); when gradients are needed it is composed as
+    sources -> solve -> projection, with the sources as a differentiable input."""
+    lat.csw = csw
+    need_grad = torch.is_grad_enabled() and isinstance(m0, torch.Tensor) and m0.requires_grad
+    if not need_grad:
+        lat.set_masses((float(m0),), csw)
+        tau, stats = lat.perambulator_raw(V, t0, 0, tol, default_params(**params))
+        return tau
+    B = lat.make_sources(V, t0)
+    X = solve(lat, B, m0, tol, **params)
+    return project(lat, X, V)

@@ -1,0 +1,429 @@
+// Fused BLAS-1 kernels of the batched BiCGStab, their FP64 partial reductions,
+// and the per-slot finalize kernels that turn the partials into the solver's
+// scalars on the device (no host round trip inside an iteration).
+//
+// Every vector kernel runs on a 2-D grid (site block, entry of the slot list)
+// and touches each site once; inner products are accumulated per site in the
+// kernel's arithmetic precision, per thread block in FP64 (wave shuffles, then
+// LDS) and across blocks by the finalize kernels in a fixed order, so results
+// are reproducible run to run.
+#include "laph_blas.h"
+
+namespace laph {
+
+constexpr int kB = 256;
+
+__device__ __forceinline__ void reduce_store(double *v, int nv, double *dst, size_t q_stride) {
+    __shared__ double red[kB / 64][4];
+    for (int q = 0; q < nv; ++q) {
+        double s = v[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        v[q] = s;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int q = 0; q < nv; ++q) red[wave][q] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int q = 0; q < nv; ++q) {
+            double s = 0;
+            for (int w = 0; w < kB / 64; ++w) s += red[w][q];
+            dst[q * q_stride] = s;
+        }
+}
+
+// slot of this block, or -1 if the block has nothing to do
+__device__ __forceinline__ int blas_slot(const BlasArgs &A, int mode) {
+    const int j = blockIdx.y;
+    if (j >= *A.nlist) return -1;
+    const int s = A.list[j];
+    const SlotState &st = A.st[s];
+    if (mode == kModeActive && st.status != LAPH_RHS_ACTIVE) return -1;
+    if (mode == kModeFlagged && !(st.status == LAPH_RHS_ACTIVE && st.flag != 0)) return -1;
+    return s;
+}
+
+template <class R>
+__device__ __forceinline__ cplx<R> c_of(double2 z) {
+    return {R(z.x), R(z.y)};
+}
+
+// p = r + beta (p - omega v);  beta == 0 means p = r (fresh start: p, v not read)
+template <class P>
+__global__ __launch_bounds__(kB) void p_update_kernel(BlasArgs A) {
+    using R = typename P::real;
+    const int s = blas_slot(A, kModeActive);
+    if (s < 0) return;
+    const int h = blockIdx.x * kB + threadIdx.x;
+    if (h >= A.vh) return;
+    const double2 beta = A.st[s].beta;
+    cplx<R> r[12];
+    SpinorIO<P>::load(A.r.at(s), A.vh, h, r);
+    if (beta.x == 0.0 && beta.y == 0.0) {
+        SpinorIO<P>::store(A.p.at(s), A.vh, h, r);
+        return;
+    }
+    const cplx<R> b = c_of<R>(beta), w = c_of<R>(A.st[s].omega);
+    cplx<R> p[12], v[12];
+    SpinorIO<P>::load(A.p.at(s), A.vh, h, p);
+    SpinorIO<P>::load(A.v.at(s), A.vh, h, v);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) p[c] = r[c] + b * (p[c] - w * v[c]);
+    SpinorIO<P>::store(A.p.at(s), A.vh, h, p);
+}
+
+// r = r - alpha v   (r becomes s)
+template <class P>
+__global__ __launch_bounds__(kB) void s_update_kernel(BlasArgs A) {
+    using R = typename P::real;
+    const int s = blas_slot(A, kModeActive);
+    if (s < 0) return;
+    const int h = blockIdx.x * kB + threadIdx.x;
+    if (h >= A.vh) return;
+    const cplx<R> al = c_of<R>(A.st[s].alpha);
+    cplx<R> r[12], v[12];
+    SpinorIO<P>::load(A.r.at(s), A.vh, h, r);
+    SpinorIO<P>::load(A.v.at(s), A.vh, h, v);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) r[c] = r[c] - al * v[c];
+    SpinorIO<P>::store(A.r.at(s), A.vh, h, r);
+}
+
+// x_lo += alpha p + omega s;  r = s - omega t;  partials <r^, r>, |r|^2
+template <class P, class PX>
+__global__ __launch_bounds__(kB) void xr_update_kernel(BlasArgs A) {
+    using R = typename P::real;
+    using RX = typename PX::real;
+    const int s = blas_slot(A, kModeActive);
+    if (s < 0) return;
+    const int h = blockIdx.x * kB + threadIdx.x;
+    double part[3] = {0, 0, 0};
+    if (h < A.vh) {
+        const cplx<R> al = c_of<R>(A.st[s].alpha), om = c_of<R>(A.st[s].omega);
+        cplx<R> p[12], r[12], t[12], rh[12];
+        cplx<RX> x[12];
+        SpinorIO<P>::load(A.p.at(s), A.vh, h, p);
+        SpinorIO<P>::load(A.r.at(s), A.vh, h, r);
+        SpinorIO<P>::load(A.t.at(s), A.vh, h, t);
+        SpinorIO<PX>::load(A.x.at(s), A.vh, h, x);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            cplx<R> dx = al * p[c] + om * r[c];
+            x[c] = x[c] + cplx<RX>{RX(dx.re), RX(dx.im)};
+            r[c] = r[c] - om * t[c];
+        }
+        SpinorIO<PX>::store(A.x.at(s), A.vh, h, x);
+        SpinorIO<P>::store(A.r.at(s), A.vh, h, r);
+        SpinorIO<P>::load(A.rh.at(s), A.vh, h, rh);
+        cplx<R> d = {R(0), R(0)};
+        R n2 = R(0);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            cmac_conj(d, rh[c], r[c]);
+            n2 += r[c].re * r[c].re + r[c].im * r[c].im;
+        }
+        part[0] = d.re;
+        part[1] = d.im;
+        part[2] = n2;
+    }
+    reduce_store(part, 3, A.partials + (size_t)s * 3 * A.nsb + blockIdx.x, A.nsb);
+}
+
+// reliable update, part 1: x64 += x_lo; x_lo = 0   (flagged slots)
+template <class PX>
+__global__ __launch_bounds__(kB) void accumulate_kernel(BlasArgs A, int mode) {
+    using RX = typename PX::real;
+    const int s = blas_slot(A, mode);
+    if (s < 0) return;
+    const int h = blockIdx.x * kB + threadIdx.x;
+    if (h >= A.vh) return;
+    cplx<RX> x[12];
+    cplx<double> y[12];
+    SpinorIO<PX>::load(A.x.at(s), A.vh, h, x);
+    SpinorIO<F64>::load(A.x64.at(s), A.vh, h, y);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        y[c] = y[c] + cplx<double>{(double)x[c].re, (double)x[c].im};
+        x[c] = {RX(0), RX(0)};
+    }
+    SpinorIO<F64>::store(A.x64.at(s), A.vh, h, y);
+    SpinorIO<PX>::store(A.x.at(s), A.vh, h, x);
+}
+
+// r = lo(r64); restart (flag 2) or init: r^ = r; init also zeroes x_lo.
+// partials <r^, r>, |r|^2
+template <class P, class PX>
+__global__ __launch_bounds__(kB) void lower_kernel(BlasArgs A, int mode, int init) {
+    using R = typename P::real;
+    const int s = blas_slot(A, mode);
+    if (s < 0) return;
+    const int h = blockIdx.x * kB + threadIdx.x;
+    double part[3] = {0, 0, 0};
+    if (h < A.vh) {
+        cplx<double> y[12];
+        SpinorIO<F64>::load(A.r64.at(s), A.vh, h, y);
+        cplx<R> r[12], rh[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) r[c] = {R(y[c].re), R(y[c].im)};
+        SpinorIO<P>::store(A.r.at(s), A.vh, h, r);
+        // work with the stored (rounded) values so r^ and r agree exactly
+        SpinorIO<P>::load(A.r.at(s), A.vh, h, r);
+        const bool reset = init || A.st[s].flag == 2;
+        if (reset) {
+            SpinorIO<P>::store(A.rh.at(s), A.vh, h, r);
+            SpinorIO<P>::load(A.rh.at(s), A.vh, h, rh);
+        } else {
+            SpinorIO<P>::load(A.rh.at(s), A.vh, h, rh);
+        }
+        if (init) {
+            cplx<typename PX::real> z[12];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) z[c] = {0, 0};
+            SpinorIO<PX>::store(A.x.at(s), A.vh, h, z);
+        }
+        cplx<R> d = {R(0), R(0)};
+        R n2 = R(0);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            cmac_conj(d, rh[c], r[c]);
+            n2 += r[c].re * r[c].re + r[c].im * r[c].im;
+        }
+        part[0] = d.re;
+        part[1] = d.im;
+        part[2] = n2;
+    }
+    reduce_store(part, 3, A.partials + (size_t)s * 3 * A.nsb + blockIdx.x, A.nsb);
+}
+
+// |v|^2 of one or two FP64 half-vectors per slot (partials q = 0)
+__global__ __launch_bounds__(kB) void norm2_kernel(BlasArgs A, Operand v1, Operand v2, int mode) {
+    const int s = blas_slot(A, mode);
+    if (s < 0) return;
+    const int h = blockIdx.x * kB + threadIdx.x;
+    double part[1] = {0};
+    if (h < A.vh) {
+        cplx<double> y[12];
+        SpinorIO<F64>::load(v1.at(s), A.vh, h, y);
+        double n2 = 0;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) n2 += y[c].re * y[c].re + y[c].im * y[c].im;
+        if (v2.base) {
+            SpinorIO<F64>::load(v2.at(s), A.vh, h, y);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) n2 += y[c].re * y[c].re + y[c].im * y[c].im;
+        }
+        part[0] = n2;
+    }
+    reduce_store(part, 1, A.partials + (size_t)s * 3 * A.nsb + blockIdx.x, A.nsb);
+}
+
+// dst = src (FP64 half-vectors) per slot
+__global__ __launch_bounds__(kB) void copy64_kernel(BlasArgs A, Operand dst, Operand src, int mode) {
+    const int s = blas_slot(A, mode);
+    if (s < 0) return;
+    const int h = blockIdx.x * kB + threadIdx.x;
+    if (h >= A.vh) return;
+    cplx<double> y[12];
+    SpinorIO<F64>::load(src.at(s), A.vh, h, y);
+    SpinorIO<F64>::store(dst.at(s), A.vh, h, y);
+}
+
+// ---------------------------------------------------------------------------
+// finalize kernels: one 64-thread wave per slot sums the partials in fixed order
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum_partials(const double *p, int nsb) {
+    double s = 0;
+    for (int i = threadIdx.x; i < nsb; i += 64) s += p[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    return s;
+}
+
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+    const double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ bool finite2(double2 a) { return isfinite(a.x) && isfinite(a.y); }
+__device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+__global__ void finalize_kernel(FinArgs A, int what) {
+    const int j = blockIdx.x;
+    if (j >= *A.nlist) return;
+    const int s = A.list[j];
+    SlotState &st = A.st[s];
+    const double *P = A.partials + (size_t)s * 3 * A.nsb;
+    const bool active = st.status == LAPH_RHS_ACTIVE;
+    switch (what) {
+        case kFinAlpha: {  // sigma = <r^, v>; alpha = rho / sigma
+            if (!active) return;
+            const double2 sig = make_double2(wave_sum_partials(P, A.nsb), wave_sum_partials(P + A.nsb, A.nsb));
+            if (threadIdx.x) return;
+            if (!finite2(sig) || cabs2(sig) <= 1e-300 * (cabs2(st.rho) + 1e-300) || cabs2(sig) == 0.0) {
+                st.alpha = make_double2(0, 0);
+                st.flag = 2;
+            } else {
+                st.alpha = cdiv(st.rho, sig);
+            }
+            return;
+        }
+        case kFinOmega: {  // omega = <t, s> / |t|^2
+            if (!active) return;
+            const double2 ts = make_double2(wave_sum_partials(P, A.nsb), wave_sum_partials(P + A.nsb, A.nsb));
+            const double tt = wave_sum_partials(P + 2 * A.nsb, A.nsb);
+            if (threadIdx.x) return;
+            if (!(tt > 0) || !isfinite(tt) || !finite2(ts)) {
+                st.omega = make_double2(0, 0);
+                st.flag = 2;
+            } else {
+                st.omega = make_double2(ts.x / tt, ts.y / tt);
+            }
+            return;
+        }
+        case kFinRho: {  // rho_new = <r^, r>, r2 = |r|^2; beta; decide on a reliable update
+            if (!active) return;
+            const double2 rn = make_double2(wave_sum_partials(P, A.nsb), wave_sum_partials(P + A.nsb, A.nsb));
+            const double r2 = wave_sum_partials(P + 2 * A.nsb, A.nsb);
+            if (threadIdx.x) return;
+            st.iters += 1;
+            st.r2 = r2;
+            if (!isfinite(r2) || !finite2(rn)) st.flag = 2;
+            if (st.flag != 2) {
+                if (cabs2(st.omega) == 0.0 || cabs2(st.rho) == 0.0 || cabs2(rn) == 0.0) {
+                    st.flag = 2;
+                } else {
+                    st.beta = cmul(cdiv(rn, st.rho), cdiv(st.alpha, st.omega));
+                }
+            }
+            st.rho_prev = st.rho;
+            st.rho = rn;
+            if (r2 <= st.stop2 || r2 < st.delta2 * st.r2_upd || st.iters >= st.maxiter) st.flag |= 1;
+            return;
+        }
+        case kFinUpdate: {  // r2_upd = |b_hat - M x64|^2 after a reliable update
+            if (!(active && st.flag != 0)) return;
+            const double r2 = wave_sum_partials(P, A.nsb);
+            if (threadIdx.x) return;
+            st.updates += 1;
+            st.r2_upd = r2;
+            if (!isfinite(r2)) {
+                st.status = LAPH_RHS_NONFINITE;
+            } else if (r2 <= st.stop2) {
+                st.status = LAPH_RHS_CONVERGED;
+            } else if (st.iters >= st.maxiter) {
+                st.status = LAPH_RHS_NOCONV;
+            } else if (st.flag == 2) {
+                st.restarts += 1;
+                if (st.restarts > A.max_restarts) st.status = LAPH_RHS_BREAKDOWN;
+            }
+            return;
+        }
+        case kFinRho2:    // after r = lo(r64): rho and beta from the corrected residual
+        case kFinInit: {  // first residual of a solve
+            const bool init = what == kFinInit;
+            if (!(active && (init || st.flag != 0))) return;
+            const double2 rn = make_double2(wave_sum_partials(P, A.nsb), wave_sum_partials(P + A.nsb, A.nsb));
+            const double r2 = wave_sum_partials(P + 2 * A.nsb, A.nsb);
+            if (threadIdx.x) return;
+            st.r2 = r2;
+            if (init || st.flag == 2) {
+                st.beta = make_double2(0, 0);
+                st.rho_prev = make_double2(1, 0);
+                st.alpha = make_double2(1, 0);
+                st.omega = make_double2(1, 0);
+            } else {
+                st.beta = cmul(cdiv(rn, st.rho_prev), cdiv(st.alpha, st.omega));
+            }
+            st.rho = rn;
+            st.flag = 0;
+            return;
+        }
+        case kFinBnorm: {  // |B|^2 of the full-lattice source; zero or non-finite sources end here
+            const double b2 = wave_sum_partials(P, A.nsb);
+            if (threadIdx.x) return;
+            st.bnorm2 = b2;
+            if (!isfinite(b2)) st.status = LAPH_RHS_NONFINITE;
+            return;
+        }
+        case kFinR64: {  // |r64|^2 at the start of a solve pass
+            if (!active) return;
+            const double r2 = wave_sum_partials(P, A.nsb);
+            if (threadIdx.x) return;
+            st.r2_upd = r2;
+            if (!isfinite(r2)) st.status = LAPH_RHS_NONFINITE;
+            else if (r2 <= st.stop2) st.status = LAPH_RHS_CONVERGED;
+            return;
+        }
+        case kFinTrueRes: {  // accumulate |B - D X|^2 (called for the even and the odd part)
+            const double r2 = wave_sum_partials(P, A.nsb);
+            if (threadIdx.x) return;
+            st.true_res2 += r2;
+            return;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+template <class F>
+static laph_status dispatch_prec(int prec, F &&f) {
+    if (prec == LAPH_F64) return f(F64{}, F64{});
+    if (prec == LAPH_F32) return f(F32{}, F32{});
+    return f(F16N{}, F32{});
+}
+
+laph_status blas_p_update(const Ctx &c, const BlasArgs &a, int prec) {
+    dim3 grid(a.nsb, a.nlist_max);
+    return dispatch_prec(prec, [&](auto P, auto) {
+        hipLaunchKernelGGL(p_update_kernel<decltype(P)>, grid, dim3(kB), 0, c.stream, a);
+        return check_launch("p_update_kernel");
+    });
+}
+laph_status blas_s_update(const Ctx &c, const BlasArgs &a, int prec) {
+    dim3 grid(a.nsb, a.nlist_max);
+    return dispatch_prec(prec, [&](auto P, auto) {
+        hipLaunchKernelGGL(s_update_kernel<decltype(P)>, grid, dim3(kB), 0, c.stream, a);
+        return check_launch("s_update_kernel");
+    });
+}
+laph_status blas_xr_update(const Ctx &c, const BlasArgs &a, int prec) {
+    dim3 grid(a.nsb, a.nlist_max);
+    return dispatch_prec(prec, [&](auto P, auto PX) {
+        hipLaunchKernelGGL((xr_update_kernel<decltype(P), decltype(PX)>), grid, dim3(kB), 0, c.stream, a);
+        return check_launch("xr_update_kernel");
+    });
+}
+laph_status blas_accumulate(const Ctx &c, const BlasArgs &a, int prec, int mode) {
+    dim3 grid(a.nsb, a.nlist_max);
+    return dispatch_prec(prec, [&](auto, auto PX) {
+        hipLaunchKernelGGL(accumulate_kernel<decltype(PX)>, grid, dim3(kB), 0, c.stream, a, mode);
+        return check_launch("accumulate_kernel");
+    });
+}
+laph_status blas_lower(const Ctx &c, const BlasArgs &a, int prec, int mode, int init) {
+    dim3 grid(a.nsb, a.nlist_max);
+    return dispatch_prec(prec, [&](auto P, auto PX) {
+        hipLaunchKernelGGL((lower_kernel<decltype(P), decltype(PX)>), grid, dim3(kB), 0, c.stream, a, mode, init);
+        return check_launch("lower_kernel");
+    });
+}
+laph_status blas_norm2(const Ctx &c, const BlasArgs &a, Operand v1, Operand v2, int mode) {
+    dim3 grid(a.nsb, a.nlist_max);
+    hipLaunchKernelGGL(norm2_kernel, grid, dim3(kB), 0, c.stream, a, v1, v2, mode);
+    return check_launch("norm2_kernel");
+}
+laph_status blas_copy64(const Ctx &c, const BlasArgs &a, Operand dst, Operand src, int mode) {
+    dim3 grid(a.nsb, a.nlist_max);
+    hipLaunchKernelGGL(copy64_kernel, grid, dim3(kB), 0, c.stream, a, dst, src, mode);
+    return check_launch("copy64_kernel");
+}
+laph_status blas_finalize(const Ctx &c, const FinArgs &f, int what) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(f.nlist_max), dim3(64), 0, c.stream, f, what);
+    return check_launch("finalize_kernel");
+}
+
+}  // namespace laph

@@ -1,0 +1,391 @@
+// Even-odd Wilson-clover stencil stages for gfx950.
+//
+// One thread owns one output site of the output parity and NR right-hand sides
+// (a "tile" of RHS that share one mass).  For each of the 8 hops the link is
+// loaded once and applied to the NR neighbour spinors, so the link and clover
+// traffic is amortised over the tile.  The (1 -/+ gamma_mu) projection halves
+// the colour work: only two colour vectors are multiplied by the link and the
+// other two spin rows are rebuilt from them.  The clover inverse of the output
+// site, the xpay terms and the solver's inner products are fused into the
+// epilogue, with FP64 per-block partial sums (wave shuffles, then LDS).
+//
+// Workgroup -> (site block, tile) uses an XCD-aware remap: workgroups that one
+// XCD receives are consecutive logical ids, and the tile index runs fastest,
+// so all tiles of a site block run on one XCD and share its L2 for the links.
+#pragma once
+
+#include <type_traits>
+
+#include "laph_host.h"
+
+namespace laph {
+
+constexpr int kBlock = 256;
+
+struct StageArgs {
+    Geom g;
+    GaugePtrs gp;
+    int out_parity;
+    Operand in, out, y, y2, z, w;
+    double a, a2, b, c;
+    const char *clover;
+    size_t clover_mass_stride;
+    const int *tile_slots;
+    const int *tile_mass;
+    const int *ntiles;
+    int ntiles_max;
+    int nsb;
+    const SlotState *st;
+    double *partials;
+};
+
+// --- spin projection: (1 + S gamma_mu) psi = (h0, h1, row2(h), row3(h)) --------
+// gamma_x rows: (i p3, i p2, -i p1, -i p0); gamma_y: (-p3, p2, p1, -p0);
+// gamma_z: (i p2, -i p3, -i p0, i p1); gamma_t: (p2, p3, p0, p1).
+template <int S, class R>
+__device__ __forceinline__ cplx<R> s_i(cplx<R> z) {  // S * i * z
+    return S > 0 ? mul_i(z) : mul_mi(z);
+}
+template <int S, class R>
+__device__ __forceinline__ cplx<R> s_1(cplx<R> z) {  // S * z
+    return S > 0 ? z : cplx<R>{-z.re, -z.im};
+}
+
+template <int MU, int S, class R>
+__device__ __forceinline__ void spin_project(const cplx<R> (&p)[12], cplx<R> (&h)[6]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (MU == 0) {
+            h[a] = p[a] + s_i<S>(p[9 + a]);
+            h[3 + a] = p[3 + a] + s_i<S>(p[6 + a]);
+        } else if (MU == 1) {
+            h[a] = p[a] - s_1<S>(p[9 + a]);
+            h[3 + a] = p[3 + a] + s_1<S>(p[6 + a]);
+        } else if (MU == 2) {
+            h[a] = p[a] + s_i<S>(p[6 + a]);
+            h[3 + a] = p[3 + a] - s_i<S>(p[9 + a]);
+        } else {
+            h[a] = p[a] + s_1<S>(p[6 + a]);
+            h[3 + a] = p[3 + a] + s_1<S>(p[9 + a]);
+        }
+    }
+}
+
+template <int MU, int S, class R>
+__device__ __forceinline__ void spin_accumulate(cplx<R> (&acc)[12], const cplx<R> (&u)[6]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        acc[a] = acc[a] + u[a];
+        acc[3 + a] = acc[3 + a] + u[3 + a];
+        if (MU == 0) {
+            acc[6 + a] = acc[6 + a] - s_i<S>(u[3 + a]);
+            acc[9 + a] = acc[9 + a] - s_i<S>(u[a]);
+        } else if (MU == 1) {
+            acc[6 + a] = acc[6 + a] + s_1<S>(u[3 + a]);
+            acc[9 + a] = acc[9 + a] - s_1<S>(u[a]);
+        } else if (MU == 2) {
+            acc[6 + a] = acc[6 + a] - s_i<S>(u[a]);
+            acc[9 + a] = acc[9 + a] + s_i<S>(u[3 + a]);
+        } else {
+            acc[6 + a] = acc[6 + a] + s_1<S>(u[a]);
+            acc[9 + a] = acc[9 + a] + s_1<S>(u[3 + a]);
+        }
+    }
+}
+
+// u = eta * L h  (ADJ: L^dagger h) for both colour vectors of the half spinor
+template <bool ADJ, class R>
+__device__ __forceinline__ void colour_mul(const cplx<R> (&L)[9], const cplx<R> (&h)[6], R eta, cplx<R> (&u)[6]) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cplx<R> s = {R(0), R(0)};
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                if (ADJ)
+                    cmac_conj(s, L[b * 3 + a], h[3 * j + b]);
+                else
+                    cmac(s, L[a * 3 + b], h[3 * j + b]);
+            }
+            u[3 * j + a] = eta * s;
+        }
+    }
+}
+
+template <class P, int NR, int MU, bool DAG>
+__device__ __forceinline__ void hop_mu(const StageArgs &A, int p, int h, const int (&x)[4],
+                                       const int (&slots)[NR], cplx<typename P::real> (&acc)[NR][12]) {
+    using R = typename P::real;
+    const Geom &g = A.g;
+    const int ext = MU == 0 ? g.lx : (MU == 1 ? g.ly : (MU == 2 ? g.lz : g.lt));
+    // forward hop: link U_mu(x), neighbour x + mu, projector (1 - gamma) [(1 + gamma) for dagger]
+    {
+        int n[4] = {x[0], x[1], x[2], x[3]};
+        R eta = R(1);
+        n[MU] = x[MU] + 1;
+        if (n[MU] == ext) {
+            n[MU] = 0;
+            if (MU == 3 && g.antiperiodic) eta = R(-1);
+        }
+        const int hn = cb_index(g, n[0], n[1], n[2], n[3]);
+        cplx<R> L[9];
+        GaugeIO<P>::load(A.gp, p, MU, g.vh, h, L);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (slots[r] < 0) continue;
+            cplx<R> psi[12], hs[6], u[6];
+            SpinorIO<P>::load(A.in.at(slots[r]), g.vh, hn, psi);
+            spin_project<MU, DAG ? 1 : -1>(psi, hs);
+            colour_mul<false>(L, hs, eta, u);
+            spin_accumulate<MU, DAG ? 1 : -1>(acc[r], u);
+        }
+    }
+    // backward hop: link U_mu(x - mu)^dagger, neighbour x - mu, projector (1 + gamma)
+    {
+        int n[4] = {x[0], x[1], x[2], x[3]};
+        R eta = R(1);
+        n[MU] = x[MU] - 1;
+        if (n[MU] < 0) {
+            n[MU] = ext - 1;
+            if (MU == 3 && g.antiperiodic) eta = R(-1);
+        }
+        const int hn = cb_index(g, n[0], n[1], n[2], n[3]);
+        cplx<R> L[9];
+        GaugeIO<P>::load(A.gp, 1 - p, MU, g.vh, hn, L);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (slots[r] < 0) continue;
+            cplx<R> psi[12], hs[6], u[6];
+            SpinorIO<P>::load(A.in.at(slots[r]), g.vh, hn, psi);
+            spin_project<MU, DAG ? -1 : 1>(psi, hs);
+            colour_mul<true>(L, hs, eta, u);
+            spin_accumulate<MU, DAG ? -1 : 1>(acc[r], u);
+        }
+    }
+}
+
+// FP64 block reduction of NV values per thread; thread 0 writes NV partials.
+template <int NV>
+__device__ __forceinline__ void block_reduce_store(double (&v)[NV], double *dst, size_t q_stride) {
+    __shared__ double red[kBlock / 64][NV > 0 ? NV : 1];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double s = v[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        v[q] = s;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) red[wave][q] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double s = 0;
+            for (int wv = 0; wv < kBlock / 64; ++wv) s += red[wv][q];
+            dst[q * q_stride] = s;
+        }
+    }
+}
+
+template <class P, int NR, bool DAG, bool CLOVER, bool PRE, int POST, int RED, bool FLAGGED>
+__global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs A) {
+    using R = typename P::real;
+    const int L = xcd_logical_block();
+    const int sb = L / A.ntiles_max;
+    const int tile = L - sb * A.ntiles_max;
+    if (sb >= A.nsb || tile >= *A.ntiles) return;
+    int slots[NR];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        int s = A.tile_slots[tile * NR + r];
+        if (FLAGGED && s >= 0 && !(A.st[s].flag != 0 && A.st[s].status == LAPH_RHS_ACTIVE)) s = -1;
+        slots[r] = s;
+        any |= s >= 0;
+    }
+    if (!any) return;
+    const Geom &g = A.g;
+    const int p = A.out_parity;
+    const int h = sb * kBlock + threadIdx.x;
+    const bool valid = h < g.vh;
+    constexpr int NQ = RED == 1 ? 2 : (RED == 2 ? 3 : (RED == 3 ? 1 : 0));
+    double part[NR][NQ > 0 ? NQ : 1];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int q = 0; q < (NQ > 0 ? NQ : 1); ++q) part[r][q] = 0.0;
+
+    if (valid) {
+        int x[4];
+        site_coords(g, p, h, x[0], x[1], x[2], x[3]);
+        cplx<R> acc[NR][12];
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int c = 0; c < 12; ++c) acc[r][c] = {R(0), R(0)};
+        hop_mu<P, NR, 0, DAG>(A, p, h, x, slots, acc);
+        hop_mu<P, NR, 1, DAG>(A, p, h, x, slots, acc);
+        hop_mu<P, NR, 2, DAG>(A, p, h, x, slots, acc);
+        hop_mu<P, NR, 3, DAG>(A, p, h, x, slots, acc);
+
+        if (PRE) {
+            const R cz = R(A.c);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                if (slots[r] < 0) continue;
+                cplx<R> zz[12];
+                SpinorIO<P>::load(A.z.at(slots[r]), g.vh, h, zz);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) acc[r][c] = acc[r][c] + cz * zz[c];
+            }
+        }
+        if (CLOVER) {
+            const char *cl = A.clover + (size_t)A.tile_mass[tile] * A.clover_mass_stride;
+#pragma unroll
+            for (int blk = 0; blk < 2; ++blk) {
+                R m[36];
+                CloverIO<P>::load(cl, blk, g.vh, h, m);
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    cplx<R> o[6];
+                    herm6_apply(m, &acc[r][6 * blk], o);
+#pragma unroll
+                    for (int i = 0; i < 6; ++i) acc[r][6 * blk + i] = o[i];
+                }
+            }
+        }
+        const R bb = R(A.b), aa = R(A.a), aa2 = R(A.a2);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (slots[r] < 0) continue;
+            cplx<R> res[12], yy[12];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) res[c] = bb * acc[r][c];
+            if (POST >= 1) {
+                SpinorIO<P>::load(A.y.at(slots[r]), g.vh, h, yy);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) res[c] = res[c] + aa * yy[c];
+            }
+            if (POST >= 2) {
+                cplx<R> y2[12];
+                SpinorIO<P>::load(A.y2.at(slots[r]), g.vh, h, y2);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) res[c] = res[c] + aa2 * y2[c];
+            }
+            SpinorIO<P>::store(A.out.at(slots[r]), g.vh, h, res);
+            if (RED == 1) {
+                cplx<R> ww[12];
+                SpinorIO<P>::load(A.w.at(slots[r]), g.vh, h, ww);
+                cplx<R> d = {R(0), R(0)};
+#pragma unroll
+                for (int c = 0; c < 12; ++c) cmac_conj(d, ww[c], res[c]);
+                part[r][0] = (double)d.re;
+                part[r][1] = (double)d.im;
+            } else if (RED == 2) {
+                cplx<R> d = {R(0), R(0)};
+                R n2 = R(0);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) {
+                    cmac_conj(d, res[c], yy[c]);
+                    n2 += res[c].re * res[c].re + res[c].im * res[c].im;
+                }
+                part[r][0] = (double)d.re;
+                part[r][1] = (double)d.im;
+                part[r][2] = (double)n2;
+            } else if (RED == 3) {
+                R n2 = R(0);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) n2 += res[c].re * res[c].re + res[c].im * res[c].im;
+                part[r][0] = (double)n2;
+            }
+        }
+    }
+    if constexpr (NQ > 0) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            double v[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) v[q] = part[r][q];
+            // every thread of the block takes part in the reduction (uniform branch)
+            if (slots[r] >= 0) {
+                block_reduce_store<NQ>(v, A.partials + ((size_t)slots[r] * 3) * A.nsb + sb, (size_t)A.nsb);
+                __syncthreads();
+            }
+        }
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// dispatch (instantiated per precision in dslash_f64/f32/f16.hip)
+// ---------------------------------------------------------------------------
+template <class P, int NR, bool DAG, bool CLOVER, bool PRE, int POST, int RED, bool FL>
+inline void launch_t(const StageArgs &a, hipStream_t st) {
+    const int nblk = pad8(a.nsb * a.ntiles_max);
+    hipLaunchKernelGGL((stage_kernel<P, NR, DAG, CLOVER, PRE, POST, RED, FL>), dim3(nblk), dim3(kBlock), 0, st, a);
+}
+
+// The (clover, pre, post, red) combinations the library uses.
+template <class P, int NR, bool DAG, bool FL>
+inline bool launch_combo(const StageSpec &s, const StageArgs &a, hipStream_t st) {
+    constexpr bool is64 = std::is_same<P, F64>::value;
+    const int key = s.clover * 1000 + s.pre * 100 + s.post * 10 + s.red;
+    if constexpr (FL) {
+        // masked reliable-update stages exist in FP64 only
+        if constexpr (is64) {
+            if (key == 1000) { launch_t<P, NR, DAG, true, false, 0, 0, FL>(a, st); return true; }
+            if (key == 1023) { launch_t<P, NR, DAG, true, false, 2, 3, FL>(a, st); return true; }
+        }
+        return false;
+    } else {
+        switch (key) {
+            case 1000: launch_t<P, NR, DAG, true, false, 0, 0, FL>(a, st); return true;     // A^-1 H in
+            case 1011: launch_t<P, NR, DAG, true, false, 1, 1, FL>(a, st); return true;     // v = p - A^-1 H t, <r^, v>
+            case 1012: launch_t<P, NR, DAG, true, false, 1, 2, FL>(a, st); return true;     // t = s - A^-1 H t, <t,s>,|t|^2
+            default: break;
+        }
+        if constexpr (NR == 1) {
+            if (key == 0) { launch_t<P, NR, DAG, false, false, 0, 0, FL>(a, st); return true; }  // bare hop
+        }
+        if constexpr (is64) {
+            switch (key) {
+                case 0: launch_t<P, NR, DAG, false, false, 0, 0, FL>(a, st); return true;
+                case 10: launch_t<P, NR, DAG, false, false, 1, 0, FL>(a, st); return true;    // y + b H in
+                case 13: launch_t<P, NR, DAG, false, false, 1, 3, FL>(a, st); return true;    // residual part
+                case 1023: launch_t<P, NR, DAG, true, false, 2, 3, FL>(a, st); return true;   // r64, |r64|^2
+                case 1100: launch_t<P, NR, DAG, true, true, 0, 0, FL>(a, st); return true;    // A^-1 (c z + H in)
+                default: break;
+            }
+        }
+        return false;
+    }
+}
+
+template <class P, int NR>
+inline bool launch_nr(const StageSpec &s, const StageArgs &a, hipStream_t st) {
+    if (s.dagger)
+        return s.flagged ? launch_combo<P, NR, true, true>(s, a, st) : launch_combo<P, NR, true, false>(s, a, st);
+    return s.flagged ? launch_combo<P, NR, false, true>(s, a, st) : launch_combo<P, NR, false, false>(s, a, st);
+}
+
+template <class P>
+inline bool launch_p(const StageSpec &s, const StageArgs &a, hipStream_t st) {
+    switch (s.tiles.nr) {
+        case 1: return launch_nr<P, 1>(s, a, st);
+        case 2: return launch_nr<P, 2>(s, a, st);
+        case 4: return launch_nr<P, 4>(s, a, st);
+        default: return false;
+    }
+}
+
+
+bool launch_stage_f64(const StageSpec &s, const StageArgs &a, hipStream_t st);
+bool launch_stage_f32(const StageSpec &s, const StageArgs &a, hipStream_t st);
+bool launch_stage_f16(const StageSpec &s, const StageArgs &a, hipStream_t st);
+
+}  // namespace laph

@@ -1,0 +1,459 @@
+// Host orchestration of the even-odd mixed-precision (batched) BiCGStab.
+//
+// Per batch of right-hand sides ("slots"):
+//   1. sources -> FP64 even/odd halves, |B|^2, even-odd prepared source b_hat
+//   2. r64 = b_hat - M_hat x64 (FP64), r = lower(r64), r^ = r
+//   3. iterations in the inner precision; every kernel reads its scalars from
+//      device memory and the finalize kernels compute alpha, omega, rho, beta
+//      and the reliable-update decision on the device; updates (x64 += x_lo,
+//      FP64 true residual, r = lower(r64)) are masked per slot inside the same
+//      launch sequence, so one captured HIP graph of K iterations serves every
+//      replay; the host only polls the per-slot status every K iterations and
+//      compacts the tile table when slots have finished
+//   4. odd reconstruction, FP64 full-lattice residual |B - D X| per slot
+// The paper batches solves so that the stencil coefficients are reused across
+// the batch (Sec. "Batched Linear Solves") and runs its sparse work in mixed
+// precision (Sec. "QUDA").
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "laph_solver.h"
+
+namespace laph {
+
+static int default_nr(int prec, int ns) {
+    (void)prec;
+    if (ns >= 4) return 4;
+    if (ns >= 2) return 2;
+    return 1;
+}
+
+size_t Solver::layout(const Ctx &c, int ns, int nr, int prec, char *base, WS *ws) {
+    const size_t h64 = c.hv(LAPH_F64), hlo = c.hv(prec), hx = c.hv(prec == LAPH_F64 ? LAPH_F64 : LAPH_F32);
+    const int nsb = stage_nsb(c);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += round256(bytes);
+        return o;
+    };
+    auto op = [&](size_t o, size_t stride) {
+        Operand r;
+        r.base = base ? base + o : nullptr;
+        r.stride = stride;
+        return r;
+    };
+    WS w;
+    w.E0 = op(take(ns * h64), h64);
+    w.E1 = op(take(ns * h64), h64);
+    w.E2 = op(take(ns * h64), h64);
+    w.O0 = op(take(ns * h64), h64);
+    w.O1 = op(take(ns * h64), h64);
+    w.r = op(take(ns * hlo), hlo);
+    w.rh = op(take(ns * hlo), hlo);
+    w.p = op(take(ns * hlo), hlo);
+    w.v = op(take(ns * hlo), hlo);
+    w.t = op(take(ns * hlo), hlo);
+    w.tmp = op(take(ns * hlo), hlo);
+    w.x = op(take(ns * hx), hx);
+    size_t o_st = take(ns * sizeof(SlotState));
+    size_t o_part = take((size_t)ns * 3 * nsb * sizeof(double));
+    size_t o_ints = take(((size_t)ns * nr + 3 * (size_t)ns + 8) * sizeof(int));
+    if (ws && base) {
+        w.st = reinterpret_cast<SlotState *>(base + o_st);
+        w.partials = reinterpret_cast<double *>(base + o_part);
+        int *ints = reinterpret_cast<int *>(base + o_ints);
+        w.tile_slots = ints;
+        w.tile_mass = ints + (size_t)ns * nr;
+        w.list = w.tile_mass + ns;
+        w.slot_mass = w.list + ns;
+        w.ntiles = w.slot_mass + ns;
+        w.nlist = w.ntiles + 1;
+        *ws = w;
+    }
+    return off;
+}
+
+size_t solver_workspace_bytes(const Ctx &c, int nslots, const laph_solve_params &p) {
+    const int nr = p.rhs_tile > 0 ? p.rhs_tile : default_nr(p.inner_prec, nslots);
+    return Solver::layout(c, nslots, nr, p.inner_prec, nullptr, nullptr);
+}
+
+laph_status Solver::init(const Ctx &ctx, int nslots, const laph_solve_params &params, char *work, size_t bytes) {
+    c = &ctx;
+    p = params;
+    ns = nslots;
+    prec = p.inner_prec;
+    nr = p.rhs_tile > 0 ? p.rhs_tile : default_nr(prec, ns);
+    if (nr != 1 && nr != 2 && nr != 4) return set_error(LAPH_ERR_INVALID, "rhs_tile must be 1, 2 or 4");
+    const size_t need = layout(ctx, ns, nr, prec, nullptr, nullptr);
+    if (!work || bytes < need)
+        return set_error(LAPH_ERR_WORKSPACE, "solver workspace too small: %zu < %zu bytes", bytes, need);
+    layout(ctx, ns, nr, prec, work, &ws);
+    nsb = stage_nsb(ctx);
+    host_ints.assign((size_t)ns * nr + 3 * (size_t)ns + 8, 0);
+    host_st.assign(ns, SlotState{});
+    return LAPH_OK;
+}
+
+Solver::~Solver() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+}
+
+BlasArgs Solver::blas(int list_max) const {
+    BlasArgs a;
+    a.vh = c->g.vh;
+    a.nsb = nsb;
+    a.list = ws.list;
+    a.nlist = ws.nlist;
+    a.nlist_max = list_max;
+    a.st = ws.st;
+    a.partials = ws.partials;
+    a.r = ws.r;
+    a.rh = ws.rh;
+    a.p = ws.p;
+    a.v = ws.v;
+    a.t = ws.t;
+    a.x = ws.x;
+    a.x64 = ws.E1;
+    a.r64 = ws.E2;
+    return a;
+}
+
+FinArgs Solver::fin(int list_max) const {
+    FinArgs f;
+    f.list = ws.list;
+    f.nlist = ws.nlist;
+    f.nlist_max = list_max;
+    f.nsb = nsb;
+    f.st = ws.st;
+    f.partials = ws.partials;
+    return f;
+}
+
+Tiles Solver::tiles() const {
+    Tiles t;
+    t.slots = ws.tile_slots;
+    t.mass = ws.tile_mass;
+    t.ntiles = ws.ntiles;
+    t.ntiles_max = ns;
+    t.nr = nr;
+    return t;
+}
+
+// Upload the slot list and the tile table for the given slots (grouped by mass).
+laph_status Solver::upload_tables(const std::vector<int> &slots) {
+    std::vector<int> sorted = slots;
+    std::stable_sort(sorted.begin(), sorted.end(), [&](int a, int b) { return mass[a] < mass[b]; });
+    int *ts = host_ints.data();
+    int *tm = ts + (size_t)ns * nr;
+    int *ls = tm + ns;
+    int *sm = ls + ns;
+    int *cnt = sm + ns;
+    std::fill(ts, ts + (size_t)ns * nr, -1);
+    int nt = 0;
+    for (size_t i = 0; i < sorted.size();) {
+        const int m = mass[sorted[i]];
+        int k = 0;
+        while (k < nr && i < sorted.size() && mass[sorted[i]] == m) ts[(size_t)nt * nr + k++] = sorted[i++];
+        tm[nt++] = m;
+    }
+    for (int i = nt; i < ns; ++i) tm[i] = 0;
+    for (size_t i = 0; i < slots.size(); ++i) ls[i] = slots[i];
+    for (int s = 0; s < ns; ++s) sm[s] = s < (int)mass.size() ? mass[s] : 0;
+    cnt[0] = nt;
+    cnt[1] = (int)slots.size();
+    LAPH_HIP(hipMemcpyAsync(ws.tile_slots, host_ints.data(), host_ints.size() * sizeof(int), hipMemcpyHostToDevice,
+                            c->stream));
+    // the copy reads host_ints asynchronously: wait before the buffer can change
+    LAPH_HIP(hipStreamSynchronize(c->stream));
+    return LAPH_OK;
+}
+
+laph_status Solver::download_state() {
+    LAPH_HIP(hipMemcpyAsync(host_st.data(), ws.st, ns * sizeof(SlotState), hipMemcpyDeviceToHost, c->stream));
+    LAPH_HIP(hipStreamSynchronize(c->stream));
+    return LAPH_OK;
+}
+
+laph_status Solver::upload_state() {
+    LAPH_HIP(hipMemcpyAsync(ws.st, host_st.data(), ns * sizeof(SlotState), hipMemcpyHostToDevice, c->stream));
+    LAPH_HIP(hipStreamSynchronize(c->stream));
+    return LAPH_OK;
+}
+
+// ---- stencil helpers --------------------------------------------------------
+laph_status Solver::stage(int sprec, int out_parity, Operand in, Operand out, int clover, int pre, Operand z,
+                          double cz, int post, Operand y, double a, Operand y2, double a2, double b, int red,
+                          Operand w, int flagged) {
+    StageSpec s;
+    s.prec = sprec;
+    s.out_parity = out_parity;
+    s.dagger = p.dagger;
+    s.clover = clover;
+    s.pre = pre;
+    s.post = post;
+    s.red = red;
+    s.flagged = flagged;
+    s.in = in;
+    s.out = out;
+    s.y = y;
+    s.y2 = y2;
+    s.z = z;
+    s.w = w;
+    s.a = a;
+    s.a2 = a2;
+    s.b = b;
+    s.c = cz;
+    s.tiles = tiles();
+    s.slots = ws.st;
+    s.partials = ws.partials;
+    return launch_stage(*c, s);
+}
+
+laph_status Solver::clover(int parity, int inverse, Operand in, Operand out, int post, Operand y, double a, double b,
+                           int nlist) {
+    CloverSpec s;
+    s.prec = LAPH_F64;
+    s.parity = parity;
+    s.inverse = inverse;
+    s.post = post;
+    s.in = in;
+    s.out = out;
+    s.y = y;
+    s.a = a;
+    s.b = b;
+    s.slot_list = ws.list;
+    s.slot_mass = ws.slot_mass;
+    s.n = nlist;
+    return launch_clover(*c, s);
+}
+
+// ---- one BiCGStab iteration (all kernels device-driven) ---------------------
+laph_status Solver::iteration() {
+    const Operand none;
+    BlasArgs a = blas(ns);
+    FinArgs f = fin(ns);
+    LAPH_TRY(blas_p_update(*c, a, prec));
+    // v = M_hat p,  <r^, v>
+    LAPH_TRY(stage(prec, 1, ws.p, ws.tmp, 1, 0, none, 0, 0, none, 0, none, 0, 1.0, 0, none, 0));
+    LAPH_TRY(stage(prec, 0, ws.tmp, ws.v, 1, 0, none, 0, 1, ws.p, 1.0, none, 0, -0.25, 1, ws.rh, 0));
+    LAPH_TRY(blas_finalize(*c, f, kFinAlpha));
+    // s = r - alpha v (in r)
+    LAPH_TRY(blas_s_update(*c, a, prec));
+    // t = M_hat s,  <t, s>, |t|^2
+    LAPH_TRY(stage(prec, 1, ws.r, ws.tmp, 1, 0, none, 0, 0, none, 0, none, 0, 1.0, 0, none, 0));
+    LAPH_TRY(stage(prec, 0, ws.tmp, ws.t, 1, 0, none, 0, 1, ws.r, 1.0, none, 0, -0.25, 2, none, 0));
+    LAPH_TRY(blas_finalize(*c, f, kFinOmega));
+    // x_lo += alpha p + omega s;  r = s - omega t;  rho, |r|^2, update decision
+    LAPH_TRY(blas_xr_update(*c, a, prec));
+    LAPH_TRY(blas_finalize(*c, f, kFinRho));
+    // reliable update of the flagged slots: x64 += x_lo, r64 = b_hat - M_hat x64 in FP64
+    LAPH_TRY(blas_accumulate(*c, a, prec, kModeFlagged));
+    LAPH_TRY(stage(LAPH_F64, 1, ws.E1, ws.O0, 1, 0, none, 0, 0, none, 0, none, 0, 1.0, 0, none, 1));
+    LAPH_TRY(stage(LAPH_F64, 0, ws.O0, ws.E2, 1, 0, none, 0, 2, ws.E0, 1.0, ws.E1, -1.0, 0.25, 3, none, 1));
+    LAPH_TRY(blas_finalize(*c, f, kFinUpdate));
+    LAPH_TRY(blas_lower(*c, a, prec, kModeFlagged, 0));
+    LAPH_TRY(blas_finalize(*c, f, kFinRho2));
+    return LAPH_OK;
+}
+
+laph_status Solver::run_iterations(int k) {
+    if (!p.use_graph) {
+        for (int i = 0; i < k; ++i) LAPH_TRY(iteration());
+        return LAPH_OK;
+    }
+    if (!graph_exec || graph_k != k) {
+        if (graph_exec) {
+            (void)hipGraphExecDestroy(graph_exec);
+            graph_exec = nullptr;
+        }
+        hipGraph_t graph = nullptr;
+        LAPH_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+        laph_status st = LAPH_OK;
+        for (int i = 0; i < k && st == LAPH_OK; ++i) st = iteration();
+        hipError_t e = hipStreamEndCapture(c->stream, &graph);
+        if (st != LAPH_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return set_error(LAPH_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            graph_exec = nullptr;
+            return set_error(LAPH_ERR_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
+        }
+        graph_k = k;
+    }
+    LAPH_HIP(hipGraphLaunch(graph_exec, c->stream));
+    return LAPH_OK;
+}
+
+// ---- sources ------------------------------------------------------------------
+laph_status Solver::load_sources(const SourceSpec &src) {
+    if (src.B) {
+        Operand e = ws.E0, o = ws.O1;
+        LAPH_TRY(pack_spinor(*c, e, src.B, LAPH_F64, src.n, 0, src.B_stride));
+        LAPH_TRY(pack_spinor(*c, o, src.B, LAPH_F64, src.n, 1, src.B_stride));
+        return LAPH_OK;
+    }
+    return make_laph_sources(*c, ws.E0, ws.O1, src.V, src.nev, src.t0, src.r_begin, src.n);
+}
+
+// ---- the full solve of n slots ----------------------------------------------------
+laph_status Solver::solve(const SourceSpec &src, const std::vector<int> &slot_mass, double tol, const double *X0,
+                          size_t X0_stride) {
+    const int n = src.n;
+    if (n > ns) return set_error(LAPH_ERR_INVALID, "batch larger than the workspace");
+    mass = slot_mass;
+    const Operand none;
+    std::vector<int> all(n);
+    for (int i = 0; i < n; ++i) all[i] = i;
+    LAPH_TRY(upload_tables(all));
+    double delta = p.delta;
+    if (delta <= 0) delta = prec == LAPH_F16N ? 0.1 : (prec == LAPH_F32 ? 0.01 : 0.0);
+    const int maxiter = p.maxiter > 0 ? p.maxiter : 10000;
+    for (int s = 0; s < ns; ++s) {
+        SlotState z{};
+        z.status = s < n ? LAPH_RHS_ACTIVE : LAPH_RHS_CONVERGED;
+        z.delta2 = delta * delta;
+        z.maxiter = maxiter;
+        host_st[s] = z;
+    }
+    LAPH_TRY(upload_state());
+    BlasArgs a = blas(n);
+    FinArgs f = fin(n);
+    // |B|^2 and the stopping threshold on the even-odd residual
+    LAPH_TRY(load_sources(src));
+    LAPH_TRY(blas_norm2(*c, a, ws.E0, ws.O1, kModeAll));
+    LAPH_TRY(blas_finalize(*c, f, kFinBnorm));
+    LAPH_TRY(download_state());
+    // |B - D X| = |A_ee r_e| for an exactly reconstructed odd half; 0.2 covers |A_ee| <~ 5
+    double stop_fac = 0.2 * tol;
+    for (int s = 0; s < n; ++s) {
+        SlotState &st = host_st[s];
+        st.stop2 = stop_fac * stop_fac * st.bnorm2;
+        if (st.status == LAPH_RHS_ACTIVE && st.bnorm2 == 0.0) st.status = LAPH_RHS_CONVERGED;
+    }
+    LAPH_TRY(upload_state());
+    bool have_x = X0 != nullptr;
+    if (have_x) LAPH_TRY(pack_spinor(*c, ws.E1, X0, LAPH_F64, n, 0, X0_stride));
+    else LAPH_HIP(hipMemsetAsync(ws.E1.base, 0, ws.E1.stride * n, c->stream));
+
+    // slots the current pass works on (all of them first, then those that missed tol)
+    std::vector<int> cur = all;
+    for (int pass = 0; pass < 4; ++pass) {
+        const int ncur = (int)cur.size();
+        a = blas(ncur);
+        f = fin(ncur);
+        // prepared source b_hat = A_ee^-1 (b_e + 1/2 H_eo A_oo^-1 b_o) in E0 (O0 scratch)
+        LAPH_TRY(clover(1, 1, ws.O1, ws.O0, 0, none, 0, 1.0, ncur));
+        LAPH_TRY(stage(LAPH_F64, 0, ws.O0, ws.E0, 1, 1, ws.E0, 2.0, 0, none, 0, none, 0, 0.5, 0, none, 0));
+        // r64 = b_hat - M_hat x64
+        if (have_x) {
+            LAPH_TRY(stage(LAPH_F64, 1, ws.E1, ws.O0, 1, 0, none, 0, 0, none, 0, none, 0, 1.0, 0, none, 0));
+            LAPH_TRY(stage(LAPH_F64, 0, ws.O0, ws.E2, 1, 0, none, 0, 2, ws.E0, 1.0, ws.E1, -1.0, 0.25, 3, none, 0));
+        } else {
+            LAPH_TRY(blas_copy64(*c, a, ws.E2, ws.E0, kModeActive));
+            LAPH_TRY(blas_norm2(*c, a, ws.E2, none, kModeActive));
+        }
+        LAPH_TRY(blas_finalize(*c, f, kFinR64));
+        LAPH_TRY(blas_lower(*c, a, prec, kModeActive, 1));
+        LAPH_TRY(blas_finalize(*c, f, kFinInit));
+        // iterate; the captured graph always spans ns slots (tables say which are live)
+        LAPH_TRY(download_state());
+        std::vector<int> active;
+        for (int s : cur)
+            if (host_st[s].status == LAPH_RHS_ACTIVE) active.push_back(s);
+        LAPH_TRY(upload_tables(active));
+        const int K = p.graph_iters > 0 ? p.graph_iters : 8;
+        int guard = 0;
+        while (!active.empty()) {
+            LAPH_TRY(run_iterations(K));
+            LAPH_TRY(download_state());
+            std::vector<int> still;
+            for (int s : active)
+                if (host_st[s].status == LAPH_RHS_ACTIVE) still.push_back(s);
+            if (still.size() != active.size()) {
+                active.swap(still);
+                if (!active.empty()) LAPH_TRY(upload_tables(active));
+            }
+            if (++guard * K > maxiter + 4 * K) break;
+        }
+        // all slots of the batch from here on
+        LAPH_TRY(upload_tables(all));
+        a = blas(n);
+        f = fin(n);
+        // any slot still active (host guard): fold x_lo into x64
+        LAPH_TRY(blas_accumulate(*c, a, prec, kModeActive));
+        // reconstruct x_o = A_oo^-1 (b_o + 1/2 H_oe x_e) into O0
+        LAPH_TRY(stage(LAPH_F64, 1, ws.E1, ws.O0, 1, 1, ws.O1, 2.0, 0, none, 0, none, 0, 0.5, 0, none, 0));
+        // true residual |B - D X|^2: even part in E0, odd part in O1
+        LAPH_TRY(download_state());
+        for (int s = 0; s < n; ++s) host_st[s].true_res2 = 0;
+        LAPH_TRY(upload_state());
+        LAPH_TRY(load_sources(src));
+        LAPH_TRY(clover(0, 0, ws.E1, ws.E0, 1, ws.E0, 1.0, -1.0, n));
+        LAPH_TRY(stage(LAPH_F64, 0, ws.O0, ws.E0, 0, 0, none, 0, 1, ws.E0, 1.0, none, 0, 0.5, 3, none, 0));
+        LAPH_TRY(blas_finalize(*c, f, kFinTrueRes));
+        LAPH_TRY(clover(1, 0, ws.O0, ws.O1, 1, ws.O1, 1.0, -1.0, n));
+        LAPH_TRY(stage(LAPH_F64, 1, ws.E1, ws.O1, 0, 0, none, 0, 1, ws.O1, 1.0, none, 0, 0.5, 3, none, 0));
+        LAPH_TRY(blas_finalize(*c, f, kFinTrueRes));
+        LAPH_TRY(download_state());
+        // slots that converged on the even-odd residual but miss tol on the full one go again
+        std::vector<int> redo;
+        for (int s = 0; s < n; ++s) {
+            SlotState &st = host_st[s];
+            const double tr = st.bnorm2 > 0 ? std::sqrt(st.true_res2 / st.bnorm2) : 0.0;
+            if (st.status == LAPH_RHS_CONVERGED && tr > tol && st.bnorm2 > 0) redo.push_back(s);
+        }
+        if (redo.empty() || pass == 3) break;
+        for (int s : redo) {
+            SlotState &st = host_st[s];
+            const double tr = std::sqrt(st.true_res2 / st.bnorm2);
+            st.stop2 *= 0.25 * (tol / tr) * (tol / tr);
+            st.status = LAPH_RHS_ACTIVE;
+            st.flag = 0;
+        }
+        LAPH_TRY(upload_state());
+        LAPH_TRY(upload_tables(redo));
+        cur = redo;
+        // sources again (E0 and O1 were overwritten by the residual check)
+        LAPH_TRY(load_sources(src));
+        have_x = true;
+    }
+    return LAPH_OK;
+}
+
+laph_status Solver::collect(laph_rhs_stats *out, int n, double tol, int *worst) {
+    LAPH_TRY(download_state());
+    int w = LAPH_OK;
+    for (int s = 0; s < n; ++s) {
+        const SlotState &st = host_st[s];
+        const double tr = st.bnorm2 > 0 ? std::sqrt(st.true_res2 / st.bnorm2) : 0.0;
+        int status = st.status;
+        if (status == LAPH_RHS_CONVERGED && !(tr <= tol)) status = LAPH_RHS_NOCONV;
+        if (status == LAPH_RHS_ACTIVE) status = LAPH_RHS_NOCONV;
+        if (!std::isfinite(tr)) status = LAPH_RHS_NONFINITE;
+        if (out) {
+            out[s].status = status;
+            out[s].iters = st.iters;
+            out[s].updates = st.updates;
+            out[s].restarts = st.restarts;
+            out[s].true_res = tr;
+        }
+        int code = status == LAPH_RHS_CONVERGED ? LAPH_OK
+                   : status == LAPH_RHS_NONFINITE ? LAPH_ERR_NONFINITE
+                   : status == LAPH_RHS_BREAKDOWN ? LAPH_ERR_BREAKDOWN
+                                                  : LAPH_ERR_NOCONV;
+        if (code == LAPH_ERR_NONFINITE || (code == LAPH_ERR_BREAKDOWN && w != LAPH_ERR_NONFINITE) ||
+            (code == LAPH_ERR_NOCONV && w == LAPH_OK))
+            w = code;
+    }
+    *worst = w;
+    return LAPH_OK;
+}
+
+}  // namespace laph
