@@ -90,9 +90,11 @@ def main():
     ap.add_argument("--config", default="c4")
     ap.add_argument("--prec", default="f16n")
     ap.add_argument("--chunk", type=int, default=128)
-    ap.add_argument("--rhs-tile", type=int, default=4)
+    ap.add_argument("--rhs-tile", type=int, default=16)
+    ap.add_argument("--stencil", type=int, default=2, help="1 register RHS tiles, 2 LDS-staged links")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--fp64-sample", type=int, default=4, help="RHS for the plain FP64 single-RHS comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the perambulator path is measured on one MI355X "
@@ -117,7 +119,8 @@ def main():
     lat.set_masses([m0], cfg["csw"])
     Vd = torch.from_numpy(V).cuda()
     del V
-    params = laph.default_params(inner_prec=args.prec, batched=1, chunk=args.chunk, rhs_tile=args.rhs_tile)
+    params = laph.default_params(inner_prec=args.prec, batched=1, chunk=args.chunk, rhs_tile=args.rhs_tile,
+                                 stencil=args.stencil)
     setup_s = time.perf_counter() - t_setup
     t0s = cfg["t0s"]
 
@@ -140,8 +143,24 @@ def main():
     worst = max(s["true_res"] for s in stats_all)
     assert all(s["status"] == "converged" for s in stats_all) and worst <= tol, worst
 
+    # the plain FP64 single-RHS solver on the same lattice, sources and tolerance (sampled RHS)
+    fp64 = None
+    if args.fp64_sample > 0:
+        B = lat.make_sources(Vd[:, :1].contiguous(), t0s[0])[:args.fp64_sample].contiguous()
+        p64 = laph.default_params(inner_prec="f64", batched=0, rhs_tile=1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st64 = lat.solve_raw(B, 0, tol, p64)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        fp64 = {"rhs_per_s": round(args.fp64_sample / dt, 3), "sample_rhs": args.fp64_sample,
+                "mean_iters": float(np.mean([s["iters"] for s in st64])),
+                "max_true_res": max(s["true_res"] for s in st64),
+                "speedup_of_batched_mixed": round(value / (args.fp64_sample / dt), 2)}
+        del B
+
     # dominant kernels: the two fused stencil stages, timed with HIP events on the lattice stream
-    ms1, ms2 = lat.time_stages(args.prec, args.chunk, args.rhs_tile, 0, reps=20)
+    ms1, ms2 = lat.time_stages(args.prec, args.chunk, args.rhs_tile, 0, reps=20, stencil=args.stencil)
     vh = int(np.prod(dims)) // 2
     b1 = stage_bytes_per_site(args.prec, args.chunk, 1) * vh
     gbs1 = b1 / (ms1 * 1e-3) / 1e9
@@ -153,8 +172,9 @@ def main():
     else:
         roofline = {"bound": "hbm", "achieved": round(gbs1, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(gbs1 / HBM_PEAK_GBS, 4), "traffic": None}
-    roofline.update({"kernel": "stage_kernel (stage 1: A_oo^-1 H_oe, %s, rhs tile %d, %d RHS)"
-                               % (args.prec, args.rhs_tile, args.chunk),
+    roofline.update({"kernel": "%s (stage 1: A_oo^-1 H_oe, %s, %d RHS per link load, %d RHS)"
+                               % ("stage_lds_kernel" if args.stencil == 2 else "stage_kernel", args.prec,
+                                  args.rhs_tile, args.chunk),
                      "ms_per_launch": round(ms1, 4), "algorithmic_bytes": b1, "hbm_gbs": round(gbs1, 1),
                      "hbm_frac": round(gbs1 / HBM_PEAK_GBS, 4), "tflops": round(tfl1, 3),
                      "stage2_ms_per_launch": round(ms2, 4)})
@@ -169,12 +189,13 @@ def main():
                                "all %d sinks" % ("x".join(map(str, dims)), nev, 4 * nev, m0, cfg["csw"],
                                                   args.chunk, dims[3]),
                    "lattice": "x".join(map(str, dims)), "nev": nev, "rhs_per_step": 4 * nev,
-                   "inner_prec": args.prec, "chunk": args.chunk, "rhs_tile": args.rhs_tile},
+                   "inner_prec": args.prec, "chunk": args.chunk, "rhs_tile": args.rhs_tile,
+                   "stencil": "lds_links" if args.stencil == 2 else "register_tiles"},
         "roofline": roofline,
         "detail": {"solve_ms": round(ms_solve, 1), "project_ms": round(ms_proj, 1),
                    "max_true_res": worst, "mean_iters": float(np.mean([s["iters"] for s in stats_all])),
                    "mean_updates": float(np.mean([s["updates"] for s in stats_all])),
-                   "setup_s": round(setup_s, 1)},
+                   "setup_s": round(setup_s, 1), "fp64_single_rhs": fp64},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, dims, args.cpu_seconds)

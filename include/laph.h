@@ -81,8 +81,11 @@ typedef struct {
     int use_graph;     /* 1: replay captured HIP graphs; 0: plain launches */
     int dagger;        /* 1: solve D^dagger x = b (= gamma5 D gamma5 x = b) */
     int use_x0;        /* 1: start from the contents of X instead of zero */
-    int rhs_tile;      /* RHS per Dslash thread tile (1, 2 or 4); <= 0: autotuned */
+    int rhs_tile;      /* RHS sharing one load of the links: register tiles 1, 2, 4;
+                          LDS-staged links 4, 8, 16; <= 0: chosen by the library */
     int chunk;         /* laph_perambulator: RHS per solver batch; <= 0: largest that fits */
+    int stencil;       /* inner stencil form: 1 register RHS tiles (one thread, several RHS),
+                          2 links staged in LDS (one wave per RHS); 0: chosen by the library */
 } laph_solve_params;
 
 typedef struct {
@@ -191,15 +194,16 @@ laph_status laph_last_timings(laph_ctx ctx, double *ms_host3);
 
 /* Measurement of the solver's two fused stencil kernels on synthetic fields:
  * launches the inner-iteration stages of M_hat exactly as the batched solver
- * does for nrhs right-hand sides of one mass (mass_idx) in tiles of rhs_tile --
+ * does for nrhs right-hand sides of one mass (mass_idx) in the stencil form
+ * `stencil` (1 register tiles, 2 LDS-staged links) with tiles of rhs_tile --
  * stage 1: t_o = A_oo^-1 H_oe p_e;  stage 2: v_e = p_e - 1/4 A_ee^-1 H_eo t_o with
  * the fused <r^, v> partial sums -- each reps times, and returns the average
  * duration of one launch in ms_host2[0] (stage 1) and ms_host2[1] (stage 2),
  * measured with HIP events on the context stream.  The fields hold a fixed
  * byte pattern; work must hold laph_time_stages_workspace_bytes bytes. */
 size_t laph_time_stages_workspace_bytes(laph_ctx ctx, int prec, int nrhs, int rhs_tile);
-laph_status laph_time_stages(laph_ctx ctx, int prec, int nrhs, int rhs_tile, int mass_idx, int reps,
-                             void *work, size_t work_bytes, double *ms_host2);
+laph_status laph_time_stages(laph_ctx ctx, int prec, int nrhs, int stencil, int rhs_tile, int mass_idx,
+                             int reps, void *work, size_t work_bytes, double *ms_host2);
 
 #ifdef __cplusplus
 }

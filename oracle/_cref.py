@@ -19,7 +19,7 @@ def build_oracle_c(force=True):
     """Compile the oracle's C code (gcc, OpenMP over sites)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fcx-limited-range", "-fPIC", "-shared",
                                _SRC, "-o", tmp])
         os.replace(tmp, _LIB)
     return _LIB

@@ -243,3 +243,58 @@ class EvenOdd:
     def reconstruct(self, b, xe):
         xo = self.o * self.Ainv(self.o * b + 0.5 * self.o * self.D.hop(self.e * xe))
         return self.e * xe + xo
+
+
+# --- sampled outputs ------------------------------------------------------------
+
+def _patch(U, t, z, y, x):
+    """The 3^4 block of links around site (t, z, y, x), periodic in every direction."""
+    lt, lz, ly, lx = U.shape[:4]
+    it = [(t + d) % lt for d in (-1, 0, 1)]
+    iz = [(z + d) % lz for d in (-1, 0, 1)]
+    iy = [(y + d) % ly for d in (-1, 0, 1)]
+    ix = [(x + d) % lx for d in (-1, 0, 1)]
+    return U[np.ix_(it, iz, iy, ix)]
+
+
+def clover_matrix_at(U, site, m0, csw):
+    """A(x) at one site: the clover leaves at x only touch links within distance 1,
+    so the whole-field construction on the periodic 3^4 block around x gives A(x)
+    at the block's centre."""
+    t, z, y, x = site
+    return clover_matrix(_patch(U, t, z, y, x), m0, csw)[1, 1, 1, 1]
+
+
+def apply_at_sites(U, psi, sites, m0, csw, antiperiodic_t=True, dagger=False):
+    """(D psi)(x) (or D^dagger) at the listed sites (t, z, y, x), straight from the
+    definition; psi has a leading RHS axis.  Returns (nrhs, nsites, 4, 3)."""
+    lt, lz, ly, lx = U.shape[:4]
+    ext = (lx, ly, lz, lt)
+    sg = -1.0 if dagger else 1.0
+    out = np.zeros((psi.shape[0], len(sites), 4, 3), dtype=np.complex128)
+    for i, (t, z, y, x) in enumerate(sites):
+        c = [x, y, z, t]
+        A = clover_matrix_at(U, (t, z, y, x), m0, csw)
+        v = psi[:, t, z, y, x].reshape(-1, 12)
+        res = (v @ A.T).reshape(-1, 4, 3)
+        hop = np.zeros_like(res)
+        for mu in range(4):
+            for k in (+1, -1):
+                n = list(c)
+                n[mu] += k
+                eta = 1.0
+                if n[mu] == ext[mu] or n[mu] < 0:
+                    n[mu] %= ext[mu]
+                    if mu == 3 and antiperiodic_t:
+                        eta = -1.0
+                nb = psi[:, n[3], n[2], n[1], n[0]]
+                if k > 0:
+                    link = U[t, z, y, x, mu]
+                    spin = np.eye(4) - sg * GAMMA[mu]
+                else:
+                    link = dag(U[n[3], n[2], n[1], n[0], mu])
+                    spin = np.eye(4) + sg * GAMMA[mu]
+                w = eta * np.einsum("ab,rsb->rsa", link, nb)
+                hop += np.einsum("st,rta->rsa", spin, w)
+        out[:, i] = res - 0.5 * hop
+    return out

@@ -213,12 +213,12 @@ class Lattice:
         L.check(self.lib.laph_last_timings(self.ctx, ms))
         return dict(total_ms=ms[0], solve_ms=ms[1], project_ms=ms[2])
 
-    def time_stages(self, prec, nrhs, rhs_tile=4, mass_idx=0, reps=20):
+    def time_stages(self, prec, nrhs, rhs_tile=4, mass_idx=0, reps=20, stencil=2):
         """Average ms per launch of the solver's two fused stencil stages (HIP events)."""
         w = self._workspace(self.lib.laph_time_stages_workspace_bytes(self.ctx, L.PREC[prec], nrhs, rhs_tile))
         ms = (ctypes.c_double * 2)()
-        L.check(self._run(self.lib.laph_time_stages, self.ctx, L.PREC[prec], nrhs, rhs_tile, mass_idx, reps,
-                          _ptr(w), w.numel(), ms))
+        L.check(self._run(self.lib.laph_time_stages, self.ctx, L.PREC[prec], nrhs, stencil, rhs_tile, mass_idx,
+                          reps, _ptr(w), w.numel(), ms))
         return ms[0], ms[1]
 
     def make_sources(self, V, t0):

@@ -127,7 +127,7 @@ __global__ __launch_bounds__(kB) void xr_update_kernel(BlasArgs A) {
         part[1] = d.im;
         part[2] = n2;
     }
-    reduce_store(part, 3, A.partials + (size_t)s * 3 * A.nsb + blockIdx.x, A.nsb);
+    reduce_store(part, 3, A.partials + (size_t)s * 3 * A.pstride + blockIdx.x, A.pstride);
 }
 
 // reliable update, part 1: x64 += x_lo; x_lo = 0   (flagged slots)
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(kB) void lower_kernel(BlasArgs A, int mode, int ini
         part[1] = d.im;
         part[2] = n2;
     }
-    reduce_store(part, 3, A.partials + (size_t)s * 3 * A.nsb + blockIdx.x, A.nsb);
+    reduce_store(part, 3, A.partials + (size_t)s * 3 * A.pstride + blockIdx.x, A.pstride);
 }
 
 // |v|^2 of one or two FP64 half-vectors per slot (partials q = 0)
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kB) void norm2_kernel(BlasArgs A, Operand v1, Opera
         }
         part[0] = n2;
     }
-    reduce_store(part, 1, A.partials + (size_t)s * 3 * A.nsb + blockIdx.x, A.nsb);
+    reduce_store(part, 1, A.partials + (size_t)s * 3 * A.pstride + blockIdx.x, A.pstride);
 }
 
 // dst = src (FP64 half-vectors) per slot
@@ -255,12 +255,12 @@ __global__ void finalize_kernel(FinArgs A, int what) {
     if (j >= *A.nlist) return;
     const int s = A.list[j];
     SlotState &st = A.st[s];
-    const double *P = A.partials + (size_t)s * 3 * A.nsb;
+    const double *P = A.partials + (size_t)s * 3 * A.pstride;
     const bool active = st.status == LAPH_RHS_ACTIVE;
     switch (what) {
         case kFinAlpha: {  // sigma = <r^, v>; alpha = rho / sigma
             if (!active) return;
-            const double2 sig = make_double2(wave_sum_partials(P, A.nsb), wave_sum_partials(P + A.nsb, A.nsb));
+            const double2 sig = make_double2(wave_sum_partials(P, A.nsb), wave_sum_partials(P + A.pstride, A.nsb));
             if (threadIdx.x) return;
             if (!finite2(sig) || cabs2(sig) <= 1e-300 * (cabs2(st.rho) + 1e-300) || cabs2(sig) == 0.0) {
                 st.alpha = make_double2(0, 0);
@@ -272,8 +272,8 @@ __global__ void finalize_kernel(FinArgs A, int what) {
         }
         case kFinOmega: {  // omega = <t, s> / |t|^2
             if (!active) return;
-            const double2 ts = make_double2(wave_sum_partials(P, A.nsb), wave_sum_partials(P + A.nsb, A.nsb));
-            const double tt = wave_sum_partials(P + 2 * A.nsb, A.nsb);
+            const double2 ts = make_double2(wave_sum_partials(P, A.nsb), wave_sum_partials(P + A.pstride, A.nsb));
+            const double tt = wave_sum_partials(P + 2 * A.pstride, A.nsb);
             if (threadIdx.x) return;
             if (!(tt > 0) || !isfinite(tt) || !finite2(ts)) {
                 st.omega = make_double2(0, 0);
@@ -285,8 +285,8 @@ __global__ void finalize_kernel(FinArgs A, int what) {
         }
         case kFinRho: {  // rho_new = <r^, r>, r2 = |r|^2; beta; decide on a reliable update
             if (!active) return;
-            const double2 rn = make_double2(wave_sum_partials(P, A.nsb), wave_sum_partials(P + A.nsb, A.nsb));
-            const double r2 = wave_sum_partials(P + 2 * A.nsb, A.nsb);
+            const double2 rn = make_double2(wave_sum_partials(P, A.nsb), wave_sum_partials(P + A.pstride, A.nsb));
+            const double r2 = wave_sum_partials(P + 2 * A.pstride, A.nsb);
             if (threadIdx.x) return;
             st.iters += 1;
             st.r2 = r2;
@@ -325,8 +325,8 @@ __global__ void finalize_kernel(FinArgs A, int what) {
         case kFinInit: {  // first residual of a solve
             const bool init = what == kFinInit;
             if (!(active && (init || st.flag != 0))) return;
-            const double2 rn = make_double2(wave_sum_partials(P, A.nsb), wave_sum_partials(P + A.nsb, A.nsb));
-            const double r2 = wave_sum_partials(P + 2 * A.nsb, A.nsb);
+            const double2 rn = make_double2(wave_sum_partials(P, A.nsb), wave_sum_partials(P + A.pstride, A.nsb));
+            const double r2 = wave_sum_partials(P + 2 * A.pstride, A.nsb);
             if (threadIdx.x) return;
             st.r2 = r2;
             if (init || st.flag == 2) {

@@ -513,7 +513,7 @@ static size_t time_stages_layout(const Ctx &c, int prec, int nrhs, int rhs_tile,
     const int ntiles = (nrhs + rhs_tile - 1) / rhs_tile;
     size_t off = 4 * (size_t)nrhs * hv;   // p (even), t (odd), v (even), r^ (even)
     *off_part = off;
-    off += round256((size_t)nrhs * 3 * stage_nsb(c) * sizeof(double));
+    off += round256((size_t)nrhs * 3 * partial_stride(c) * sizeof(double));
     *off_ints = off;
     off += round256(((size_t)ntiles * rhs_tile + ntiles + 1) * sizeof(int));
     return off;
@@ -525,12 +525,15 @@ size_t laph_time_stages_workspace_bytes(laph_ctx h, int prec, int nrhs, int rhs_
     return time_stages_layout(C(h), prec, nrhs, rhs_tile, &a, &b);
 }
 
-laph_status laph_time_stages(laph_ctx h, int prec, int nrhs, int rhs_tile, int mass_idx, int reps, void *work,
-                             size_t work_bytes, double *ms_host2) {
+laph_status laph_time_stages(laph_ctx h, int prec, int nrhs, int stencil, int rhs_tile, int mass_idx, int reps,
+                             void *work, size_t work_bytes, double *ms_host2) {
     LAPH_TRY(check_ctx(h, true, true));
     Ctx &c = C(h);
-    if (!valid_prec(prec) || nrhs <= 0 || nrhs > 65535 || reps <= 0 || !ms_host2 ||
-        (rhs_tile != 1 && rhs_tile != 2 && rhs_tile != 4) || mass_idx < 0 || mass_idx >= c.n_mass)
+    const int form = stencil == 2 ? kFormLds : kFormRegister;
+    const bool tile_ok = form == kFormLds ? (rhs_tile == 4 || rhs_tile == 8 || rhs_tile == 16) && prec != LAPH_F64
+                                          : (rhs_tile == 1 || rhs_tile == 2 || rhs_tile == 4);
+    if (!valid_prec(prec) || nrhs <= 0 || nrhs > 65535 || reps <= 0 || !ms_host2 || !tile_ok || mass_idx < 0 ||
+        mass_idx >= c.n_mass || (stencil != 1 && stencil != 2))
         return set_error(LAPH_ERR_INVALID, "bad arguments");
     size_t off_ints, off_part;
     const size_t need = time_stages_layout(c, prec, nrhs, rhs_tile, &off_ints, &off_part);
@@ -555,6 +558,8 @@ laph_status laph_time_stages(laph_ctx h, int prec, int nrhs, int rhs_tile, int m
     t.nr = rhs_tile;
     StageSpec s1;
     s1.prec = prec;
+    s1.form = form;
+    s1.pstride = partial_stride(c);
     s1.out_parity = 1;
     s1.clover = 1;
     s1.in = Operand{w, hv};

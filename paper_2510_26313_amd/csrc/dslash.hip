@@ -1,10 +1,15 @@
 // Launch of the even-odd stencil stages (kernels in dslash_kernels.h) and the
 // single-parity clover apply kernel.
-#include "dslash_kernels.h"
+#include "dslash_lds.h"
 
 namespace laph {
 
-int stage_nsb(const Ctx &c) { return (c.g.vh + kBlock - 1) / kBlock; }
+int stage_nsb(const Ctx &c, int form) {
+    const int sites = form == kFormLds ? kLdsSites : kBlock;
+    return (c.g.vh + sites - 1) / sites;
+}
+
+int partial_stride(const Ctx &c) { return stage_nsb(c, kFormLds); }
 
 laph_status launch_stage(const Ctx &c, const StageSpec &s) {
     StageArgs a;
@@ -27,17 +32,25 @@ laph_status launch_stage(const Ctx &c, const StageSpec &s) {
     a.tile_mass = s.tiles.mass;
     a.ntiles = s.tiles.ntiles;
     a.ntiles_max = s.tiles.ntiles_max;
-    a.nsb = stage_nsb(c);
+    a.nsb = stage_nsb(c, s.form);
+    a.pstride = s.pstride;
     a.st = s.slots;
     a.partials = s.partials;
     if (a.ntiles_max <= 0) return LAPH_OK;
+    if (s.red && s.pstride < a.nsb) return set_error(LAPH_ERR_INVALID, "partial-sum stride too small");
     bool ok = false;
-    if (s.prec == LAPH_F64)
+    if (s.form == kFormLds) {
+        if (s.prec == LAPH_F32)
+            ok = launch_stage_lds_f32(s, a, c.stream);
+        else if (s.prec == LAPH_F16N)
+            ok = launch_stage_lds_f16(s, a, c.stream);
+    } else if (s.prec == LAPH_F64) {
         ok = launch_stage_f64(s, a, c.stream);
-    else if (s.prec == LAPH_F32)
+    } else if (s.prec == LAPH_F32) {
         ok = launch_stage_f32(s, a, c.stream);
-    else if (s.prec == LAPH_F16N)
+    } else if (s.prec == LAPH_F16N) {
         ok = launch_stage_f16(s, a, c.stream);
+    }
     if (!ok) return set_error(LAPH_ERR_INVALID, "unsupported stencil stage combination");
     return check_launch("stage_kernel");
 }

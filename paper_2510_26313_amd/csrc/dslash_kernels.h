@@ -22,6 +22,14 @@ namespace laph {
 
 constexpr int kBlock = 256;
 
+// Register budget of the stencil kernels: ask for at least this many waves per
+// SIMD so the compiler keeps the kernel under 512 / N VGPRs (memory latency is
+// hidden by occupancy; the accumulators of a 4-RHS tile still fit).
+#ifndef LAPH_STAGE_WAVES
+#define LAPH_STAGE_WAVES 1
+#endif
+#define LAPH_STAGE_OCCUPANCY __attribute__((amdgpu_waves_per_eu(LAPH_STAGE_WAVES)))
+
 struct StageArgs {
     Geom g;
     GaugePtrs gp;
@@ -35,6 +43,7 @@ struct StageArgs {
     const int *ntiles;
     int ntiles_max;
     int nsb;
+    int pstride;
     const SlotState *st;
     double *partials;
 };
@@ -93,9 +102,11 @@ __device__ __forceinline__ void spin_accumulate(cplx<R> (&acc)[12], const cplx<R
     }
 }
 
-// u = eta * L h  (ADJ: L^dagger h) for both colour vectors of the half spinor
-template <bool ADJ, class R>
-__device__ __forceinline__ void colour_mul(const cplx<R> (&L)[9], const cplx<R> (&h)[6], R eta, cplx<R> (&u)[6]) {
+// u = L h  (ADJ: L^dagger h) for both colour vectors of the half spinor, times
+// `scale` when SCALE (the FP16 site norm and/or the time-boundary sign)
+template <bool ADJ, bool SCALE, class R>
+__device__ __forceinline__ void colour_mul(const cplx<R> (&L)[9], const cplx<R> (&h)[6], R scale,
+                                           cplx<R> (&u)[6]) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
 #pragma unroll
@@ -108,61 +119,66 @@ __device__ __forceinline__ void colour_mul(const cplx<R> (&L)[9], const cplx<R> 
                 else
                     cmac(s, L[a * 3 + b], h[3 * j + b]);
             }
-            u[3 * j + a] = eta * s;
+            u[3 * j + a] = SCALE ? scale * s : s;
         }
     }
 }
 
+// One hop (forward: FWD, link U_mu(x), neighbour x + mu; backward: link
+// U_mu(x - mu)^dagger, neighbour x - mu) for the NR right-hand sides of the tile.
+// The spin projection is linear, so an FP16N neighbour is projected from its
+// codes and its norm is applied together with the boundary sign after the
+// colour product (12 multiplies instead of 24).
+template <class P, int NR, int MU, bool DAG, bool FWD>
+__device__ __forceinline__ void hop_dir(const StageArgs &A, int p, int h, const int (&x)[4],
+                                        const int (&slots)[NR], cplx<typename P::real> (&acc)[NR][12]) {
+    using R = typename P::real;
+    constexpr int S = (FWD != DAG) ? -1 : 1;     // (1 + S gamma_mu)
+    const Geom &g = A.g;
+    const int ext = MU == 0 ? g.lx : (MU == 1 ? g.ly : (MU == 2 ? g.lz : g.lt));
+    int n[4] = {x[0], x[1], x[2], x[3]};
+    bool wrap = false;
+    if (FWD) {
+        n[MU] = x[MU] + 1;
+        if (n[MU] == ext) { n[MU] = 0; wrap = true; }
+    } else {
+        n[MU] = x[MU] - 1;
+        if (n[MU] < 0) { n[MU] = ext - 1; wrap = true; }
+    }
+    const R eta = (MU == 3 && wrap && g.antiperiodic) ? R(-1) : R(1);
+    const int hn = cb_index(g, n[0], n[1], n[2], n[3]);
+    cplx<R> L[9];
+    if (FWD)
+        GaugeIO<P>::load(A.gp, p, MU, g.vh, h, L);
+    else
+        GaugeIO<P>::load(A.gp, 1 - p, MU, g.vh, hn, L);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        if (slots[r] < 0) continue;
+        cplx<R> psi[12], hs[6], u[6];
+        R nrm;
+        SpinorIO<P>::load_unscaled(A.in.at(slots[r]), g.vh, hn, psi, nrm);
+        spin_project<MU, S>(psi, hs);
+        if (SpinorIO<P>::kNorm || MU == 3)
+            colour_mul<!FWD, true>(L, hs, eta * nrm, u);
+        else
+            colour_mul<!FWD, false>(L, hs, R(1), u);
+        spin_accumulate<MU, S>(acc[r], u);
+    }
+}
+
+// Keep the instruction scheduler from hoisting the loads of all eight hops to
+// the top of the kernel: that schedule needs several hundred VGPRs (occupancy 1
+// or spills); latency is hidden across waves instead.
+__device__ __forceinline__ void hop_fence() { __builtin_amdgcn_sched_barrier(0); }
+
 template <class P, int NR, int MU, bool DAG>
 __device__ __forceinline__ void hop_mu(const StageArgs &A, int p, int h, const int (&x)[4],
                                        const int (&slots)[NR], cplx<typename P::real> (&acc)[NR][12]) {
-    using R = typename P::real;
-    const Geom &g = A.g;
-    const int ext = MU == 0 ? g.lx : (MU == 1 ? g.ly : (MU == 2 ? g.lz : g.lt));
-    // forward hop: link U_mu(x), neighbour x + mu, projector (1 - gamma) [(1 + gamma) for dagger]
-    {
-        int n[4] = {x[0], x[1], x[2], x[3]};
-        R eta = R(1);
-        n[MU] = x[MU] + 1;
-        if (n[MU] == ext) {
-            n[MU] = 0;
-            if (MU == 3 && g.antiperiodic) eta = R(-1);
-        }
-        const int hn = cb_index(g, n[0], n[1], n[2], n[3]);
-        cplx<R> L[9];
-        GaugeIO<P>::load(A.gp, p, MU, g.vh, h, L);
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            if (slots[r] < 0) continue;
-            cplx<R> psi[12], hs[6], u[6];
-            SpinorIO<P>::load(A.in.at(slots[r]), g.vh, hn, psi);
-            spin_project<MU, DAG ? 1 : -1>(psi, hs);
-            colour_mul<false>(L, hs, eta, u);
-            spin_accumulate<MU, DAG ? 1 : -1>(acc[r], u);
-        }
-    }
-    // backward hop: link U_mu(x - mu)^dagger, neighbour x - mu, projector (1 + gamma)
-    {
-        int n[4] = {x[0], x[1], x[2], x[3]};
-        R eta = R(1);
-        n[MU] = x[MU] - 1;
-        if (n[MU] < 0) {
-            n[MU] = ext - 1;
-            if (MU == 3 && g.antiperiodic) eta = R(-1);
-        }
-        const int hn = cb_index(g, n[0], n[1], n[2], n[3]);
-        cplx<R> L[9];
-        GaugeIO<P>::load(A.gp, 1 - p, MU, g.vh, hn, L);
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            if (slots[r] < 0) continue;
-            cplx<R> psi[12], hs[6], u[6];
-            SpinorIO<P>::load(A.in.at(slots[r]), g.vh, hn, psi);
-            spin_project<MU, DAG ? -1 : 1>(psi, hs);
-            colour_mul<true>(L, hs, eta, u);
-            spin_accumulate<MU, DAG ? -1 : 1>(acc[r], u);
-        }
-    }
+    hop_dir<P, NR, MU, DAG, true>(A, p, h, x, slots, acc);
+    hop_fence();
+    hop_dir<P, NR, MU, DAG, false>(A, p, h, x, slots, acc);
+    hop_fence();
 }
 
 // FP64 block reduction of NV values per thread; thread 0 writes NV partials.
@@ -193,7 +209,7 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NV], double *dst,
 }
 
 template <class P, int NR, bool DAG, bool CLOVER, bool PRE, int POST, int RED, bool FLAGGED>
-__global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs A) {
+__global__ __launch_bounds__(kBlock) LAPH_STAGE_OCCUPANCY void stage_kernel(StageArgs A) {
     using R = typename P::real;
     const int L = xcd_logical_block();
     const int sb = L / A.ntiles_max;
@@ -313,7 +329,7 @@ __global__ __launch_bounds__(kBlock) void stage_kernel(StageArgs A) {
             for (int q = 0; q < NQ; ++q) v[q] = part[r][q];
             // every thread of the block takes part in the reduction (uniform branch)
             if (slots[r] >= 0) {
-                block_reduce_store<NQ>(v, A.partials + ((size_t)slots[r] * 3) * A.nsb + sb, (size_t)A.nsb);
+                block_reduce_store<NQ>(v, A.partials + ((size_t)slots[r] * 3) * A.pstride + sb, (size_t)A.pstride);
                 __syncthreads();
             }
         }

@@ -1,0 +1,251 @@
+// Even-odd stencil stage, RHS-parallel form with the links staged in LDS.
+//
+// A workgroup owns 64 output sites and a tile of 4*RW right-hand sides of one
+// mass.  Phase 1: its four waves compute the 8 neighbour indices of the 64
+// sites and load, decompress (third row) and store the 8 links per site in
+// LDS, already transposed for the backward hops and multiplied by the
+// time-boundary sign.  Phase 2: each wave takes one RHS at a time (RW rounds);
+// a lane owns one site, so its accumulator is a single 12-component spinor,
+// the neighbour spinor loads of a wave are coalesced (consecutive sites), and
+// every link staged in LDS is reused by all 4*RW RHS of the tile.  Compared
+// with the register-tile form this keeps the VGPR count low (high occupancy
+// hides the neighbour-gather latency) while still reading each link once per
+// tile.  Inner products are reduced per wave (one partial per 64 sites).
+#pragma once
+
+#include "dslash_kernels.h"
+
+namespace laph {
+
+constexpr int kLdsSites = 64;
+
+// One hop for one RHS: neighbour index and link (already L or L^dagger, times the
+// boundary sign) come from LDS; an FP16N neighbour is projected from its codes
+// and scaled by its norm after the colour product.
+template <class P, int MU, bool DAG, bool FWD>
+__device__ __forceinline__ void lds_hop(const char *src, int vh, const typename P::real (&lnk)[8][18][kLdsSites],
+                                        const int (&nbr)[8][kLdsSites], int lane,
+                                        cplx<typename P::real> (&acc)[12]) {
+    using R = typename P::real;
+    constexpr int hop = 2 * MU + (FWD ? 0 : 1);
+    constexpr int S = (FWD != DAG) ? -1 : 1;
+    const int hn = nbr[hop][lane];
+    cplx<R> psi[12], hs[6], u[6], L[9];
+    R nrm;
+    SpinorIO<P>::load_unscaled(src, vh, hn, psi, nrm);
+    spin_project<MU, S>(psi, hs);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) L[k] = {lnk[hop][2 * k][lane], lnk[hop][2 * k + 1][lane]};
+    colour_mul<false, SpinorIO<P>::kNorm>(L, hs, nrm, u);
+    spin_accumulate<MU, S>(acc, u);
+}
+
+template <class P, int RW, bool DAG, bool CLOVER, bool PRE, int POST, int RED>
+__global__ __launch_bounds__(256) void stage_lds_kernel(StageArgs A) {
+    using R = typename P::real;
+    constexpr int NT = 4 * RW;
+    __shared__ R lnk[8][18][kLdsSites];
+    __shared__ int nbr[8][kLdsSites];
+    const int Lb = xcd_logical_block();
+    const int sb = Lb / A.ntiles_max;
+    const int tile = Lb - sb * A.ntiles_max;
+    if (sb >= A.nsb || tile >= *A.ntiles) return;
+    const Geom &g = A.g;
+    const int p = A.out_parity;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int h = sb * kLdsSites + lane;
+    const bool valid = h < g.vh;
+    // ---- phase 1: neighbours and links of the 64 sites (wave w: hops 2w, 2w+1 = mu w fwd / bwd)
+    {
+        int x = 0, y = 0, z = 0, t = 0;
+        if (valid) site_coords(g, p, h, x, y, z, t);
+        const int mu = wave;   // wave-uniform; no dynamic indexing of local arrays
+#pragma unroll
+        for (int fb = 0; fb < 2; ++fb) {
+            const int hop = 2 * mu + fb;
+            const int d = fb == 0 ? 1 : -1;
+            int nx = x, ny = y, nz = z, nt = t;
+            bool wrap = false;
+            if (mu == 0) {
+                nx = x + d;
+                if (nx == g.lx) { nx = 0; wrap = true; }
+                if (nx < 0) { nx = g.lx - 1; wrap = true; }
+            } else if (mu == 1) {
+                ny = y + d;
+                if (ny == g.ly) { ny = 0; wrap = true; }
+                if (ny < 0) { ny = g.ly - 1; wrap = true; }
+            } else if (mu == 2) {
+                nz = z + d;
+                if (nz == g.lz) { nz = 0; wrap = true; }
+                if (nz < 0) { nz = g.lz - 1; wrap = true; }
+            } else {
+                nt = t + d;
+                if (nt == g.lt) { nt = 0; wrap = true; }
+                if (nt < 0) { nt = g.lt - 1; wrap = true; }
+            }
+            const R eta = (mu == 3 && wrap && g.antiperiodic) ? R(-1) : R(1);
+            const int hn = valid ? cb_index(g, nx, ny, nz, nt) : 0;
+            cplx<R> L[9];
+            if (valid) {
+                GaugeIO<P>::load(A.gp, fb == 0 ? p : 1 - p, mu, g.vh, fb == 0 ? h : hn, L);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) L[k] = {R(0), R(0)};
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    // forward: L[a][b]; backward: (L^dagger)[a][b] = conj(L[b][a])
+                    const cplx<R> e = fb == 0 ? L[a * 3 + b] : conj(L[b * 3 + a]);
+                    lnk[hop][2 * (a * 3 + b)][lane] = eta * e.re;
+                    lnk[hop][2 * (a * 3 + b) + 1][lane] = eta * e.im;
+                }
+            nbr[hop][lane] = hn;
+        }
+    }
+    __syncthreads();
+    // ---- phase 2: one RHS per wave per round
+    constexpr int NQ = RED == 1 ? 2 : (RED == 2 ? 3 : (RED == 3 ? 1 : 0));
+#pragma unroll 1
+    for (int rw = 0; rw < RW; ++rw) {
+        const int slot = A.tile_slots[tile * NT + rw * 4 + wave];
+        if (slot < 0) continue;   // wave-uniform
+        double part[NQ > 0 ? NQ : 1];
+#pragma unroll
+        for (int q = 0; q < (NQ > 0 ? NQ : 1); ++q) part[q] = 0.0;
+        if (valid) {
+            cplx<R> acc[12];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) acc[c] = {R(0), R(0)};
+            const char *src = A.in.at(slot);
+            lds_hop<P, 0, DAG, true>(src, g.vh, lnk, nbr, lane, acc);
+            hop_fence();
+            lds_hop<P, 0, DAG, false>(src, g.vh, lnk, nbr, lane, acc);
+            hop_fence();
+            lds_hop<P, 1, DAG, true>(src, g.vh, lnk, nbr, lane, acc);
+            hop_fence();
+            lds_hop<P, 1, DAG, false>(src, g.vh, lnk, nbr, lane, acc);
+            hop_fence();
+            lds_hop<P, 2, DAG, true>(src, g.vh, lnk, nbr, lane, acc);
+            hop_fence();
+            lds_hop<P, 2, DAG, false>(src, g.vh, lnk, nbr, lane, acc);
+            hop_fence();
+            lds_hop<P, 3, DAG, true>(src, g.vh, lnk, nbr, lane, acc);
+            hop_fence();
+            lds_hop<P, 3, DAG, false>(src, g.vh, lnk, nbr, lane, acc);
+            hop_fence();
+            if (PRE) {
+                cplx<R> zz[12];
+                SpinorIO<P>::load(A.z.at(slot), g.vh, h, zz);
+                const R cz = R(A.c);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) acc[c] = acc[c] + cz * zz[c];
+            }
+            if (CLOVER) {
+                const char *cl = A.clover + (size_t)A.tile_mass[tile] * A.clover_mass_stride;
+#pragma unroll
+                for (int blk = 0; blk < 2; ++blk) {
+                    R m[36];
+                    CloverIO<P>::load(cl, blk, g.vh, h, m);
+                    cplx<R> o[6];
+                    herm6_apply(m, &acc[6 * blk], o);
+#pragma unroll
+                    for (int i = 0; i < 6; ++i) acc[6 * blk + i] = o[i];
+                    hop_fence();
+                }
+            }
+            cplx<R> res[12], yy[12];
+            const R bb = R(A.b);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) res[c] = bb * acc[c];
+            if (POST >= 1) {
+                SpinorIO<P>::load(A.y.at(slot), g.vh, h, yy);
+                const R aa = R(A.a);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) res[c] = res[c] + aa * yy[c];
+            }
+            if (POST >= 2) {
+                cplx<R> y2[12];
+                SpinorIO<P>::load(A.y2.at(slot), g.vh, h, y2);
+                const R aa2 = R(A.a2);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) res[c] = res[c] + aa2 * y2[c];
+            }
+            SpinorIO<P>::store(A.out.at(slot), g.vh, h, res);
+            hop_fence();
+            if (RED == 1) {
+                cplx<R> ww[12];
+                SpinorIO<P>::load(A.w.at(slot), g.vh, h, ww);
+                cplx<R> d = {R(0), R(0)};
+#pragma unroll
+                for (int c = 0; c < 12; ++c) cmac_conj(d, ww[c], res[c]);
+                part[0] = d.re;
+                part[1] = d.im;
+            } else if (RED == 2) {
+                cplx<R> d = {R(0), R(0)};
+                R n2 = R(0);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) {
+                    cmac_conj(d, res[c], yy[c]);
+                    n2 += res[c].re * res[c].re + res[c].im * res[c].im;
+                }
+                part[0] = d.re;
+                part[1] = d.im;
+                part[2] = n2;
+            } else if (RED == 3) {
+                R n2 = R(0);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) n2 += res[c].re * res[c].re + res[c].im * res[c].im;
+                part[0] = n2;
+            }
+        }
+        if constexpr (NQ > 0) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                double s = part[q];
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+                if (lane == 0) A.partials[((size_t)slot * 3 + q) * A.pstride + sb] = s;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// dispatch (FP32 / FP16N; instantiated in dslash_f32.hip and dslash_f16.hip)
+// ---------------------------------------------------------------------------
+template <class P, int RW, bool DAG, bool CLOVER, bool PRE, int POST, int RED>
+inline void launch_lds_t(const StageArgs &a, hipStream_t st) {
+    const int nblk = pad8(a.nsb * a.ntiles_max);
+    hipLaunchKernelGGL((stage_lds_kernel<P, RW, DAG, CLOVER, PRE, POST, RED>), dim3(nblk), dim3(256), 0, st, a);
+}
+
+template <class P, int RW, bool DAG>
+inline bool launch_lds_combo(const StageSpec &s, const StageArgs &a, hipStream_t st) {
+    if (s.flagged) return false;
+    const int key = s.clover * 1000 + s.pre * 100 + s.post * 10 + s.red;
+    switch (key) {
+        case 0: launch_lds_t<P, RW, DAG, false, false, 0, 0>(a, st); return true;       // bare hop
+        case 1000: launch_lds_t<P, RW, DAG, true, false, 0, 0>(a, st); return true;    // A^-1 H in
+        case 1011: launch_lds_t<P, RW, DAG, true, false, 1, 1>(a, st); return true;    // v = p - A^-1 H t, <r^, v>
+        case 1012: launch_lds_t<P, RW, DAG, true, false, 1, 2>(a, st); return true;    // t = s - A^-1 H t, <t,s>,|t|^2
+        default: return false;
+    }
+}
+
+template <class P>
+inline bool launch_lds_p(const StageSpec &s, const StageArgs &a, hipStream_t st) {
+    const bool d = s.dagger != 0;
+    switch (s.tiles.nr) {
+        case 4: return d ? launch_lds_combo<P, 1, true>(s, a, st) : launch_lds_combo<P, 1, false>(s, a, st);
+        case 8: return d ? launch_lds_combo<P, 2, true>(s, a, st) : launch_lds_combo<P, 2, false>(s, a, st);
+        case 16: return d ? launch_lds_combo<P, 4, true>(s, a, st) : launch_lds_combo<P, 4, false>(s, a, st);
+        default: return false;
+    }
+}
+
+bool launch_stage_lds_f32(const StageSpec &s, const StageArgs &a, hipStream_t st);
+bool launch_stage_lds_f16(const StageSpec &s, const StageArgs &a, hipStream_t st);
+
+}  // namespace laph

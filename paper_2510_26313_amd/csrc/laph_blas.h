@@ -10,12 +10,13 @@ enum { kFinAlpha, kFinOmega, kFinRho, kFinUpdate, kFinRho2, kFinInit, kFinBnorm,
 
 struct BlasArgs {
     int vh = 0;
-    int nsb = 0;                 // site blocks (partials per quantity per slot)
+    int nsb = 0;                 // site blocks of 256 (partials written per quantity per slot)
+    int pstride = 0;             // partial-sum stride per quantity per slot
     const int *list = nullptr;   // slot list
     const int *nlist = nullptr;  // device scalar: entries in use
     int nlist_max = 0;           // grid size
     SlotState *st = nullptr;
-    double *partials = nullptr;  // [slot][3][nsb]
+    double *partials = nullptr;  // [slot][3][pstride]
     Operand r, rh, p, v, t, x;   // inner-precision vectors (x: the x_lo precision)
     Operand x64, r64;            // FP64 solution and residual
 };
@@ -24,7 +25,8 @@ struct FinArgs {
     const int *list = nullptr;
     const int *nlist = nullptr;
     int nlist_max = 0;
-    int nsb = 0;
+    int nsb = 0;        // partials to sum (the producing kernel's site blocks)
+    int pstride = 0;    // partial-sum stride per quantity per slot
     SlotState *st = nullptr;
     const double *partials = nullptr;
     int max_restarts = 10;

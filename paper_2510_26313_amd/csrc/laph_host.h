@@ -29,6 +29,10 @@ struct SlotState {
     int iters, updates, restarts, maxiter;
 };
 
+// Two forms of the stencil stage kernel: RHS tiles held in registers by one
+// thread, or RHS-parallel waves sharing links staged in LDS.
+enum { kFormRegister = 0, kFormLds = 1 };
+
 // Tile table shared by the stencil kernels: tile j holds up to nr slots of one mass.
 struct Tiles {
     const int *slots = nullptr;   // [ntiles_max][nr], -1 = empty
@@ -114,10 +118,16 @@ struct StageSpec {
     Operand in, out, y, y2, z, w;
     double a = 0, a2 = 0, b = 1, c = 0;
     Tiles tiles;
+    int form = kFormRegister;           // kFormRegister: tiles.nr RHS per thread;
+                                        // kFormLds: tiles.nr = 4 * RW RHS per workgroup, links in LDS
     const SlotState *slots = nullptr;   // may be null when flagged == 0
-    double *partials = nullptr;         // [slot][3][nsb]
+    double *partials = nullptr;         // [slot][3][pstride]
+    int pstride = 0;                    // partials per quantity per slot (>= stage_nsb)
 };
-int stage_nsb(const Ctx &c);
+// site blocks of a stage launch (= partial sums it writes per quantity and slot)
+int stage_nsb(const Ctx &c, int form);
+// a partial-sum stride large enough for every kernel of the library
+int partial_stride(const Ctx &c);
 laph_status launch_stage(const Ctx &c, const StageSpec &s);
 
 // out = a*y + b * M in with M = A (inverse = 0) or A^-1 of the given parity,

@@ -124,8 +124,17 @@ inline size_t hv_bytes(int prec, size_t vh) {
 template <class P>
 struct SpinorIO;
 
+// load_unscaled: the stored values before the per-site norm (FP16N codes as FP32)
+// and that norm (1 for FP64 / FP32), so a linear consumer can apply the norm once
+// to a smaller result.
 template <>
 struct SpinorIO<F64> {
+    static constexpr bool kNorm = false;
+    static __device__ __forceinline__ void load_unscaled(const char *hv, int vh, int h, cplx<double> (&s)[12],
+                                                         double &n) {
+        load(hv, vh, h, s);
+        n = 1.0;
+    }
     static __device__ __forceinline__ void load(const char *hv, int vh, int h, cplx<double> (&s)[12]) {
         const double2 *p = reinterpret_cast<const double2 *>(hv);
 #pragma unroll
@@ -143,6 +152,12 @@ struct SpinorIO<F64> {
 
 template <>
 struct SpinorIO<F32> {
+    static constexpr bool kNorm = false;
+    static __device__ __forceinline__ void load_unscaled(const char *hv, int vh, int h, cplx<float> (&s)[12],
+                                                         float &n) {
+        load(hv, vh, h, s);
+        n = 1.f;
+    }
     static __device__ __forceinline__ void load(const char *hv, int vh, int h, cplx<float> (&s)[12]) {
         const float4 *p = reinterpret_cast<const float4 *>(hv);
 #pragma unroll
@@ -162,6 +177,18 @@ struct SpinorIO<F32> {
 
 template <>
 struct SpinorIO<F16N> {
+    static constexpr bool kNorm = true;
+    static __device__ __forceinline__ void load_unscaled(const char *hv, int vh, int h, cplx<float> (&s)[12],
+                                                         float &n) {
+        const half8 *p = reinterpret_cast<const half8 *>(hv);
+        n = reinterpret_cast<const float *>(hv + (size_t)48 * vh)[h];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            half8 v = p[(size_t)j * vh + h];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s[4 * j + k] = {(float)v[2 * k], (float)v[2 * k + 1]};
+        }
+    }
     static __device__ __forceinline__ void load(const char *hv, int vh, int h, cplx<float> (&s)[12]) {
         const half8 *p = reinterpret_cast<const half8 *>(hv);
         const float n = reinterpret_cast<const float *>(hv + (size_t)48 * vh)[h];

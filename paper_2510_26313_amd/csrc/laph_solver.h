@@ -50,11 +50,15 @@ class Solver {
         Operand r, rh, p, v, t, tmp, x;    // inner precision; x in the x_lo precision
         SlotState *st = nullptr;
         double *partials = nullptr;
-        int *tile_slots = nullptr, *tile_mass = nullptr, *list = nullptr, *slot_mass = nullptr;
-        int *ntiles = nullptr, *nlist = nullptr;
+        int *tile_slots = nullptr, *tile_mass = nullptr;      // inner-form tiles
+        int *tile64_slots = nullptr, *tile64_mass = nullptr;  // FP64 register tiles
+        int *list = nullptr, *slot_mass = nullptr;
+        int *ntiles = nullptr, *nlist = nullptr, *ntiles64 = nullptr;
+        size_t nints = 0;
     };
 
-    static size_t layout(const Ctx &c, int ns, int nr, int prec, char *base, WS *ws);
+    static void choose_shape(const laph_solve_params &p, int ns, int &form, int &nr, int &nr64);
+    static size_t layout(const Ctx &c, int ns, int nr, int nr64, int prec, char *base, WS *ws);
     laph_status init(const Ctx &ctx, int nslots, const laph_solve_params &params, char *work, size_t bytes);
     ~Solver();
 
@@ -67,7 +71,7 @@ class Solver {
    private:
     const Ctx *c = nullptr;
     laph_solve_params p{};
-    int ns = 0, prec = 0, nr = 1, nsb = 0;
+    int ns = 0, prec = 0, form = kFormRegister, nr = 1, nr64 = 1, nsb256 = 0, nsb_inner = 0, pstride = 0;
     WS ws;
     std::vector<int> mass;
     std::vector<int> host_ints;
@@ -76,8 +80,8 @@ class Solver {
     int graph_k = 0;
 
     BlasArgs blas(int list_max) const;
-    FinArgs fin(int list_max) const;
-    Tiles tiles() const;
+    FinArgs fin(int list_max, int nsb = 0) const;
+    Tiles tiles(bool f64) const;
     laph_status upload_tables(const std::vector<int> &slots);
     laph_status download_state();
     laph_status upload_state();

@@ -22,16 +22,27 @@
 
 namespace laph {
 
-static int default_nr(int prec, int ns) {
-    (void)prec;
-    if (ns >= 4) return 4;
-    if (ns >= 2) return 2;
-    return 1;
+// RHS per register tile: 4, 2 or 1
+static int reg_tile(int ns) { return ns >= 4 ? 4 : (ns >= 2 ? 2 : 1); }
+
+// Stencil form and tile size of the inner iterations: FP64 keeps the register
+// tiles (its LDS link stage would need twice the LDS); FP32 / FP16N use the
+// LDS-staged links with up to 16 RHS sharing each link load.
+void Solver::choose_shape(const laph_solve_params &p, int ns, int &form, int &nr, int &nr64) {
+    const int prec = p.inner_prec;
+    form = prec == LAPH_F64 ? kFormRegister : kFormLds;
+    if (p.stencil == 1) form = kFormRegister;
+    if (p.stencil == 2 && prec != LAPH_F64) form = kFormLds;
+    if (form == kFormLds)
+        nr = p.rhs_tile > 0 ? p.rhs_tile : (ns >= 16 ? 16 : (ns >= 8 ? 8 : 4));
+    else
+        nr = p.rhs_tile > 0 ? p.rhs_tile : reg_tile(ns);
+    nr64 = prec == LAPH_F64 ? nr : reg_tile(ns);
 }
 
-size_t Solver::layout(const Ctx &c, int ns, int nr, int prec, char *base, WS *ws) {
+size_t Solver::layout(const Ctx &c, int ns, int nr, int nr64, int prec, char *base, WS *ws) {
     const size_t h64 = c.hv(LAPH_F64), hlo = c.hv(prec), hx = c.hv(prec == LAPH_F64 ? LAPH_F64 : LAPH_F32);
-    const int nsb = stage_nsb(c);
+    const int pstride = partial_stride(c);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -58,26 +69,32 @@ size_t Solver::layout(const Ctx &c, int ns, int nr, int prec, char *base, WS *ws
     w.tmp = op(take(ns * hlo), hlo);
     w.x = op(take(ns * hx), hx);
     size_t o_st = take(ns * sizeof(SlotState));
-    size_t o_part = take((size_t)ns * 3 * nsb * sizeof(double));
-    size_t o_ints = take(((size_t)ns * nr + 3 * (size_t)ns + 8) * sizeof(int));
+    size_t o_part = take((size_t)ns * 3 * pstride * sizeof(double));
+    const size_t nints = (size_t)ns * nr + (size_t)ns * nr64 + 4 * (size_t)ns + 8;
+    size_t o_ints = take(nints * sizeof(int));
     if (ws && base) {
         w.st = reinterpret_cast<SlotState *>(base + o_st);
         w.partials = reinterpret_cast<double *>(base + o_part);
         int *ints = reinterpret_cast<int *>(base + o_ints);
         w.tile_slots = ints;
-        w.tile_mass = ints + (size_t)ns * nr;
-        w.list = w.tile_mass + ns;
+        w.tile_mass = w.tile_slots + (size_t)ns * nr;
+        w.tile64_slots = w.tile_mass + ns;
+        w.tile64_mass = w.tile64_slots + (size_t)ns * nr64;
+        w.list = w.tile64_mass + ns;
         w.slot_mass = w.list + ns;
         w.ntiles = w.slot_mass + ns;
         w.nlist = w.ntiles + 1;
+        w.ntiles64 = w.ntiles + 2;
+        w.nints = nints;
         *ws = w;
     }
     return off;
 }
 
 size_t solver_workspace_bytes(const Ctx &c, int nslots, const laph_solve_params &p) {
-    const int nr = p.rhs_tile > 0 ? p.rhs_tile : default_nr(p.inner_prec, nslots);
-    return Solver::layout(c, nslots, nr, p.inner_prec, nullptr, nullptr);
+    int form, nr, nr64;
+    Solver::choose_shape(p, nslots, form, nr, nr64);
+    return Solver::layout(c, nslots, nr, nr64, p.inner_prec, nullptr, nullptr);
 }
 
 laph_status Solver::init(const Ctx &ctx, int nslots, const laph_solve_params &params, char *work, size_t bytes) {
@@ -85,14 +102,19 @@ laph_status Solver::init(const Ctx &ctx, int nslots, const laph_solve_params &pa
     p = params;
     ns = nslots;
     prec = p.inner_prec;
-    nr = p.rhs_tile > 0 ? p.rhs_tile : default_nr(prec, ns);
-    if (nr != 1 && nr != 2 && nr != 4) return set_error(LAPH_ERR_INVALID, "rhs_tile must be 1, 2 or 4");
-    const size_t need = layout(ctx, ns, nr, prec, nullptr, nullptr);
+    choose_shape(p, ns, form, nr, nr64);
+    if (form == kFormRegister && nr != 1 && nr != 2 && nr != 4)
+        return set_error(LAPH_ERR_INVALID, "rhs_tile must be 1, 2 or 4 for register tiles");
+    if (form == kFormLds && nr != 4 && nr != 8 && nr != 16)
+        return set_error(LAPH_ERR_INVALID, "rhs_tile must be 4, 8 or 16 for LDS-staged links");
+    const size_t need = layout(ctx, ns, nr, nr64, prec, nullptr, nullptr);
     if (!work || bytes < need)
         return set_error(LAPH_ERR_WORKSPACE, "solver workspace too small: %zu < %zu bytes", bytes, need);
-    layout(ctx, ns, nr, prec, work, &ws);
-    nsb = stage_nsb(ctx);
-    host_ints.assign((size_t)ns * nr + 3 * (size_t)ns + 8, 0);
+    layout(ctx, ns, nr, nr64, prec, work, &ws);
+    nsb256 = stage_nsb(ctx, kFormRegister);
+    nsb_inner = stage_nsb(ctx, form);
+    pstride = partial_stride(ctx);
+    host_ints.assign(ws.nints, 0);
     host_st.assign(ns, SlotState{});
     return LAPH_OK;
 }
@@ -104,7 +126,8 @@ Solver::~Solver() {
 BlasArgs Solver::blas(int list_max) const {
     BlasArgs a;
     a.vh = c->g.vh;
-    a.nsb = nsb;
+    a.nsb = nsb256;
+    a.pstride = pstride;
     a.list = ws.list;
     a.nlist = ws.nlist;
     a.nlist_max = list_max;
@@ -121,48 +144,56 @@ BlasArgs Solver::blas(int list_max) const {
     return a;
 }
 
-FinArgs Solver::fin(int list_max) const {
+FinArgs Solver::fin(int list_max, int nsb) const {
     FinArgs f;
     f.list = ws.list;
     f.nlist = ws.nlist;
     f.nlist_max = list_max;
-    f.nsb = nsb;
+    f.nsb = nsb > 0 ? nsb : nsb256;
+    f.pstride = pstride;
     f.st = ws.st;
     f.partials = ws.partials;
     return f;
 }
 
-Tiles Solver::tiles() const {
+Tiles Solver::tiles(bool f64) const {
     Tiles t;
-    t.slots = ws.tile_slots;
-    t.mass = ws.tile_mass;
-    t.ntiles = ws.ntiles;
+    t.slots = f64 ? ws.tile64_slots : ws.tile_slots;
+    t.mass = f64 ? ws.tile64_mass : ws.tile_mass;
+    t.ntiles = f64 ? ws.ntiles64 : ws.ntiles;
     t.ntiles_max = ns;
-    t.nr = nr;
+    t.nr = f64 ? nr64 : nr;
     return t;
 }
 
-// Upload the slot list and the tile table for the given slots (grouped by mass).
+// Upload the slot list and the tile tables (inner form and FP64) for the given slots,
+// grouped by mass so that every tile shares one clover inverse.
 laph_status Solver::upload_tables(const std::vector<int> &slots) {
     std::vector<int> sorted = slots;
     std::stable_sort(sorted.begin(), sorted.end(), [&](int a, int b) { return mass[a] < mass[b]; });
     int *ts = host_ints.data();
     int *tm = ts + (size_t)ns * nr;
-    int *ls = tm + ns;
+    int *ts64 = tm + ns;
+    int *tm64 = ts64 + (size_t)ns * nr64;
+    int *ls = tm64 + ns;
     int *sm = ls + ns;
     int *cnt = sm + ns;
-    std::fill(ts, ts + (size_t)ns * nr, -1);
-    int nt = 0;
-    for (size_t i = 0; i < sorted.size();) {
-        const int m = mass[sorted[i]];
-        int k = 0;
-        while (k < nr && i < sorted.size() && mass[sorted[i]] == m) ts[(size_t)nt * nr + k++] = sorted[i++];
-        tm[nt++] = m;
-    }
-    for (int i = nt; i < ns; ++i) tm[i] = 0;
+    auto build = [&](int *tsl, int *tms, int tile) {
+        std::fill(tsl, tsl + (size_t)ns * tile, -1);
+        std::fill(tms, tms + ns, 0);
+        int nt = 0;
+        for (size_t i = 0; i < sorted.size();) {
+            const int m = mass[sorted[i]];
+            int k = 0;
+            while (k < tile && i < sorted.size() && mass[sorted[i]] == m) tsl[(size_t)nt * tile + k++] = sorted[i++];
+            tms[nt++] = m;
+        }
+        return nt;
+    };
+    cnt[0] = build(ts, tm, nr);
+    cnt[2] = build(ts64, tm64, nr64);
     for (size_t i = 0; i < slots.size(); ++i) ls[i] = slots[i];
     for (int s = 0; s < ns; ++s) sm[s] = s < (int)mass.size() ? mass[s] : 0;
-    cnt[0] = nt;
     cnt[1] = (int)slots.size();
     LAPH_HIP(hipMemcpyAsync(ws.tile_slots, host_ints.data(), host_ints.size() * sizeof(int), hipMemcpyHostToDevice,
                             c->stream));
@@ -206,9 +237,12 @@ laph_status Solver::stage(int sprec, int out_parity, Operand in, Operand out, in
     s.a2 = a2;
     s.b = b;
     s.c = cz;
-    s.tiles = tiles();
+    const bool f64 = sprec == LAPH_F64;
+    s.tiles = tiles(f64);
+    s.form = f64 ? kFormRegister : form;
     s.slots = ws.st;
     s.partials = ws.partials;
+    s.pstride = pstride;
     return launch_stage(*c, s);
 }
 
@@ -239,13 +273,13 @@ laph_status Solver::iteration() {
     // v = M_hat p,  <r^, v>
     LAPH_TRY(stage(prec, 1, ws.p, ws.tmp, 1, 0, none, 0, 0, none, 0, none, 0, 1.0, 0, none, 0));
     LAPH_TRY(stage(prec, 0, ws.tmp, ws.v, 1, 0, none, 0, 1, ws.p, 1.0, none, 0, -0.25, 1, ws.rh, 0));
-    LAPH_TRY(blas_finalize(*c, f, kFinAlpha));
+    LAPH_TRY(blas_finalize(*c, fin(ns, nsb_inner), kFinAlpha));
     // s = r - alpha v (in r)
     LAPH_TRY(blas_s_update(*c, a, prec));
     // t = M_hat s,  <t, s>, |t|^2
     LAPH_TRY(stage(prec, 1, ws.r, ws.tmp, 1, 0, none, 0, 0, none, 0, none, 0, 1.0, 0, none, 0));
     LAPH_TRY(stage(prec, 0, ws.tmp, ws.t, 1, 0, none, 0, 1, ws.r, 1.0, none, 0, -0.25, 2, none, 0));
-    LAPH_TRY(blas_finalize(*c, f, kFinOmega));
+    LAPH_TRY(blas_finalize(*c, fin(ns, nsb_inner), kFinOmega));
     // x_lo += alpha p + omega s;  r = s - omega t;  rho, |r|^2, update decision
     LAPH_TRY(blas_xr_update(*c, a, prec));
     LAPH_TRY(blas_finalize(*c, f, kFinRho));

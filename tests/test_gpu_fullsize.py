@@ -1,0 +1,129 @@
+"""Parity at the benchmark sizes, in the configuration bench.py times.
+
+The oracle cannot solve 32^3 x 64 (or 24^3 x 48) in test time, so these checks
+use outputs it computes one by one and properties that hold at any size:
+
+* C4 (32^3 x 64, nev 64, m0 0.02): the fused perambulator for t0 = 0 and t0 = 16
+  (FP16N inner, LDS stencil, chunks of 128 -- the bench configuration); sampled
+  solutions are checked against the oracle's D at sampled sites (pointwise
+  residual), the oracle's projection of those solutions reproduces the sampled
+  tau entries, and tau obeys gamma5 reciprocity between the two source times;
+* C2 (24^3 x 48, four masses split 40/72/64/80 in one batched solve): per-RHS
+  FP64 residual reported by the library and the oracle's D at sampled sites;
+* C1 (16^3 x 32, single-RHS solver, FP32 and FP16N inner): sampled RHS against
+  full oracle solves (1e-8).
+"""
+import numpy as np
+import pytest
+import torch
+
+import laph_synth as ls
+from gpu_common import dev, host, log_case, make_lattice, per_rhs_rel, require_gpu
+from oracle import dirac, laph, solvers
+
+pytestmark = pytest.mark.gpu
+
+
+def _sample_sites(dims, n, seed, t_fixed=None):
+    lx, ly, lz, lt = dims
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        t = int(rng.integers(0, lt)) if t_fixed is None else t_fixed
+        out.append((t, int(rng.integers(0, lz)), int(rng.integers(0, ly)), int(rng.integers(0, lx))))
+    return out
+
+
+def _pointwise_residual(U, X, B, sites, m0, csw):
+    DX = dirac.apply_at_sites(U, X, sites, m0, csw)
+    b = np.stack([B[:, t, z, y, x] for (t, z, y, x) in sites], axis=1)
+    return np.abs(b - DX).max(axis=(1, 2, 3)), np.linalg.norm(B.reshape(B.shape[0], -1), axis=1)
+
+
+@pytest.fixture(scope="module")
+def c4():
+    require_gpu()
+    cfg = ls.CONFIGS["c4"]
+    dims = cfg["dims"]
+    log_case("c4 inputs", dims=dims)
+    U = ls.gauge_field(dims, cfg["seed_u"])
+    V = ls.orthonormal_laph_vectors(dims, cfg["nev"], cfg["seed_v"])
+    lat = make_lattice(dims, U, masses=cfg["masses"], csw=cfg["csw"])
+    return dict(cfg=cfg, U=U, V=V, lat=lat, Vd=dev(V))
+
+
+def test_c4_perambulator_sampled_and_reciprocal(c4):
+    import paper_2510_26313_amd as pl
+    cfg, U, V, lat, Vd = c4["cfg"], c4["U"], c4["V"], c4["lat"], c4["Vd"]
+    m0, csw = cfg["masses"][0], cfg["csw"]
+    p = pl.default_params(inner_prec="f16n", chunk=128, rhs_tile=16, stencil=2)
+    log_case("c4 perambulator", t0=0)
+    tauA, stA = lat.perambulator_raw(Vd, 0, 0, 1e-10, p)
+    log_case("c4 perambulator", t0=16)
+    tauB, stB = lat.perambulator_raw(Vd, 16, 0, 1e-10, p)
+    assert all(s["status"] == "converged" and s["true_res"] <= 1e-10 for s in stA + stB)
+    tauA, tauB = host(tauA), host(tauB)
+    # gamma5 reciprocity between source times 0 and 16
+    g5 = np.array([1, 1, -1, -1])
+    exp = np.einsum("b,a,klab->lkba", g5, g5, np.conj(tauB[0]))
+    assert np.linalg.norm(tauA[16] - exp) <= 1e-8 * np.linalg.norm(exp)
+    # sampled solutions: oracle residual at sampled sites, oracle projection of the sampled sinks
+    rhs = [5, 130, 255]
+    B = laph.laph_sources(V, 0)[rhs]
+    log_case("c4 sampled solves", rhs=rhs)
+    X, st = lat.solve_raw(dev(B), 0, 1e-10, pl.default_params(inner_prec="f16n", rhs_tile=4, stencil=2))
+    X = host(X)
+    sites = _sample_sites(cfg["dims"], 24, 7) + _sample_sites(cfg["dims"], 8, 8, t_fixed=0)
+    res, bn = _pointwise_residual(U, X, B, sites, m0, csw)
+    assert np.all(res <= 1e-10 * bn)
+    for i, r in enumerate(rhs):
+        k, al = divmod(r, 4)
+        for t in (0, 1, 33, 63):
+            # tau[t][l][k][beta][alpha] for this RHS from the oracle's projection of X
+            exp_t = np.einsum("lzyxa,zyxba->lb", np.conj(V[t]), X[i, t])
+            got = tauA[t, :, k, :, al]
+            assert np.linalg.norm(got - exp_t) <= 1e-8 * np.linalg.norm(tauA[t]) + 1e-14
+
+
+def test_c2_multimass_batched_sampled():
+    import paper_2510_26313_amd as pl
+    require_gpu()
+    cfg = ls.CONFIGS["c2"]
+    dims = cfg["dims"]
+    log_case("c2 inputs", dims=dims)
+    U = ls.gauge_field(dims, cfg["seed_u"])
+    V = ls.orthonormal_laph_vectors(dims, cfg["nev"], cfg["seed_v"])
+    lat = make_lattice(dims, U, masses=cfg["masses"], csw=cfg["csw"])
+    mi = ls.rhs_masses(cfg)
+    Vd = dev(V)
+    B = lat.make_sources(Vd, 0)
+    log_case("c2 batched solve", nrhs=len(mi))
+    X, st = lat.solve_raw(B, mi, 1e-10, pl.default_params(inner_prec="f16n", rhs_tile=16, stencil=2))
+    assert all(s["status"] == "converged" and s["true_res"] <= 1e-10 for s in st)
+    iters = {m: [s["iters"] for s, mm in zip(st, mi) if mm == m] for m in range(4)}
+    print("c2 iterations per mass", {cfg["masses"][m]: (min(v), max(v)) for m, v in iters.items()}, flush=True)
+    pick = [0, 39, 40, 111, 112, 175, 176, 255]   # two per mass, at the range edges
+    Xs, Bs = host(X[pick]), host(B[pick])
+    del X
+    sites = _sample_sites(dims, 16, 11) + _sample_sites(dims, 8, 12, t_fixed=0)
+    for j, r in enumerate(pick):
+        res, bn = _pointwise_residual(U, Xs[j:j + 1], Bs[j:j + 1], sites, cfg["masses"][mi[r]], cfg["csw"])
+        assert res[0] <= 1e-10 * bn[0]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16n"])
+def test_c1_single_rhs_vs_oracle(prec):
+    import paper_2510_26313_amd as pl
+    require_gpu()
+    cfg = ls.CONFIGS["c1"]
+    dims = cfg["dims"]
+    U = ls.gauge_field(dims, cfg["seed_u"])
+    V = ls.orthonormal_laph_vectors(dims, cfg["nev"], cfg["seed_v"])
+    lat = make_lattice(dims, U, masses=cfg["masses"], csw=cfg["csw"])
+    rhs = [0, 77]
+    B = laph.laph_sources(V, 0)[rhs]
+    log_case("c1 single-rhs", prec=prec)
+    X, st = lat.solve_raw(dev(B), 0, 1e-10, pl.default_params(inner_prec=prec, batched=0))
+    D = dirac.WilsonClover(U, cfg["masses"][0], cfg["csw"])
+    x_ref, _ = solvers.bicgstab(D.apply, B, tol=1e-13)
+    assert per_rhs_rel(host(X), x_ref).max() < 1e-8

@@ -188,14 +188,17 @@ def ragged_ref(ragged):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16n"])
-@pytest.mark.parametrize("batched,tile", [(1, 0), (1, 2), (0, 1)])
+@pytest.mark.parametrize("batched,tile,stencil", [(1, 0, 0), (1, 2, 1), (1, 4, 2), (1, 8, 2), (0, 1, 1)])
 @pytest.mark.parametrize("graph", [1, 0])
-def test_solve_mixed_precision(ragged, ragged_ref, prec, batched, tile, graph):
+def test_solve_mixed_precision(ragged, ragged_ref, prec, batched, tile, stencil, graph):
     import paper_2510_26313_amd as pl
     U, lat = ragged
     b, x_ref = ragged_ref
-    log_case("solve", prec=prec, batched=batched, tile=tile, graph=graph)
-    p = pl.default_params(inner_prec=prec, batched=batched, rhs_tile=tile, use_graph=graph, graph_iters=4)
+    if prec == "f64" and stencil == 2:
+        tile, stencil = 2, 1      # FP64 runs the register-tile form only
+    log_case("solve", prec=prec, batched=batched, tile=tile, stencil=stencil, graph=graph)
+    p = pl.default_params(inner_prec=prec, batched=batched, rhs_tile=tile, stencil=stencil, use_graph=graph,
+                          graph_iters=4)
     X, st = lat.solve_raw(dev(b), 1, 1e-10, p)
     e = per_rhs_rel(host(X), x_ref)
     assert e.max() < 1e-8, (e.max(), st)
@@ -225,12 +228,37 @@ def test_solve_multimass_batched(ragged):
     mi = [i for i, n in enumerate(split) for _ in range(n)]
     b = ls.random_spinor(ls.spinor_shape(DIMS_RAGGED, len(mi)), 5020)
     log_case("solve_multimass")
-    X, st = lat.solve_raw(dev(b), mi, 1e-10, pl.default_params(inner_prec="f16n", rhs_tile=4))
+    X, st = lat.solve_raw(dev(b), mi, 1e-10, pl.default_params(inner_prec="f16n", rhs_tile=4, stencil=1))
     X = host(X)
     for m, m0 in enumerate(masses):
         idx = [r for r in range(len(mi)) if mi[r] == m]
         x_ref, _ = solvers.bicgstab(dirac.WilsonClover(U, m0, 1.0).apply, b[idx], tol=1e-13)
         assert per_rhs_rel(X[idx], x_ref).max() < 1e-8
+
+
+def test_solve_multimass_lds(ragged):
+    """Uneven mass split with the LDS-staged stencil (tiles of 8 RHS of one mass)."""
+    import paper_2510_26313_amd as pl
+    U, _ = ragged
+    masses = (0.02, 0.2)
+    mi = [0] * 5 + [1] * 11
+    lat = make_lattice(DIMS_RAGGED, U, masses=masses)
+    b = ls.random_spinor(ls.spinor_shape(DIMS_RAGGED, len(mi)), 5021)
+    log_case("solve_multimass_lds")
+    X, st = lat.solve_raw(dev(b), mi, 1e-10, pl.default_params(inner_prec="f32", rhs_tile=8, stencil=2))
+    X = host(X)
+    for m, m0 in enumerate(masses):
+        idx = [r for r in range(len(mi)) if mi[r] == m]
+        x_ref, _ = solvers.bicgstab(dirac.WilsonClover(U, m0, 1.0).apply, b[idx], tol=1e-13)
+        assert per_rhs_rel(X[idx], x_ref).max() < 1e-8
+
+
+@pytest.mark.parametrize("prec,stencil,tile", [("f16n", 2, 16), ("f16n", 1, 4), ("f32", 2, 8), ("f64", 1, 2)])
+def test_time_stages_runs(ragged, prec, stencil, tile):
+    U, lat = ragged
+    log_case("time_stages", prec=prec, stencil=stencil, tile=tile)
+    ms1, ms2 = lat.time_stages(prec, 16, tile, 0, reps=2, stencil=stencil)
+    assert ms1 > 0 and ms2 > 0
 
 
 def test_solve_x0_warm_start(ragged, ragged_ref):

@@ -458,3 +458,19 @@ def test_codec_bound_and_zero():
     # the largest component is coded as +-1 exactly
     i = np.argmax(np.abs(v[0]))
     assert abs(float(q[0, i])) == 1.0
+
+
+def test_sampled_sites_match_full_operator():
+    """The one-site form of D (used for sampled checks at large sizes) equals the full operator."""
+    dims = (4, 6, 4, 6)
+    U = ls.gauge_field(dims, 23)
+    psi = ls.random_spinor(ls.spinor_shape(dims, 2), 24)
+    D = dirac.WilsonClover(U, 0.02, 1.0)
+    full = D.apply(psi)
+    fulld = D.apply_dagger(psi)
+    sites = [(0, 0, 0, 0), (5, 3, 5, 3), (2, 1, 4, 0), (5, 0, 0, 3)]
+    got = dirac.apply_at_sites(U, psi, sites, 0.02, 1.0)
+    gotd = dirac.apply_at_sites(U, psi, sites, 0.02, 1.0, dagger=True)
+    for i, (t, z, y, x) in enumerate(sites):
+        assert np.abs(got[:, i] - full[:, t, z, y, x]).max() < 1e-13
+        assert np.abs(gotd[:, i] - fulld[:, t, z, y, x]).max() < 1e-13
