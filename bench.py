@@ -90,8 +90,9 @@ def main():
     ap.add_argument("--config", default="c4")
     ap.add_argument("--prec", default="f16n")
     ap.add_argument("--chunk", type=int, default=128)
-    ap.add_argument("--rhs-tile", type=int, default=16)
-    ap.add_argument("--stencil", type=int, default=2, help="1 register RHS tiles, 2 LDS-staged links")
+    ap.add_argument("--rhs-tile", type=int, default=0, help="RHS per link load (0: autotuned)")
+    ap.add_argument("--stencil", type=int, default=0, help="1 register RHS tiles, 2 LDS-staged links, 0 autotuned")
+    ap.add_argument("--traversal", type=int, default=0, help="1 tiles of a site block together, 2 tile sweeps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--fp64-sample", type=int, default=4, help="RHS for the plain FP64 single-RHS comparison")
@@ -119,8 +120,13 @@ def main():
     lat.set_masses([m0], cfg["csw"])
     Vd = torch.from_numpy(V).cuda()
     del V
+    tuned = None
+    if args.stencil == 0 or args.rhs_tile <= 0:
+        # the library's autotuner picks the stencil form and RHS per link load for this batch
+        tuned = lat.autotune(args.prec, args.chunk, 0)
+        args.stencil, args.rhs_tile, args.traversal = tuned["stencil"], tuned["rhs_tile"], tuned["traversal"]
     params = laph.default_params(inner_prec=args.prec, batched=1, chunk=args.chunk, rhs_tile=args.rhs_tile,
-                                 stencil=args.stencil)
+                                 stencil=args.stencil, traversal=args.traversal)
     setup_s = time.perf_counter() - t_setup
     t0s = cfg["t0s"]
 
@@ -160,7 +166,8 @@ def main():
         del B
 
     # dominant kernels: the two fused stencil stages, timed with HIP events on the lattice stream
-    ms1, ms2 = lat.time_stages(args.prec, args.chunk, args.rhs_tile, 0, reps=20, stencil=args.stencil)
+    ms1, ms2 = lat.time_stages(args.prec, args.chunk, args.rhs_tile, 0, reps=20, stencil=args.stencil,
+                               traversal=args.traversal)
     vh = int(np.prod(dims)) // 2
     b1 = stage_bytes_per_site(args.prec, args.chunk, 1) * vh
     gbs1 = b1 / (ms1 * 1e-3) / 1e9
@@ -190,12 +197,13 @@ def main():
                                                   args.chunk, dims[3]),
                    "lattice": "x".join(map(str, dims)), "nev": nev, "rhs_per_step": 4 * nev,
                    "inner_prec": args.prec, "chunk": args.chunk, "rhs_tile": args.rhs_tile,
-                   "stencil": "lds_links" if args.stencil == 2 else "register_tiles"},
+                   "stencil": "lds_links" if args.stencil == 2 else "register_tiles",
+                   "traversal": "tile_sweeps" if args.traversal == 2 else "site_block_tiles"},
         "roofline": roofline,
         "detail": {"solve_ms": round(ms_solve, 1), "project_ms": round(ms_proj, 1),
                    "max_true_res": worst, "mean_iters": float(np.mean([s["iters"] for s in stats_all])),
                    "mean_updates": float(np.mean([s["updates"] for s in stats_all])),
-                   "setup_s": round(setup_s, 1), "fp64_single_rhs": fp64},
+                   "setup_s": round(setup_s, 1), "fp64_single_rhs": fp64, "autotuned": tuned},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, dims, args.cpu_seconds)

@@ -86,6 +86,8 @@ typedef struct {
     int chunk;         /* laph_perambulator: RHS per solver batch; <= 0: largest that fits */
     int stencil;       /* inner stencil form: 1 register RHS tiles (one thread, several RHS),
                           2 links staged in LDS (one wave per RHS); 0: chosen by the library */
+    int traversal;     /* stencil workgroup order: 1 the tiles of one site block together,
+                          2 each tile sweeps the lattice; 0: chosen by the library */
 } laph_solve_params;
 
 typedef struct {
@@ -195,15 +197,28 @@ laph_status laph_last_timings(laph_ctx ctx, double *ms_host3);
 /* Measurement of the solver's two fused stencil kernels on synthetic fields:
  * launches the inner-iteration stages of M_hat exactly as the batched solver
  * does for nrhs right-hand sides of one mass (mass_idx) in the stencil form
- * `stencil` (1 register tiles, 2 LDS-staged links) with tiles of rhs_tile --
+ * `stencil` (1 register tiles, 2 LDS-staged links) with tiles of rhs_tile and
+ * workgroup order `traversal` (1 or 2, as in laph_solve_params) --
  * stage 1: t_o = A_oo^-1 H_oe p_e;  stage 2: v_e = p_e - 1/4 A_ee^-1 H_eo t_o with
  * the fused <r^, v> partial sums -- each reps times, and returns the average
  * duration of one launch in ms_host2[0] (stage 1) and ms_host2[1] (stage 2),
  * measured with HIP events on the context stream.  The fields hold a fixed
  * byte pattern; work must hold laph_time_stages_workspace_bytes bytes. */
 size_t laph_time_stages_workspace_bytes(laph_ctx ctx, int prec, int nrhs, int rhs_tile);
-laph_status laph_time_stages(laph_ctx ctx, int prec, int nrhs, int stencil, int rhs_tile, int mass_idx,
-                             int reps, void *work, size_t work_bytes, double *ms_host2);
+laph_status laph_time_stages(laph_ctx ctx, int prec, int nrhs, int stencil, int rhs_tile, int traversal,
+                             int mass_idx, int reps, void *work, size_t work_bytes, double *ms_host2);
+
+/* Autotuner (the paper tunes launch parameters per machine, Sec. "QUDA"):
+ * time every stencil form / RHS-per-link-load candidate for nrhs RHS of
+ * mass_idx as laph_time_stages does, keep the fastest for this context and
+ * (inner precision, nrhs), and return it (stencil 1 or 2, rhs_tile, traversal).
+ * laph_solve / laph_perambulator with stencil = 0 and rhs_tile <= 0 use the
+ * tuned choice for their batch size, tuning on first use on their own
+ * workspace.  If the environment variable LAPH_TUNE_CACHE names a file,
+ * choices are appended there and read back by later contexts of the same
+ * lattice.  work: laph_time_stages_workspace_bytes(ctx, prec, nrhs, 16). */
+laph_status laph_autotune(laph_ctx ctx, int prec, int nrhs, int mass_idx, void *work, size_t work_bytes,
+                          int *stencil_out, int *rhs_tile_out, int *traversal_out, double *ms_host);
 
 #ifdef __cplusplus
 }

@@ -26,7 +26,8 @@ STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "HIP", 3: "WORKSPACE", 4: "NOCONV", 5:
 class SolveParams(ctypes.Structure):
     _fields_ = [("inner_prec", c_int), ("batched", c_int), ("delta", c_double), ("maxiter", c_int),
                 ("graph_iters", c_int), ("use_graph", c_int), ("dagger", c_int), ("use_x0", c_int),
-                ("rhs_tile", c_int), ("chunk", c_int), ("stencil", c_int)]
+                ("rhs_tile", c_int), ("chunk", c_int), ("stencil", c_int),
+                ("traversal", c_int)]
 
 
 class RhsStats(ctypes.Structure):
@@ -62,8 +63,10 @@ _SIGS = [
     ("laph_project_adjoint", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int]),
     ("laph_last_timings", c_int, [c_void_p, P(c_double)]),
     ("laph_time_stages_workspace_bytes", c_size_t, [c_void_p, c_int, c_int, c_int]),
-    ("laph_time_stages", c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int, c_void_p, c_size_t,
+    ("laph_time_stages", c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_void_p, c_size_t,
                                  P(c_double)]),
+    ("laph_autotune", c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_size_t, P(c_int), P(c_int), P(c_int),
+                              P(c_double)]),
 ]
 EXPORTED = [s[0] for s in _SIGS]
 

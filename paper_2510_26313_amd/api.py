@@ -213,13 +213,21 @@ class Lattice:
         L.check(self.lib.laph_last_timings(self.ctx, ms))
         return dict(total_ms=ms[0], solve_ms=ms[1], project_ms=ms[2])
 
-    def time_stages(self, prec, nrhs, rhs_tile=4, mass_idx=0, reps=20, stencil=2):
+    def time_stages(self, prec, nrhs, rhs_tile=4, mass_idx=0, reps=20, stencil=2, traversal=2):
         """Average ms per launch of the solver's two fused stencil stages (HIP events)."""
         w = self._workspace(self.lib.laph_time_stages_workspace_bytes(self.ctx, L.PREC[prec], nrhs, rhs_tile))
         ms = (ctypes.c_double * 2)()
-        L.check(self._run(self.lib.laph_time_stages, self.ctx, L.PREC[prec], nrhs, stencil, rhs_tile, mass_idx,
-                          reps, _ptr(w), w.numel(), ms))
+        L.check(self._run(self.lib.laph_time_stages, self.ctx, L.PREC[prec], nrhs, stencil, rhs_tile, traversal,
+                          mass_idx, reps, _ptr(w), w.numel(), ms))
         return ms[0], ms[1]
+
+    def autotune(self, prec, nrhs, mass_idx=0):
+        """Measure and keep the fastest stencil form / RHS per link load for this batch size."""
+        w = self._workspace(self.lib.laph_time_stages_workspace_bytes(self.ctx, L.PREC[prec], nrhs, 16))
+        st, tile, trav, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        L.check(self._run(self.lib.laph_autotune, self.ctx, L.PREC[prec], nrhs, mass_idx, _ptr(w), w.numel(),
+                          ctypes.byref(st), ctypes.byref(tile), ctypes.byref(trav), ctypes.byref(ms)))
+        return dict(stencil=st.value, rhs_tile=tile.value, traversal=trav.value, ms=ms.value)
 
     def make_sources(self, V, t0):
         nev = V.shape[1]

@@ -34,6 +34,7 @@ laph_status launch_stage(const Ctx &c, const StageSpec &s) {
     a.ntiles_max = s.tiles.ntiles_max;
     a.nsb = stage_nsb(c, s.form);
     a.pstride = s.pstride;
+    a.site_major = s.site_major;
     a.st = s.slots;
     a.partials = s.partials;
     if (a.ntiles_max <= 0) return LAPH_OK;

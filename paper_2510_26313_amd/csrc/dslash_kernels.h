@@ -44,9 +44,26 @@ struct StageArgs {
     int ntiles_max;
     int nsb;
     int pstride;
+    int site_major;
     const SlotState *st;
     double *partials;
 };
+
+// Workgroup -> (site block, tile), after the XCD remap.  Tile-major: the tiles of
+// one site block are consecutive, so they share its links in one L2.  Site-major:
+// each tile sweeps all site blocks before the next (each XCD takes whole tiles),
+// so neighbouring site blocks -- whose spinors are each other's hop inputs --
+// run together on one XCD and share its L2.
+__device__ __forceinline__ void stage_block(int site_major, int nsb, int ntiles_max, int &sb, int &tile) {
+    const int L = xcd_logical_block();
+    if (site_major) {
+        tile = L / nsb;
+        sb = L - tile * nsb;
+    } else {
+        sb = L / ntiles_max;
+        tile = L - sb * ntiles_max;
+    }
+}
 
 // --- spin projection: (1 + S gamma_mu) psi = (h0, h1, row2(h), row3(h)) --------
 // gamma_x rows: (i p3, i p2, -i p1, -i p0); gamma_y: (-p3, p2, p1, -p0);
@@ -211,9 +228,8 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NV], double *dst,
 template <class P, int NR, bool DAG, bool CLOVER, bool PRE, int POST, int RED, bool FLAGGED>
 __global__ __launch_bounds__(kBlock) LAPH_STAGE_OCCUPANCY void stage_kernel(StageArgs A) {
     using R = typename P::real;
-    const int L = xcd_logical_block();
-    const int sb = L / A.ntiles_max;
-    const int tile = L - sb * A.ntiles_max;
+    int sb, tile;
+    stage_block(A.site_major, A.nsb, A.ntiles_max, sb, tile);
     if (sb >= A.nsb || tile >= *A.ntiles) return;
     int slots[NR];
     bool any = false;

@@ -46,9 +46,8 @@ __global__ __launch_bounds__(256) void stage_lds_kernel(StageArgs A) {
     constexpr int NT = 4 * RW;
     __shared__ R lnk[8][18][kLdsSites];
     __shared__ int nbr[8][kLdsSites];
-    const int Lb = xcd_logical_block();
-    const int sb = Lb / A.ntiles_max;
-    const int tile = Lb - sb * A.ntiles_max;
+    int sb, tile;
+    stage_block(A.site_major, A.nsb, A.ntiles_max, sb, tile);
     if (sb >= A.nsb || tile >= *A.ntiles) return;
     const Geom &g = A.g;
     const int p = A.out_parity;

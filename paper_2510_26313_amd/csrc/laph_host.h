@@ -1,7 +1,9 @@
 // Host-side context and launcher declarations of liblaph.
 #pragma once
 
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "laph_internal.h"
@@ -64,6 +66,11 @@ struct Ctx {
     size_t pinned_i_len = 0;
     hipEvent_t ev[4]{};
     double last_ms[3]{};
+    // autotuned stencil shape per (inner precision, batch size)
+    struct Shape {
+        int form, tile, site_major;
+    };
+    std::map<std::pair<int, int>, Shape> tuned;
 
     size_t hv(int prec) const { return hv_bytes(prec, (size_t)g.vh); }
     // misc region: per-mass diagonal 4 + m0, the SU(3) deviation and the clover failure flag
@@ -118,6 +125,7 @@ struct StageSpec {
     Operand in, out, y, y2, z, w;
     double a = 0, a2 = 0, b = 1, c = 0;
     Tiles tiles;
+    int site_major = 0;                 // 1: each tile sweeps all site blocks (see stage_block)
     int form = kFormRegister;           // kFormRegister: tiles.nr RHS per thread;
                                         // kFormLds: tiles.nr = 4 * RW RHS per workgroup, links in LDS
     const SlotState *slots = nullptr;   // may be null when flagged == 0
@@ -145,6 +153,17 @@ struct CloverSpec {
     int n = 0;
 };
 laph_status launch_clover(const Ctx &c, const CloverSpec &s);
+
+// ---- autotuner (tune.hip) ------------------------------------------------------
+// Time the solver's two fused stages for nrhs RHS in one form / tile; fields holds
+// 4 * nrhs half-vectors of prec, partials nrhs * 3 * partial_stride doubles,
+// d_ints tune_ints(nrhs) ints.
+laph_status time_stage_pair(const Ctx &c, int prec, int nrhs, int form, int tile, int site_major, int mass_idx,
+                            int reps, char *fields, double *partials, int *d_ints, double ms[2]);
+laph_status autotune_stencil(Ctx &c, int prec, int nrhs, int mass_idx, char *fields, double *partials, int *d_ints,
+                             Ctx::Shape *out, double *ms_out);
+void load_tune_cache(Ctx &c);
+size_t tune_ints(int nrhs);
 
 // ---- setup kernels (setup.hip) ------------------------------------------------
 laph_status load_gauge(Ctx &c, const double *U);

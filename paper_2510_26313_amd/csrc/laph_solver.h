@@ -54,12 +54,16 @@ class Solver {
         int *tile64_slots = nullptr, *tile64_mass = nullptr;  // FP64 register tiles
         int *list = nullptr, *slot_mass = nullptr;
         int *ntiles = nullptr, *nlist = nullptr, *ntiles64 = nullptr;
-        size_t nints = 0;
+        int *ints = nullptr;          // integer region the tables are carved from
+        size_t nints = 0, nints_used = 0;
     };
 
     static void choose_shape(const laph_solve_params &p, int ns, int &form, int &nr, int &nr64);
-    static size_t layout(const Ctx &c, int ns, int nr, int nr64, int prec, char *base, WS *ws);
-    laph_status init(const Ctx &ctx, int nslots, const laph_solve_params &params, char *work, size_t bytes);
+    static size_t layout(const Ctx &c, int ns, int prec, char *base, WS *ws);
+    // tune_mass >= 0: with stencil == 0 and rhs_tile <= 0, measure the stencil shape
+    // for this batch if no tuned choice exists yet (on the workspace, before use)
+    laph_status init(Ctx &ctx, int nslots, const laph_solve_params &params, char *work, size_t bytes,
+                     int tune_mass = -1);
     ~Solver();
 
     // Solve the n = src.n RHS of one batch (slot s <- RHS s of the spec).
@@ -71,7 +75,8 @@ class Solver {
    private:
     const Ctx *c = nullptr;
     laph_solve_params p{};
-    int ns = 0, prec = 0, form = kFormRegister, nr = 1, nr64 = 1, nsb256 = 0, nsb_inner = 0, pstride = 0;
+    int ns = 0, prec = 0, form = kFormRegister, nr = 1, nr64 = 1, site_major = 0, nsb256 = 0, nsb_inner = 0,
+        pstride = 0;
     WS ws;
     std::vector<int> mass;
     std::vector<int> host_ints;
@@ -79,6 +84,7 @@ class Solver {
     hipGraphExec_t graph_exec = nullptr;
     int graph_k = 0;
 
+    void carve_tables();
     BlasArgs blas(int list_max) const;
     FinArgs fin(int list_max, int nsb = 0) const;
     Tiles tiles(bool f64) const;

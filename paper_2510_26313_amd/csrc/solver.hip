@@ -25,9 +25,10 @@ namespace laph {
 // RHS per register tile: 4, 2 or 1
 static int reg_tile(int ns) { return ns >= 4 ? 4 : (ns >= 2 ? 2 : 1); }
 
-// Stencil form and tile size of the inner iterations: FP64 keeps the register
-// tiles (its LDS link stage would need twice the LDS); FP32 / FP16N use the
-// LDS-staged links with up to 16 RHS sharing each link load.
+// Stencil form and tile size of the inner iterations when the caller fixes them
+// or no tuned choice exists: FP64 keeps the register tiles (its LDS link stage
+// would need twice the LDS); FP32 / FP16N use the LDS-staged links with up to
+// 16 RHS sharing each link load.
 void Solver::choose_shape(const laph_solve_params &p, int ns, int &form, int &nr, int &nr64) {
     const int prec = p.inner_prec;
     form = prec == LAPH_F64 ? kFormRegister : kFormLds;
@@ -40,7 +41,11 @@ void Solver::choose_shape(const laph_solve_params &p, int ns, int &form, int &nr
     nr64 = prec == LAPH_F64 ? nr : reg_tile(ns);
 }
 
-size_t Solver::layout(const Ctx &c, int ns, int nr, int nr64, int prec, char *base, WS *ws) {
+// The integer tables are sized for the largest tile (16), so the workspace does
+// not depend on the tuned shape.
+static size_t table_ints(int ns) { return (size_t)ns * 16 + (size_t)ns * 4 + 4 * (size_t)ns + 8; }
+
+size_t Solver::layout(const Ctx &c, int ns, int prec, char *base, WS *ws) {
     const size_t h64 = c.hv(LAPH_F64), hlo = c.hv(prec), hx = c.hv(prec == LAPH_F64 ? LAPH_F64 : LAPH_F32);
     const int pstride = partial_stride(c);
     size_t off = 0;
@@ -61,6 +66,7 @@ size_t Solver::layout(const Ctx &c, int ns, int nr, int nr64, int prec, char *ba
     w.E2 = op(take(ns * h64), h64);
     w.O0 = op(take(ns * h64), h64);
     w.O1 = op(take(ns * h64), h64);
+    // r, rh, p, v are contiguous: the autotuner uses them as its 4 * ns fields
     w.r = op(take(ns * hlo), hlo);
     w.rh = op(take(ns * hlo), hlo);
     w.p = op(take(ns * hlo), hlo);
@@ -70,51 +76,75 @@ size_t Solver::layout(const Ctx &c, int ns, int nr, int nr64, int prec, char *ba
     w.x = op(take(ns * hx), hx);
     size_t o_st = take(ns * sizeof(SlotState));
     size_t o_part = take((size_t)ns * 3 * pstride * sizeof(double));
-    const size_t nints = (size_t)ns * nr + (size_t)ns * nr64 + 4 * (size_t)ns + 8;
+    const size_t nints = std::max(table_ints(ns), tune_ints(ns));
     size_t o_ints = take(nints * sizeof(int));
     if (ws && base) {
         w.st = reinterpret_cast<SlotState *>(base + o_st);
         w.partials = reinterpret_cast<double *>(base + o_part);
-        int *ints = reinterpret_cast<int *>(base + o_ints);
-        w.tile_slots = ints;
-        w.tile_mass = w.tile_slots + (size_t)ns * nr;
-        w.tile64_slots = w.tile_mass + ns;
-        w.tile64_mass = w.tile64_slots + (size_t)ns * nr64;
-        w.list = w.tile64_mass + ns;
-        w.slot_mass = w.list + ns;
-        w.ntiles = w.slot_mass + ns;
-        w.nlist = w.ntiles + 1;
-        w.ntiles64 = w.ntiles + 2;
+        w.ints = reinterpret_cast<int *>(base + o_ints);
         w.nints = nints;
         *ws = w;
     }
     return off;
 }
 
-size_t solver_workspace_bytes(const Ctx &c, int nslots, const laph_solve_params &p) {
-    int form, nr, nr64;
-    Solver::choose_shape(p, nslots, form, nr, nr64);
-    return Solver::layout(c, nslots, nr, nr64, p.inner_prec, nullptr, nullptr);
+// carve the tile tables for the chosen tile sizes out of the integer region
+void Solver::carve_tables() {
+    int *ints = ws.ints;
+    ws.tile_slots = ints;
+    ws.tile_mass = ws.tile_slots + (size_t)ns * nr;
+    ws.tile64_slots = ws.tile_mass + ns;
+    ws.tile64_mass = ws.tile64_slots + (size_t)ns * nr64;
+    ws.list = ws.tile64_mass + ns;
+    ws.slot_mass = ws.list + ns;
+    ws.ntiles = ws.slot_mass + ns;
+    ws.nlist = ws.ntiles + 1;
+    ws.ntiles64 = ws.ntiles + 2;
+    ws.nints_used = (size_t)(ws.ntiles64 + 1 - ints);
 }
 
-laph_status Solver::init(const Ctx &ctx, int nslots, const laph_solve_params &params, char *work, size_t bytes) {
+size_t solver_workspace_bytes(const Ctx &c, int nslots, const laph_solve_params &p) {
+    return Solver::layout(c, nslots, p.inner_prec, nullptr, nullptr);
+}
+
+laph_status Solver::init(Ctx &ctx, int nslots, const laph_solve_params &params, char *work, size_t bytes,
+                         int tune_mass) {
     c = &ctx;
     p = params;
     ns = nslots;
     prec = p.inner_prec;
-    choose_shape(p, ns, form, nr, nr64);
-    if (form == kFormRegister && nr != 1 && nr != 2 && nr != 4)
-        return set_error(LAPH_ERR_INVALID, "rhs_tile must be 1, 2 or 4 for register tiles");
-    if (form == kFormLds && nr != 4 && nr != 8 && nr != 16)
-        return set_error(LAPH_ERR_INVALID, "rhs_tile must be 4, 8 or 16 for LDS-staged links");
-    const size_t need = layout(ctx, ns, nr, nr64, prec, nullptr, nullptr);
+    const size_t need = layout(ctx, ns, prec, nullptr, nullptr);
     if (!work || bytes < need)
         return set_error(LAPH_ERR_WORKSPACE, "solver workspace too small: %zu < %zu bytes", bytes, need);
-    layout(ctx, ns, nr, nr64, prec, work, &ws);
+    layout(ctx, ns, prec, work, &ws);
+    choose_shape(p, ns, form, nr, nr64);
+    site_major = p.traversal == 2 ? 1 : 0;
+    if (p.stencil == 0 && p.rhs_tile <= 0) {
+        // autotuned shape: reuse a choice for this (precision, batch) or measure one now
+        auto it = ctx.tuned.find({prec, ns});
+        if (it == ctx.tuned.end() && tune_mass >= 0) {
+            Ctx::Shape sh{};
+            LAPH_TRY(autotune_stencil(ctx, prec, ns, tune_mass, ws.r.base, ws.partials, ws.ints, &sh, nullptr));
+            it = ctx.tuned.find({prec, ns});
+        }
+        if (it != ctx.tuned.end()) {
+            form = it->second.form;
+            nr = it->second.tile;
+            if (p.traversal == 0) site_major = it->second.site_major;
+            if (prec == LAPH_F64) nr64 = nr;
+        }
+    }
+    if (form == kFormRegister && nr != 1 && nr != 2 && nr != 4)
+        return set_error(LAPH_ERR_INVALID, "rhs_tile must be 1, 2 or 4 for register tiles");
+    if (form == kFormLds && (nr != 4 && nr != 8 && nr != 16))
+        return set_error(LAPH_ERR_INVALID, "rhs_tile must be 4, 8 or 16 for LDS-staged links");
+    if (form == kFormLds && prec == LAPH_F64)
+        return set_error(LAPH_ERR_INVALID, "the LDS-staged stencil form is available for FP32 and FP16N");
+    carve_tables();
     nsb256 = stage_nsb(ctx, kFormRegister);
     nsb_inner = stage_nsb(ctx, form);
     pstride = partial_stride(ctx);
-    host_ints.assign(ws.nints, 0);
+    host_ints.assign(ws.nints_used, 0);
     host_st.assign(ns, SlotState{});
     return LAPH_OK;
 }
@@ -240,6 +270,7 @@ laph_status Solver::stage(int sprec, int out_parity, Operand in, Operand out, in
     const bool f64 = sprec == LAPH_F64;
     s.tiles = tiles(f64);
     s.form = f64 ? kFormRegister : form;
+    s.site_major = site_major;
     s.slots = ws.st;
     s.partials = ws.partials;
     s.pstride = pstride;

@@ -188,17 +188,18 @@ def ragged_ref(ragged):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16n"])
-@pytest.mark.parametrize("batched,tile,stencil", [(1, 0, 0), (1, 2, 1), (1, 4, 2), (1, 8, 2), (0, 1, 1)])
+@pytest.mark.parametrize("batched,tile,stencil,trav", [(1, 0, 0, 0), (1, 2, 1, 2), (1, 4, 2, 1), (1, 8, 2, 2),
+                                                      (0, 1, 1, 1)])
 @pytest.mark.parametrize("graph", [1, 0])
-def test_solve_mixed_precision(ragged, ragged_ref, prec, batched, tile, stencil, graph):
+def test_solve_mixed_precision(ragged, ragged_ref, prec, batched, tile, stencil, trav, graph):
     import paper_2510_26313_amd as pl
     U, lat = ragged
     b, x_ref = ragged_ref
     if prec == "f64" and stencil == 2:
         tile, stencil = 2, 1      # FP64 runs the register-tile form only
     log_case("solve", prec=prec, batched=batched, tile=tile, stencil=stencil, graph=graph)
-    p = pl.default_params(inner_prec=prec, batched=batched, rhs_tile=tile, stencil=stencil, use_graph=graph,
-                          graph_iters=4)
+    p = pl.default_params(inner_prec=prec, batched=batched, rhs_tile=tile, stencil=stencil, traversal=trav,
+                          use_graph=graph, graph_iters=4)
     X, st = lat.solve_raw(dev(b), 1, 1e-10, p)
     e = per_rhs_rel(host(X), x_ref)
     assert e.max() < 1e-8, (e.max(), st)
@@ -253,12 +254,26 @@ def test_solve_multimass_lds(ragged):
         assert per_rhs_rel(X[idx], x_ref).max() < 1e-8
 
 
-@pytest.mark.parametrize("prec,stencil,tile", [("f16n", 2, 16), ("f16n", 1, 4), ("f32", 2, 8), ("f64", 1, 2)])
-def test_time_stages_runs(ragged, prec, stencil, tile):
+@pytest.mark.parametrize("prec,stencil,tile,trav", [("f16n", 2, 16, 2), ("f16n", 1, 4, 1), ("f32", 2, 8, 1),
+                                                   ("f64", 1, 2, 2)])
+def test_time_stages_runs(ragged, prec, stencil, tile, trav):
     U, lat = ragged
-    log_case("time_stages", prec=prec, stencil=stencil, tile=tile)
-    ms1, ms2 = lat.time_stages(prec, 16, tile, 0, reps=2, stencil=stencil)
+    log_case("time_stages", prec=prec, stencil=stencil, tile=tile, traversal=trav)
+    ms1, ms2 = lat.time_stages(prec, 16, tile, 0, reps=2, stencil=stencil, traversal=trav)
     assert ms1 > 0 and ms2 > 0
+
+
+def test_autotune_and_auto_solve(ragged, ragged_ref):
+    """The autotuner returns a valid shape, and an automatic solve (tuning on first use) converges."""
+    import paper_2510_26313_amd as pl
+    U, lat = ragged
+    b, x_ref = ragged_ref
+    log_case("autotune")
+    t = lat.autotune("f16n", 6, 1)
+    assert (t["stencil"], t["rhs_tile"]) in [(1, 1), (1, 2), (1, 4), (2, 4), (2, 8), (2, 16)] and t["ms"] > 0
+    assert t["traversal"] in (1, 2)
+    X, st = lat.solve_raw(dev(b), 1, 1e-10, pl.default_params(inner_prec="f32", stencil=0, rhs_tile=0))
+    assert per_rhs_rel(host(X), x_ref).max() < 1e-8
 
 
 def test_solve_x0_warm_start(ragged, ragged_ref):
