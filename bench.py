@@ -50,7 +50,10 @@ def stage_bytes_per_site(prec, n_rhs, stage):
 def cpu_baseline(cfg, dims, seconds_budget=20.0):
     """The FP64 oracle timed on the host: full-lattice BiCGStab iterations on the
     headline lattice for one LapH source, scaled to RHS/s with the iteration count
-    the oracle needs for 1e-10 on the same parameters (measured on 8^3 x 16)."""
+    the oracle needs for 1e-10 on the same parameters (measured on 8^3 x 16).
+
+    One iteration costs T(2 iterations) - T(1 iteration) of the oracle's solver
+    (each call also forms the initial and the final true residual)."""
     from oracle import dirac, laph as olaph, solvers
     m0, csw = cfg["masses"][0], cfg["csw"]
     # iteration count at the same mass and gauge parameters on a small lattice
@@ -66,20 +69,89 @@ def cpu_baseline(cfg, dims, seconds_budget=20.0):
     D = dirac.WilsonClover(U, m0, csw)
     b = olaph.laph_sources(V1, 0)[:1]
     D.apply(b)  # first touch
-    t = time.perf_counter()
-    k = 0
-    while True:
-        k += 1
-        solvers.bicgstab(D.apply, b, tol=1e-30, maxiter=1, max_restarts=0)
-        if time.perf_counter() - t > seconds_budget * 0.5 or k >= 8:
+
+    def run(k_iters):
+        t = time.perf_counter()
+        solvers.bicgstab(D.apply, b, tol=1e-30, maxiter=k_iters, max_restarts=0)
+        return time.perf_counter() - t
+
+    t1, t2, reps = [], [], 0
+    t_start = time.perf_counter()
+    while reps < 4:
+        t1.append(run(1))
+        t2.append(run(2))
+        reps += 1
+        if time.perf_counter() - t_start > seconds_budget:
             break
-    per_iter = (time.perf_counter() - t) / k   # one BiCGStab iteration incl. its true-residual check
+    per_iter = max(min(t2) - min(t1), 1e-9)
     rhs_per_s = 1.0 / (per_iter * n_it)
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
     return {"value": rhs_per_s, "unit": "RHS/s", "cores": cores, "kind": "oracle",
-            "sample": "%d full-lattice FP64 BiCGStab iterations (1 RHS) at %s, scaled by the %d iterations "
-                      "the oracle needs for 1e-10 at m0=%g (measured on 8^3x16)" % (k, "x".join(map(str, dims)),
-                                                                                  n_it, m0)}
+            "sample": "1 LapH source on %s: the FP64 oracle BiCGStab run for 1 and for 2 iterations (%d times "
+                      "each); one iteration = the difference of the fastest runs (%.2f s), times the %d "
+                      "iterations the oracle needs for 1e-10 at m0=%g (measured on 8^3x16)"
+                      % ("x".join(map(str, dims)), reps, per_iter, n_it, m0)}
+
+
+# The stencil sources whose counters a stored traffic figure describes.
+STAGE_SOURCES = ["dslash_kernels.h", "dslash_lds.h", "laph_internal.h", "dslash_f16.hip", "dslash_f32.hip",
+                 "dslash_f64.hip", "dslash.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage1_pmc_traffic.md")
+
+
+def stage_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in STAGE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2510_26313_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(key):
+    """HBM bytes per launch of the dominant stage from the committed counter
+    summary, or None when there is none for this shape or the stencil sources
+    changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    digest = stage_source_digest()
+    for ln in lines:
+        if ln.startswith("traffic:"):
+            f = dict(kv.split("=", 1) for kv in ln[len("traffic:"):].split())
+            if f.get("key") == key and f.get("sources") == digest:
+                return float(f["bytes_per_launch"])
+    return None
+
+
+def stage_key(args, dims):
+    return "%s/%s/n%d/s%d/t%d/v%d" % ("x".join(map(str, dims)), args.prec, args.chunk, args.stencil,
+                                      args.rhs_tile, args.traversal)
+
+
+def pmc_probe(args, cfg, torch, laph):
+    """Launch the dominant stage of the bench workload (shape given on the command
+    line; unit gauge, the traffic does not depend on the values) and a plain
+    copy of known size, for hardware-counter runs."""
+    dims = cfg["dims"]
+    if args.stencil == 0 or args.rhs_tile <= 0 or args.traversal == 0:
+        sys.exit("--pmc-probe needs an explicit --stencil, --rhs-tile and --traversal")
+    lat = laph.Lattice(dims)
+    lat.load_gauge(torch.from_numpy(ls.unit_gauge(dims)).cuda())
+    lat.set_masses([cfg["masses"][0]], cfg["csw"])
+    ms1, ms2 = lat.time_stages(args.prec, args.chunk, args.rhs_tile, 0, reps=3, stencil=args.stencil,
+                               traversal=args.traversal)
+    print("stage key %s sources %s: stage1 %.4f ms stage2 %.4f ms (3 timed launches each, after one warm "
+          "launch)" % (stage_key(args, dims), stage_source_digest(), ms1, ms2), flush=True)
+    x = torch.empty(2 ** 29, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print("copy: 3 x 2 GiB device-to-device", flush=True)
 
 
 def main():
@@ -96,11 +168,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--fp64-sample", type=int, default=4, help="RHS for the plain FP64 single-RHS comparison")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="only launch the dominant stage (and a 2 GiB copy for the counter scale), for "
+                         "rocprofv3 --pmc runs; needs --stencil, --rhs-tile and --traversal")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the perambulator path is measured on one MI355X "
-              "(independent RHS batches would shard across GPUs with no collective; see DESIGN.md)",
-              file=sys.stderr)
+              "(independent RHS batches would shard across GPUs with no collective)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -108,6 +182,9 @@ def main():
 
     cfg = ls.CONFIGS[args.config]
     dims = cfg["dims"]
+    if args.pmc_probe:
+        pmc_probe(args, cfg, torch, laph)
+        return
     nev = cfg["nev"]
     m0 = cfg["masses"][0]
     tol = 1e-10
@@ -179,12 +256,22 @@ def main():
     else:
         roofline = {"bound": "hbm", "achieved": round(gbs1, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(gbs1 / HBM_PEAK_GBS, 4), "traffic": None}
+    tb = stored_traffic(stage_key(args, dims))
+    roofline["traffic"] = tb
     roofline.update({"kernel": "%s (stage 1: A_oo^-1 H_oe, %s, %d RHS per link load, %d RHS)"
                                % ("stage_lds_kernel" if args.stencil == 2 else "stage_kernel", args.prec,
                                   args.rhs_tile, args.chunk),
                      "ms_per_launch": round(ms1, 4), "algorithmic_bytes": b1, "hbm_gbs": round(gbs1, 1),
                      "hbm_frac": round(gbs1 / HBM_PEAK_GBS, 4), "tflops": round(tfl1, 3),
                      "stage2_ms_per_launch": round(ms2, 4)})
+
+    # the stencil at small batches, where it is bound by HBM (algorithmic bytes / time)
+    dslash = {}
+    for prec, nrhs, st, tile in (("f32", 1, 1, 1), ("f16n", 1, 1, 1), ("f32", 8, 2, 8), ("f16n", 8, 2, 8)):
+        m1, _ = lat.time_stages(prec, nrhs, tile, 0, reps=10, stencil=st, traversal=1)
+        gb = stage_bytes_per_site(prec, nrhs, 1) * vh / (m1 * 1e-3) / 1e9
+        dslash["%s_nrhs%d" % (prec, nrhs)] = {"ms": round(m1, 4), "gbs": round(gb, 1),
+                                              "hbm_frac": round(gb / HBM_PEAK_GBS, 4)}
 
     out = {
         "metric": "perambulator RHS solved/s at rel. residual 1e-10; Dslash HBM GB/s vs peak",
@@ -203,7 +290,8 @@ def main():
         "detail": {"solve_ms": round(ms_solve, 1), "project_ms": round(ms_proj, 1),
                    "max_true_res": worst, "mean_iters": float(np.mean([s["iters"] for s in stats_all])),
                    "mean_updates": float(np.mean([s["updates"] for s in stats_all])),
-                   "setup_s": round(setup_s, 1), "fp64_single_rhs": fp64, "autotuned": tuned},
+                   "setup_s": round(setup_s, 1), "fp64_single_rhs": fp64, "autotuned": tuned,
+                   "stage1_small_batches": dslash},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, dims, args.cpu_seconds)

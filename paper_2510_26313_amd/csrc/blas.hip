@@ -31,18 +31,30 @@ __device__ __forceinline__ void reduce_store(double *v, int nv, double *dst, siz
             for (int w = 0; w < kB / 64; ++w) s += red[w][q];
             dst[q * q_stride] = s;
         }
+    // a block handles several slots in turn: red is written again next round
+    __syncthreads();
 }
 
-// slot of this block, or -1 if the block has nothing to do
-__device__ __forceinline__ int blas_slot(const BlasArgs &A, int mode) {
-    const int j = blockIdx.y;
-    if (j >= *A.nlist) return -1;
-    const int s = A.list[j];
+// Entries of the slot list this launch walks: the flagged list (built on the
+// device after the rho finalize) in flagged mode, the slot list otherwise.
+__device__ __forceinline__ int blas_count(const BlasArgs &A, int mode) {
+    return mode == kModeFlagged ? *A.nflist : *A.nlist;
+}
+
+// slot of list entry j, or -1 if it has nothing to do in this mode
+__device__ __forceinline__ int blas_slot_at(const BlasArgs &A, int mode, int j) {
+    const int s = mode == kModeFlagged ? A.flist[j] : A.list[j];
     const SlotState &st = A.st[s];
     if (mode == kModeActive && st.status != LAPH_RHS_ACTIVE) return -1;
     if (mode == kModeFlagged && !(st.status == LAPH_RHS_ACTIVE && st.flag != 0)) return -1;
     return s;
 }
+
+// Grid rows walk the list entries j = blockIdx.y, blockIdx.y + gridDim.y, ...;
+// the slot test is uniform over the block.
+#define LAPH_FOR_SLOTS(A, mode, s)                                                              \
+    for (int j_ = blockIdx.y, n_ = blas_count(A, mode); j_ < n_; j_ += gridDim.y)              \
+        if (const int s = blas_slot_at(A, mode, j_); s >= 0)
 
 template <class R>
 __device__ __forceinline__ cplx<R> c_of(double2 z) {
@@ -53,41 +65,41 @@ __device__ __forceinline__ cplx<R> c_of(double2 z) {
 template <class P>
 __global__ __launch_bounds__(kB) void p_update_kernel(BlasArgs A) {
     using R = typename P::real;
-    const int s = blas_slot(A, kModeActive);
-    if (s < 0) return;
     const int h = blockIdx.x * kB + threadIdx.x;
     if (h >= A.vh) return;
-    const double2 beta = A.st[s].beta;
-    cplx<R> r[12];
-    SpinorIO<P>::load(A.r.at(s), A.vh, h, r);
-    if (beta.x == 0.0 && beta.y == 0.0) {
-        SpinorIO<P>::store(A.p.at(s), A.vh, h, r);
-        return;
-    }
-    const cplx<R> b = c_of<R>(beta), w = c_of<R>(A.st[s].omega);
-    cplx<R> p[12], v[12];
-    SpinorIO<P>::load(A.p.at(s), A.vh, h, p);
-    SpinorIO<P>::load(A.v.at(s), A.vh, h, v);
+    LAPH_FOR_SLOTS(A, kModeActive, s) {
+        const double2 beta = A.st[s].beta;
+        cplx<R> r[12];
+        SpinorIO<P>::load(A.r.at(s), A.vh, h, r);
+        if (beta.x == 0.0 && beta.y == 0.0) {
+            SpinorIO<P>::store(A.p.at(s), A.vh, h, r);
+            continue;
+        }
+        const cplx<R> b = c_of<R>(beta), w = c_of<R>(A.st[s].omega);
+        cplx<R> p[12], v[12];
+        SpinorIO<P>::load(A.p.at(s), A.vh, h, p);
+        SpinorIO<P>::load(A.v.at(s), A.vh, h, v);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) p[c] = r[c] + b * (p[c] - w * v[c]);
-    SpinorIO<P>::store(A.p.at(s), A.vh, h, p);
+        for (int c = 0; c < 12; ++c) p[c] = r[c] + b * (p[c] - w * v[c]);
+        SpinorIO<P>::store(A.p.at(s), A.vh, h, p);
+    }
 }
 
 // r = r - alpha v   (r becomes s)
 template <class P>
 __global__ __launch_bounds__(kB) void s_update_kernel(BlasArgs A) {
     using R = typename P::real;
-    const int s = blas_slot(A, kModeActive);
-    if (s < 0) return;
     const int h = blockIdx.x * kB + threadIdx.x;
     if (h >= A.vh) return;
-    const cplx<R> al = c_of<R>(A.st[s].alpha);
-    cplx<R> r[12], v[12];
-    SpinorIO<P>::load(A.r.at(s), A.vh, h, r);
-    SpinorIO<P>::load(A.v.at(s), A.vh, h, v);
+    LAPH_FOR_SLOTS(A, kModeActive, s) {
+        const cplx<R> al = c_of<R>(A.st[s].alpha);
+        cplx<R> r[12], v[12];
+        SpinorIO<P>::load(A.r.at(s), A.vh, h, r);
+        SpinorIO<P>::load(A.v.at(s), A.vh, h, v);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) r[c] = r[c] - al * v[c];
-    SpinorIO<P>::store(A.r.at(s), A.vh, h, r);
+        for (int c = 0; c < 12; ++c) r[c] = r[c] - al * v[c];
+        SpinorIO<P>::store(A.r.at(s), A.vh, h, r);
+    }
 }
 
 // x_lo += alpha p + omega s;  r = s - omega t;  partials <r^, r>, |r|^2
@@ -95,60 +107,60 @@ template <class P, class PX>
 __global__ __launch_bounds__(kB) void xr_update_kernel(BlasArgs A) {
     using R = typename P::real;
     using RX = typename PX::real;
-    const int s = blas_slot(A, kModeActive);
-    if (s < 0) return;
     const int h = blockIdx.x * kB + threadIdx.x;
-    double part[3] = {0, 0, 0};
-    if (h < A.vh) {
-        const cplx<R> al = c_of<R>(A.st[s].alpha), om = c_of<R>(A.st[s].omega);
-        cplx<R> p[12], r[12], t[12], rh[12];
-        cplx<RX> x[12];
-        SpinorIO<P>::load(A.p.at(s), A.vh, h, p);
-        SpinorIO<P>::load(A.r.at(s), A.vh, h, r);
-        SpinorIO<P>::load(A.t.at(s), A.vh, h, t);
-        SpinorIO<PX>::load(A.x.at(s), A.vh, h, x);
+    LAPH_FOR_SLOTS(A, kModeActive, s) {
+        double part[3] = {0, 0, 0};
+        if (h < A.vh) {
+            const cplx<R> al = c_of<R>(A.st[s].alpha), om = c_of<R>(A.st[s].omega);
+            cplx<R> p[12], r[12], t[12], rh[12];
+            cplx<RX> x[12];
+            SpinorIO<P>::load(A.p.at(s), A.vh, h, p);
+            SpinorIO<P>::load(A.r.at(s), A.vh, h, r);
+            SpinorIO<P>::load(A.t.at(s), A.vh, h, t);
+            SpinorIO<PX>::load(A.x.at(s), A.vh, h, x);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            cplx<R> dx = al * p[c] + om * r[c];
-            x[c] = x[c] + cplx<RX>{RX(dx.re), RX(dx.im)};
-            r[c] = r[c] - om * t[c];
-        }
-        SpinorIO<PX>::store(A.x.at(s), A.vh, h, x);
-        SpinorIO<P>::store(A.r.at(s), A.vh, h, r);
-        SpinorIO<P>::load(A.rh.at(s), A.vh, h, rh);
-        cplx<R> d = {R(0), R(0)};
-        R n2 = R(0);
+            for (int c = 0; c < 12; ++c) {
+                cplx<R> dx = al * p[c] + om * r[c];
+                x[c] = x[c] + cplx<RX>{RX(dx.re), RX(dx.im)};
+                r[c] = r[c] - om * t[c];
+            }
+            SpinorIO<PX>::store(A.x.at(s), A.vh, h, x);
+            SpinorIO<P>::store(A.r.at(s), A.vh, h, r);
+            SpinorIO<P>::load(A.rh.at(s), A.vh, h, rh);
+            cplx<R> d = {R(0), R(0)};
+            R n2 = R(0);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            cmac_conj(d, rh[c], r[c]);
-            n2 += r[c].re * r[c].re + r[c].im * r[c].im;
+            for (int c = 0; c < 12; ++c) {
+                cmac_conj(d, rh[c], r[c]);
+                n2 += r[c].re * r[c].re + r[c].im * r[c].im;
+            }
+            part[0] = d.re;
+            part[1] = d.im;
+            part[2] = n2;
         }
-        part[0] = d.re;
-        part[1] = d.im;
-        part[2] = n2;
+        reduce_store(part, 3, A.partials + (size_t)s * 3 * A.pstride + blockIdx.x, A.pstride);
     }
-    reduce_store(part, 3, A.partials + (size_t)s * 3 * A.pstride + blockIdx.x, A.pstride);
 }
 
 // reliable update, part 1: x64 += x_lo; x_lo = 0   (flagged slots)
 template <class PX>
 __global__ __launch_bounds__(kB) void accumulate_kernel(BlasArgs A, int mode) {
     using RX = typename PX::real;
-    const int s = blas_slot(A, mode);
-    if (s < 0) return;
     const int h = blockIdx.x * kB + threadIdx.x;
     if (h >= A.vh) return;
-    cplx<RX> x[12];
-    cplx<double> y[12];
-    SpinorIO<PX>::load(A.x.at(s), A.vh, h, x);
-    SpinorIO<F64>::load(A.x64.at(s), A.vh, h, y);
+    LAPH_FOR_SLOTS(A, mode, s) {
+        cplx<RX> x[12];
+        cplx<double> y[12];
+        SpinorIO<PX>::load(A.x.at(s), A.vh, h, x);
+        SpinorIO<F64>::load(A.x64.at(s), A.vh, h, y);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-        y[c] = y[c] + cplx<double>{(double)x[c].re, (double)x[c].im};
-        x[c] = {RX(0), RX(0)};
+        for (int c = 0; c < 12; ++c) {
+            y[c] = y[c] + cplx<double>{(double)x[c].re, (double)x[c].im};
+            x[c] = {RX(0), RX(0)};
+        }
+        SpinorIO<F64>::store(A.x64.at(s), A.vh, h, y);
+        SpinorIO<PX>::store(A.x.at(s), A.vh, h, x);
     }
-    SpinorIO<F64>::store(A.x64.at(s), A.vh, h, y);
-    SpinorIO<PX>::store(A.x.at(s), A.vh, h, x);
 }
 
 // r = lo(r64); restart (flag 2) or init: r^ = r; init also zeroes x_lo.
@@ -156,77 +168,120 @@ __global__ __launch_bounds__(kB) void accumulate_kernel(BlasArgs A, int mode) {
 template <class P, class PX>
 __global__ __launch_bounds__(kB) void lower_kernel(BlasArgs A, int mode, int init) {
     using R = typename P::real;
-    const int s = blas_slot(A, mode);
-    if (s < 0) return;
     const int h = blockIdx.x * kB + threadIdx.x;
-    double part[3] = {0, 0, 0};
-    if (h < A.vh) {
-        cplx<double> y[12];
-        SpinorIO<F64>::load(A.r64.at(s), A.vh, h, y);
-        cplx<R> r[12], rh[12];
+    LAPH_FOR_SLOTS(A, mode, s) {
+        double part[3] = {0, 0, 0};
+        if (h < A.vh) {
+            cplx<double> y[12];
+            SpinorIO<F64>::load(A.r64.at(s), A.vh, h, y);
+            cplx<R> r[12], rh[12];
 #pragma unroll
-        for (int c = 0; c < 12; ++c) r[c] = {R(y[c].re), R(y[c].im)};
-        SpinorIO<P>::store(A.r.at(s), A.vh, h, r);
-        // work with the stored (rounded) values so r^ and r agree exactly
-        SpinorIO<P>::load(A.r.at(s), A.vh, h, r);
-        const bool reset = init || A.st[s].flag == 2;
-        if (reset) {
-            SpinorIO<P>::store(A.rh.at(s), A.vh, h, r);
-            SpinorIO<P>::load(A.rh.at(s), A.vh, h, rh);
-        } else {
-            SpinorIO<P>::load(A.rh.at(s), A.vh, h, rh);
-        }
-        if (init) {
-            cplx<typename PX::real> z[12];
+            for (int c = 0; c < 12; ++c) r[c] = {R(y[c].re), R(y[c].im)};
+            SpinorIO<P>::store(A.r.at(s), A.vh, h, r);
+            // work with the stored (rounded) values so r^ and r agree exactly
+            SpinorIO<P>::load(A.r.at(s), A.vh, h, r);
+            const bool reset = init || A.st[s].flag == 2;
+            if (reset) {
+                SpinorIO<P>::store(A.rh.at(s), A.vh, h, r);
+                SpinorIO<P>::load(A.rh.at(s), A.vh, h, rh);
+            } else {
+                SpinorIO<P>::load(A.rh.at(s), A.vh, h, rh);
+            }
+            if (init) {
+                cplx<typename PX::real> z[12];
 #pragma unroll
-            for (int c = 0; c < 12; ++c) z[c] = {0, 0};
-            SpinorIO<PX>::store(A.x.at(s), A.vh, h, z);
-        }
-        cplx<R> d = {R(0), R(0)};
-        R n2 = R(0);
+                for (int c = 0; c < 12; ++c) z[c] = {0, 0};
+                SpinorIO<PX>::store(A.x.at(s), A.vh, h, z);
+            }
+            cplx<R> d = {R(0), R(0)};
+            R n2 = R(0);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            cmac_conj(d, rh[c], r[c]);
-            n2 += r[c].re * r[c].re + r[c].im * r[c].im;
+            for (int c = 0; c < 12; ++c) {
+                cmac_conj(d, rh[c], r[c]);
+                n2 += r[c].re * r[c].re + r[c].im * r[c].im;
+            }
+            part[0] = d.re;
+            part[1] = d.im;
+            part[2] = n2;
         }
-        part[0] = d.re;
-        part[1] = d.im;
-        part[2] = n2;
+        reduce_store(part, 3, A.partials + (size_t)s * 3 * A.pstride + blockIdx.x, A.pstride);
     }
-    reduce_store(part, 3, A.partials + (size_t)s * 3 * A.pstride + blockIdx.x, A.pstride);
 }
 
 // |v|^2 of one or two FP64 half-vectors per slot (partials q = 0)
 __global__ __launch_bounds__(kB) void norm2_kernel(BlasArgs A, Operand v1, Operand v2, int mode) {
-    const int s = blas_slot(A, mode);
-    if (s < 0) return;
     const int h = blockIdx.x * kB + threadIdx.x;
-    double part[1] = {0};
-    if (h < A.vh) {
-        cplx<double> y[12];
-        SpinorIO<F64>::load(v1.at(s), A.vh, h, y);
-        double n2 = 0;
-#pragma unroll
-        for (int c = 0; c < 12; ++c) n2 += y[c].re * y[c].re + y[c].im * y[c].im;
-        if (v2.base) {
-            SpinorIO<F64>::load(v2.at(s), A.vh, h, y);
+    LAPH_FOR_SLOTS(A, mode, s) {
+        double part[1] = {0};
+        if (h < A.vh) {
+            cplx<double> y[12];
+            SpinorIO<F64>::load(v1.at(s), A.vh, h, y);
+            double n2 = 0;
 #pragma unroll
             for (int c = 0; c < 12; ++c) n2 += y[c].re * y[c].re + y[c].im * y[c].im;
+            if (v2.base) {
+                SpinorIO<F64>::load(v2.at(s), A.vh, h, y);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) n2 += y[c].re * y[c].re + y[c].im * y[c].im;
+            }
+            part[0] = n2;
         }
-        part[0] = n2;
+        reduce_store(part, 1, A.partials + (size_t)s * 3 * A.pstride + blockIdx.x, A.pstride);
     }
-    reduce_store(part, 1, A.partials + (size_t)s * 3 * A.pstride + blockIdx.x, A.pstride);
 }
 
 // dst = src (FP64 half-vectors) per slot
 __global__ __launch_bounds__(kB) void copy64_kernel(BlasArgs A, Operand dst, Operand src, int mode) {
-    const int s = blas_slot(A, mode);
-    if (s < 0) return;
     const int h = blockIdx.x * kB + threadIdx.x;
     if (h >= A.vh) return;
-    cplx<double> y[12];
-    SpinorIO<F64>::load(src.at(s), A.vh, h, y);
-    SpinorIO<F64>::store(dst.at(s), A.vh, h, y);
+    LAPH_FOR_SLOTS(A, mode, s) {
+        cplx<double> y[12];
+        SpinorIO<F64>::load(src.at(s), A.vh, h, y);
+        SpinorIO<F64>::store(dst.at(s), A.vh, h, y);
+    }
+}
+
+// Flagged slots after the rho finalize: the list of slots that take a reliable
+// update this iteration, and FP64 register tiles of them (tiles never mix
+// masses).  One block; entries of the static FP64 tile table (already grouped
+// by mass) are tested in parallel, then packed in table order by one thread.
+__global__ __launch_bounds__(kB) void flag_tiles_kernel(FlagArgs A) {
+    __shared__ int ks[kB], km[kB];
+    const int total = *A.ntiles * A.nr;
+    int cur = -1, fill = 0, cm = -1, nf = 0;   // packing state (thread 0)
+    for (int base = 0; base < total; base += kB) {
+        const int e = base + (int)threadIdx.x;
+        int s = -1, m = 0;
+        if (e < total) {
+            s = A.tile_slots[e];
+            m = A.tile_mass[e / A.nr];
+            if (s >= 0 && !(A.st[s].status == LAPH_RHS_ACTIVE && A.st[s].flag != 0)) s = -1;
+        }
+        ks[threadIdx.x] = s;
+        km[threadIdx.x] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int n = min(kB, total - base);
+            for (int i = 0; i < n; ++i) {
+                const int si = ks[i];
+                if (si < 0) continue;
+                if (cur < 0 || fill == A.nr || km[i] != cm) {
+                    ++cur;
+                    for (int k = 0; k < A.nr; ++k) A.out_slots[cur * A.nr + k] = -1;
+                    A.out_mass[cur] = km[i];
+                    cm = km[i];
+                    fill = 0;
+                }
+                A.out_slots[cur * A.nr + fill++] = si;
+                A.flist[nf++] = si;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *A.out_ntiles = cur + 1;
+        *A.nflist = nf;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -397,29 +452,40 @@ laph_status blas_xr_update(const Ctx &c, const BlasArgs &a, int prec) {
         return check_launch("xr_update_kernel");
     });
 }
+// grid rows: one per list entry, or a quarter of them in flagged mode (a block
+// then walks several flagged slots; the flagged count is known only on the device)
+static dim3 blas_grid(const BlasArgs &a, int mode) {
+    const int rows = mode == kModeFlagged ? (a.nlist_max + 3) / 4 : a.nlist_max;
+    return dim3(a.nsb, rows > 0 ? rows : 1);
+}
+
 laph_status blas_accumulate(const Ctx &c, const BlasArgs &a, int prec, int mode) {
-    dim3 grid(a.nsb, a.nlist_max);
+    dim3 grid = blas_grid(a, mode);
     return dispatch_prec(prec, [&](auto, auto PX) {
         hipLaunchKernelGGL(accumulate_kernel<decltype(PX)>, grid, dim3(kB), 0, c.stream, a, mode);
         return check_launch("accumulate_kernel");
     });
 }
 laph_status blas_lower(const Ctx &c, const BlasArgs &a, int prec, int mode, int init) {
-    dim3 grid(a.nsb, a.nlist_max);
+    dim3 grid = blas_grid(a, mode);
     return dispatch_prec(prec, [&](auto P, auto PX) {
         hipLaunchKernelGGL((lower_kernel<decltype(P), decltype(PX)>), grid, dim3(kB), 0, c.stream, a, mode, init);
         return check_launch("lower_kernel");
     });
 }
 laph_status blas_norm2(const Ctx &c, const BlasArgs &a, Operand v1, Operand v2, int mode) {
-    dim3 grid(a.nsb, a.nlist_max);
+    dim3 grid = blas_grid(a, mode);
     hipLaunchKernelGGL(norm2_kernel, grid, dim3(kB), 0, c.stream, a, v1, v2, mode);
     return check_launch("norm2_kernel");
 }
 laph_status blas_copy64(const Ctx &c, const BlasArgs &a, Operand dst, Operand src, int mode) {
-    dim3 grid(a.nsb, a.nlist_max);
+    dim3 grid = blas_grid(a, mode);
     hipLaunchKernelGGL(copy64_kernel, grid, dim3(kB), 0, c.stream, a, dst, src, mode);
     return check_launch("copy64_kernel");
+}
+laph_status blas_flag_tiles(const Ctx &c, const FlagArgs &f) {
+    hipLaunchKernelGGL(flag_tiles_kernel, dim3(1), dim3(kB), 0, c.stream, f);
+    return check_launch("flag_tiles_kernel");
 }
 laph_status blas_finalize(const Ctx &c, const FinArgs &f, int what) {
     hipLaunchKernelGGL(finalize_kernel, dim3(f.nlist_max), dim3(64), 0, c.stream, f, what);

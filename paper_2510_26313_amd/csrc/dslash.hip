@@ -35,6 +35,8 @@ laph_status launch_stage(const Ctx &c, const StageSpec &s) {
     a.nsb = stage_nsb(c, s.form);
     a.pstride = s.pstride;
     a.site_major = s.site_major;
+    a.grid_cap = s.grid_cap;
+    a.one = 1.0f;
     a.st = s.slots;
     a.partials = s.partials;
     if (a.ntiles_max <= 0) return LAPH_OK;

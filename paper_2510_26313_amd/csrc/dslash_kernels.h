@@ -47,22 +47,41 @@ struct StageArgs {
     int site_major;
     const SlotState *st;
     double *partials;
+    float one;   // 1.0f, opaque to the compiler (keeps FP16N projections as mixed-precision FMAs)
+    int grid_cap;   // launch only: at most this many workgroups (0: one per item)
 };
 
-// Workgroup -> (site block, tile), after the XCD remap.  Tile-major: the tiles of
-// one site block are consecutive, so they share its links in one L2.  Site-major:
-// each tile sweeps all site blocks before the next (each XCD takes whole tiles),
-// so neighbouring site blocks -- whose spinors are each other's hop inputs --
-// run together on one XCD and share its L2.
-__device__ __forceinline__ void stage_block(int site_major, int nsb, int ntiles_max, int &sb, int &tile) {
-    const int L = xcd_logical_block();
+// Work items of a stage launch are (site block, tile) pairs of the live tiles:
+// W = ntiles * nsb with ntiles read on the device.  The items are split into 8
+// contiguous ranges, one per XCD (workgroups are dispatched round-robin over the
+// XCDs, so workgroup b runs on XCD b % 8), and the workgroups of an XCD walk its
+// range with a stride of gridDim.x / 8.  A grid of W_max workgroups takes at most
+// one item each; a smaller grid (launches whose live tile count is known only on
+// the device) loops, so no workgroup of a retired or unflagged tile is scheduled.
+// Site-major: each tile sweeps all site blocks (neighbouring site blocks, whose
+// spinors are each other's hop inputs, share an XCD's L2); tile-major: the tiles
+// of one site block are consecutive (they share its links in L2).
+__device__ __forceinline__ void stage_item_range(int W, int &first, int &end, int &step) {
+    const int per = gridDim.x >> 3;   // launches pad the grid to a multiple of 8
+    const int xcd = blockIdx.x & 7, k = blockIdx.x >> 3;
+    const int chunk = (W + 7) >> 3;
+    first = xcd * chunk + k;
+    end = min(W, (xcd + 1) * chunk);
+    step = per;
+}
+__device__ __forceinline__ void stage_item(int w, int site_major, int nsb, int ntiles, int &sb, int &tile) {
     if (site_major) {
-        tile = L / nsb;
-        sb = L - tile * nsb;
+        tile = w / nsb;
+        sb = w - tile * nsb;
     } else {
-        sb = L / ntiles_max;
-        tile = L - sb * ntiles_max;
+        sb = w / ntiles;
+        tile = w - sb * ntiles;
     }
+}
+// grid of a stage launch: every item, or at most cap workgroups (cap > 0)
+inline int stage_grid(int items_max, int cap) {
+    int n = cap > 0 && cap < items_max ? cap : items_max;
+    return pad8(n > 0 ? n : 1);
 }
 
 // --- spin projection: (1 + S gamma_mu) psi = (h0, h1, row2(h), row3(h)) --------
@@ -97,46 +116,105 @@ __device__ __forceinline__ void spin_project(const cplx<R> (&p)[12], cplx<R> (&h
     }
 }
 
-template <int MU, int S, class R>
-__device__ __forceinline__ void spin_accumulate(cplx<R> (&acc)[12], const cplx<R> (&u)[6]) {
+// The same projection for an FP16N neighbour, computed from its binary16 codes:
+// x + c y with c in {1, -1, i, -i} per real part as one mixed-precision fused
+// multiply-add (binary16 inputs, binary32 result; exact inputs, one rounding --
+// the value of converting both and adding).  `one` is 1.0f.
+template <int C>
+__device__ __forceinline__ cplx<float> proj_mix(_Float16 xr, _Float16 xi, _Float16 yr, _Float16 yi, float one) {
+    if (C == 1) return {fmaf((float)yr, one, (float)xr), fmaf((float)yi, one, (float)xi)};
+    if (C == -1) return {fmaf((float)yr, -one, (float)xr), fmaf((float)yi, -one, (float)xi)};
+    if (C == 2) return {fmaf((float)yi, -one, (float)xr), fmaf((float)yr, one, (float)xi)};   // + i y
+    return {fmaf((float)yi, one, (float)xr), fmaf((float)yr, -one, (float)xi)};               // - i y
+}
+
+template <int MU, int S>
+__device__ __forceinline__ void spin_project_codes(const half8 (&q)[3], float one, cplx<float> (&h)[6]) {
+    // component c (= 3 spin + colour) has its real part at q[c / 4][2 (c % 4)]
+#define LAPH_Q(c) q[(c) >> 2][2 * ((c)&3)], q[(c) >> 2][2 * ((c)&3) + 1]
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        acc[a] = acc[a] + u[a];
-        acc[3 + a] = acc[3 + a] + u[3 + a];
         if (MU == 0) {
-            acc[6 + a] = acc[6 + a] - s_i<S>(u[3 + a]);
-            acc[9 + a] = acc[9 + a] - s_i<S>(u[a]);
+            h[a] = proj_mix<2 * S>(LAPH_Q(a), LAPH_Q(9 + a), one);
+            h[3 + a] = proj_mix<2 * S>(LAPH_Q(3 + a), LAPH_Q(6 + a), one);
         } else if (MU == 1) {
-            acc[6 + a] = acc[6 + a] + s_1<S>(u[3 + a]);
-            acc[9 + a] = acc[9 + a] - s_1<S>(u[a]);
+            h[a] = proj_mix<-S>(LAPH_Q(a), LAPH_Q(9 + a), one);
+            h[3 + a] = proj_mix<S>(LAPH_Q(3 + a), LAPH_Q(6 + a), one);
         } else if (MU == 2) {
-            acc[6 + a] = acc[6 + a] - s_i<S>(u[a]);
-            acc[9 + a] = acc[9 + a] + s_i<S>(u[3 + a]);
+            h[a] = proj_mix<2 * S>(LAPH_Q(a), LAPH_Q(6 + a), one);
+            h[3 + a] = proj_mix<-2 * S>(LAPH_Q(3 + a), LAPH_Q(9 + a), one);
         } else {
-            acc[6 + a] = acc[6 + a] + s_1<S>(u[a]);
-            acc[9 + a] = acc[9 + a] + s_1<S>(u[3 + a]);
+            h[a] = proj_mix<S>(LAPH_Q(a), LAPH_Q(6 + a), one);
+            h[3 + a] = proj_mix<S>(LAPH_Q(3 + a), LAPH_Q(9 + a), one);
+        }
+    }
+#undef LAPH_Q
+}
+
+// Load and project a neighbour half-spinor; returns the factor still to apply
+// (the FP16N site norm, 1 otherwise).
+template <class P, int MU, int S>
+__device__ __forceinline__ typename P::real load_project(const char *hv, int vh, int h, float one,
+                                                         cplx<typename P::real> (&hs)[6]) {
+    using R = typename P::real;
+    if constexpr (SpinorIO<P>::kNorm) {
+        half8 q[3];
+        float n;
+        SpinorIO<P>::load_codes(hv, vh, h, q, n);
+        spin_project_codes<MU, S>(q, one, hs);
+        return n;
+    } else {
+        cplx<R> psi[12];
+        R n;
+        SpinorIO<P>::load_unscaled(hv, vh, h, psi, n);
+        spin_project<MU, S>(psi, hs);
+        return R(1);
+    }
+}
+
+// acc += sc * (u, row2(u), row3(u)): the lower spin components of (1 + S gamma_mu)
+// follow from the upper ones; the scale sc (FP16 site norm, time-boundary sign)
+// is folded into the fused multiply-adds.
+template <int MU, int S, class R>
+__device__ __forceinline__ void spin_accumulate(cplx<R> (&acc)[12], const cplx<R> (&u)[6], R sc) {
+    // S * i * z scaled: (-S sc z.im, S sc z.re); S * z scaled: (S sc z.re, S sc z.im)
+    const R ss = S > 0 ? sc : -sc;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        acc[a] = caxpy(sc, u[a], acc[a]);
+        acc[3 + a] = caxpy(sc, u[3 + a], acc[3 + a]);
+        if (MU == 0) {   // lower = -S i (u1, u0)
+            acc[6 + a] = {ffma(ss, u[3 + a].im, acc[6 + a].re), ffma(-ss, u[3 + a].re, acc[6 + a].im)};
+            acc[9 + a] = {ffma(ss, u[a].im, acc[9 + a].re), ffma(-ss, u[a].re, acc[9 + a].im)};
+        } else if (MU == 1) {   // lower = (S u1, -S u0)
+            acc[6 + a] = caxpy(ss, u[3 + a], acc[6 + a]);
+            acc[9 + a] = caxpy(-ss, u[a], acc[9 + a]);
+        } else if (MU == 2) {   // lower = (-S i u0, S i u1)
+            acc[6 + a] = {ffma(ss, u[a].im, acc[6 + a].re), ffma(-ss, u[a].re, acc[6 + a].im)};
+            acc[9 + a] = {ffma(-ss, u[3 + a].im, acc[9 + a].re), ffma(ss, u[3 + a].re, acc[9 + a].im)};
+        } else {   // lower = (S u0, S u1)
+            acc[6 + a] = caxpy(ss, u[a], acc[6 + a]);
+            acc[9 + a] = caxpy(ss, u[3 + a], acc[9 + a]);
         }
     }
 }
 
-// u = L h  (ADJ: L^dagger h) for both colour vectors of the half spinor, times
-// `scale` when SCALE (the FP16 site norm and/or the time-boundary sign)
-template <bool ADJ, bool SCALE, class R>
-__device__ __forceinline__ void colour_mul(const cplx<R> (&L)[9], const cplx<R> (&h)[6], R scale,
-                                           cplx<R> (&u)[6]) {
+// u = L h  (ADJ: L^dagger h) for both colour vectors of the half spinor
+template <bool ADJ, class R>
+__device__ __forceinline__ void colour_mul(const cplx<R> (&L)[9], const cplx<R> (&h)[6], cplx<R> (&u)[6]) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            cplx<R> s = {R(0), R(0)};
+            cplx<R> s = ADJ ? cmul1_conj(L[a], h[3 * j]) : cmul1(L[a * 3], h[3 * j]);
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
+            for (int b = 1; b < 3; ++b) {
                 if (ADJ)
                     cmac_conj(s, L[b * 3 + a], h[3 * j + b]);
                 else
                     cmac(s, L[a * 3 + b], h[3 * j + b]);
             }
-            u[3 * j + a] = SCALE ? scale * s : s;
+            u[3 * j + a] = s;
         }
     }
 }
@@ -172,15 +250,10 @@ __device__ __forceinline__ void hop_dir(const StageArgs &A, int p, int h, const 
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         if (slots[r] < 0) continue;
-        cplx<R> psi[12], hs[6], u[6];
-        R nrm;
-        SpinorIO<P>::load_unscaled(A.in.at(slots[r]), g.vh, hn, psi, nrm);
-        spin_project<MU, S>(psi, hs);
-        if (SpinorIO<P>::kNorm || MU == 3)
-            colour_mul<!FWD, true>(L, hs, eta * nrm, u);
-        else
-            colour_mul<!FWD, false>(L, hs, R(1), u);
-        spin_accumulate<MU, S>(acc[r], u);
+        cplx<R> hs[6], u[6];
+        const R nrm = load_project<P, MU, S>(A.in.at(slots[r]), g.vh, hn, A.one, hs);
+        colour_mul<!FWD>(L, hs, u);
+        spin_accumulate<MU, S>(acc[r], u, SpinorIO<P>::kNorm ? eta * nrm : eta);
     }
 }
 
@@ -225,12 +298,10 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NV], double *dst,
     }
 }
 
+// One work item: NR right-hand sides of a tile on kBlock sites.
 template <class P, int NR, bool DAG, bool CLOVER, bool PRE, int POST, int RED, bool FLAGGED>
-__global__ __launch_bounds__(kBlock) LAPH_STAGE_OCCUPANCY void stage_kernel(StageArgs A) {
+__device__ __forceinline__ void stage_body(const StageArgs &A, int sb, int tile) {
     using R = typename P::real;
-    int sb, tile;
-    stage_block(A.site_major, A.nsb, A.ntiles_max, sb, tile);
-    if (sb >= A.nsb || tile >= *A.ntiles) return;
     int slots[NR];
     bool any = false;
 #pragma unroll
@@ -352,13 +423,25 @@ __global__ __launch_bounds__(kBlock) LAPH_STAGE_OCCUPANCY void stage_kernel(Stag
     }
 }
 
+template <class P, int NR, bool DAG, bool CLOVER, bool PRE, int POST, int RED, bool FLAGGED>
+__global__ __launch_bounds__(kBlock) LAPH_STAGE_OCCUPANCY void stage_kernel(StageArgs A) {
+    const int nt = *A.ntiles;
+    int first, end, step;
+    stage_item_range(nt * A.nsb, first, end, step);
+    for (int w = first; w < end; w += step) {
+        int sb, tile;
+        stage_item(w, A.site_major, A.nsb, nt, sb, tile);
+        stage_body<P, NR, DAG, CLOVER, PRE, POST, RED, FLAGGED>(A, sb, tile);
+    }
+}
+
 
 // ---------------------------------------------------------------------------
 // dispatch (instantiated per precision in dslash_f64/f32/f16.hip)
 // ---------------------------------------------------------------------------
 template <class P, int NR, bool DAG, bool CLOVER, bool PRE, int POST, int RED, bool FL>
 inline void launch_t(const StageArgs &a, hipStream_t st) {
-    const int nblk = pad8(a.nsb * a.ntiles_max);
+    const int nblk = stage_grid(a.nsb * a.ntiles_max, a.grid_cap);
     hipLaunchKernelGGL((stage_kernel<P, NR, DAG, CLOVER, PRE, POST, RED, FL>), dim3(nblk), dim3(kBlock), 0, st, a);
 }
 

@@ -24,31 +24,27 @@ constexpr int kLdsSites = 64;
 // and scaled by its norm after the colour product.
 template <class P, int MU, bool DAG, bool FWD>
 __device__ __forceinline__ void lds_hop(const char *src, int vh, const typename P::real (&lnk)[8][18][kLdsSites],
-                                        const int (&nbr)[8][kLdsSites], int lane,
+                                        const int (&nbr)[8][kLdsSites], int lane, float one,
                                         cplx<typename P::real> (&acc)[12]) {
     using R = typename P::real;
     constexpr int hop = 2 * MU + (FWD ? 0 : 1);
     constexpr int S = (FWD != DAG) ? -1 : 1;
     const int hn = nbr[hop][lane];
-    cplx<R> psi[12], hs[6], u[6], L[9];
-    R nrm;
-    SpinorIO<P>::load_unscaled(src, vh, hn, psi, nrm);
-    spin_project<MU, S>(psi, hs);
+    cplx<R> hs[6], u[6], L[9];
+    const R nrm = load_project<P, MU, S>(src, vh, hn, one, hs);
 #pragma unroll
     for (int k = 0; k < 9; ++k) L[k] = {lnk[hop][2 * k][lane], lnk[hop][2 * k + 1][lane]};
-    colour_mul<false, SpinorIO<P>::kNorm>(L, hs, nrm, u);
-    spin_accumulate<MU, S>(acc, u);
+    colour_mul<false>(L, hs, u);
+    spin_accumulate<MU, S>(acc, u, nrm);
 }
 
+// One work item: the 4 * RW right-hand sides of a tile on kLdsSites sites.
 template <class P, int RW, bool DAG, bool CLOVER, bool PRE, int POST, int RED>
-__global__ __launch_bounds__(256) void stage_lds_kernel(StageArgs A) {
+__device__ __forceinline__ void stage_lds_body(const StageArgs &A, int sb, int tile) {
     using R = typename P::real;
     constexpr int NT = 4 * RW;
     __shared__ R lnk[8][18][kLdsSites];
     __shared__ int nbr[8][kLdsSites];
-    int sb, tile;
-    stage_block(A.site_major, A.nsb, A.ntiles_max, sb, tile);
-    if (sb >= A.nsb || tile >= *A.ntiles) return;
     const Geom &g = A.g;
     const int p = A.out_parity;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -118,21 +114,21 @@ __global__ __launch_bounds__(256) void stage_lds_kernel(StageArgs A) {
 #pragma unroll
             for (int c = 0; c < 12; ++c) acc[c] = {R(0), R(0)};
             const char *src = A.in.at(slot);
-            lds_hop<P, 0, DAG, true>(src, g.vh, lnk, nbr, lane, acc);
+            lds_hop<P, 0, DAG, true>(src, g.vh, lnk, nbr, lane, A.one, acc);
             hop_fence();
-            lds_hop<P, 0, DAG, false>(src, g.vh, lnk, nbr, lane, acc);
+            lds_hop<P, 0, DAG, false>(src, g.vh, lnk, nbr, lane, A.one, acc);
             hop_fence();
-            lds_hop<P, 1, DAG, true>(src, g.vh, lnk, nbr, lane, acc);
+            lds_hop<P, 1, DAG, true>(src, g.vh, lnk, nbr, lane, A.one, acc);
             hop_fence();
-            lds_hop<P, 1, DAG, false>(src, g.vh, lnk, nbr, lane, acc);
+            lds_hop<P, 1, DAG, false>(src, g.vh, lnk, nbr, lane, A.one, acc);
             hop_fence();
-            lds_hop<P, 2, DAG, true>(src, g.vh, lnk, nbr, lane, acc);
+            lds_hop<P, 2, DAG, true>(src, g.vh, lnk, nbr, lane, A.one, acc);
             hop_fence();
-            lds_hop<P, 2, DAG, false>(src, g.vh, lnk, nbr, lane, acc);
+            lds_hop<P, 2, DAG, false>(src, g.vh, lnk, nbr, lane, A.one, acc);
             hop_fence();
-            lds_hop<P, 3, DAG, true>(src, g.vh, lnk, nbr, lane, acc);
+            lds_hop<P, 3, DAG, true>(src, g.vh, lnk, nbr, lane, A.one, acc);
             hop_fence();
-            lds_hop<P, 3, DAG, false>(src, g.vh, lnk, nbr, lane, acc);
+            lds_hop<P, 3, DAG, false>(src, g.vh, lnk, nbr, lane, A.one, acc);
             hop_fence();
             if (PRE) {
                 cplx<R> zz[12];
@@ -211,12 +207,25 @@ __global__ __launch_bounds__(256) void stage_lds_kernel(StageArgs A) {
     }
 }
 
+template <class P, int RW, bool DAG, bool CLOVER, bool PRE, int POST, int RED>
+__global__ __launch_bounds__(256) void stage_lds_kernel(StageArgs A) {
+    const int nt = *A.ntiles;
+    int first, end, step;
+    stage_item_range(nt * A.nsb, first, end, step);
+    for (int w = first; w < end; w += step) {
+        int sb, tile;
+        stage_item(w, A.site_major, A.nsb, nt, sb, tile);
+        stage_lds_body<P, RW, DAG, CLOVER, PRE, POST, RED>(A, sb, tile);
+        __syncthreads();   // the next item stages its links in the same LDS
+    }
+}
+
 // ---------------------------------------------------------------------------
 // dispatch (FP32 / FP16N; instantiated in dslash_f32.hip and dslash_f16.hip)
 // ---------------------------------------------------------------------------
 template <class P, int RW, bool DAG, bool CLOVER, bool PRE, int POST, int RED>
 inline void launch_lds_t(const StageArgs &a, hipStream_t st) {
-    const int nblk = pad8(a.nsb * a.ntiles_max);
+    const int nblk = stage_grid(a.nsb * a.ntiles_max, a.grid_cap);
     hipLaunchKernelGGL((stage_lds_kernel<P, RW, DAG, CLOVER, PRE, POST, RED>), dim3(nblk), dim3(256), 0, st, a);
 }
 

@@ -19,6 +19,19 @@ struct BlasArgs {
     double *partials = nullptr;  // [slot][3][pstride]
     Operand r, rh, p, v, t, x;   // inner-precision vectors (x: the x_lo precision)
     Operand x64, r64;            // FP64 solution and residual
+    const int *flist = nullptr;  // flagged mode: slots taking a reliable update
+    const int *nflist = nullptr; // device scalar: entries of flist
+};
+
+// Input / output of the flagged-slot compaction (blas_flag_tiles).
+struct FlagArgs {
+    const int *tile_slots = nullptr;   // static FP64 tiles [ntiles][nr], grouped by mass
+    const int *tile_mass = nullptr;
+    const int *ntiles = nullptr;       // device scalar
+    int nr = 1;
+    const SlotState *st = nullptr;
+    int *out_slots = nullptr, *out_mass = nullptr, *out_ntiles = nullptr;   // flagged tiles
+    int *flist = nullptr, *nflist = nullptr;                                // flagged slots
 };
 
 struct FinArgs {
@@ -39,6 +52,7 @@ laph_status blas_accumulate(const Ctx &c, const BlasArgs &a, int prec, int mode)
 laph_status blas_lower(const Ctx &c, const BlasArgs &a, int prec, int mode, int init);
 laph_status blas_norm2(const Ctx &c, const BlasArgs &a, Operand v1, Operand v2, int mode);
 laph_status blas_copy64(const Ctx &c, const BlasArgs &a, Operand dst, Operand src, int mode);
+laph_status blas_flag_tiles(const Ctx &c, const FlagArgs &f);
 laph_status blas_finalize(const Ctx &c, const FinArgs &f, int what);
 
 }  // namespace laph

@@ -125,7 +125,8 @@ struct StageSpec {
     Operand in, out, y, y2, z, w;
     double a = 0, a2 = 0, b = 1, c = 0;
     Tiles tiles;
-    int site_major = 0;                 // 1: each tile sweeps all site blocks (see stage_block)
+    int site_major = 0;                 // 1: each tile sweeps all site blocks (see stage_item)
+    int grid_cap = 0;                   // > 0: at most this many workgroups, each walking several items
     int form = kFormRegister;           // kFormRegister: tiles.nr RHS per thread;
                                         // kFormLds: tiles.nr = 4 * RW RHS per workgroup, links in LDS
     const SlotState *slots = nullptr;   // may be null when flagged == 0

@@ -55,7 +55,15 @@ template <class R>
 __host__ __device__ __forceinline__ cplx<R> mul_i(cplx<R> a) { return {-a.im, a.re}; }
 template <class R>
 __host__ __device__ __forceinline__ cplx<R> mul_mi(cplx<R> a) { return {a.im, -a.re}; }
-// a += b * c ; a += conj(b) * c
+// fused multiply-add in the operands' precision (host and device)
+__host__ __device__ __forceinline__ float ffma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__host__ __device__ __forceinline__ double ffma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// a += b * c ; a += conj(b) * c.  Written as a sum of products rather than a
+// chain of four fused multiply-adds: the chained form lets the scheduler keep
+// more independent chains in flight and roughly doubles the stencil kernels'
+// VGPRs (fewer waves to hide the neighbour gathers), which costs more than the
+// extra adds.
 template <class R>
 __host__ __device__ __forceinline__ void cmac(cplx<R> &a, cplx<R> b, cplx<R> c) {
     a.re += b.re * c.re - b.im * c.im;
@@ -65,6 +73,20 @@ template <class R>
 __host__ __device__ __forceinline__ void cmac_conj(cplx<R> &a, cplx<R> b, cplx<R> c) {
     a.re += b.re * c.re + b.im * c.im;
     a.im += b.re * c.im - b.im * c.re;
+}
+// b * c and conj(b) * c (one multiply and three fused multiply-adds)
+template <class R>
+__host__ __device__ __forceinline__ cplx<R> cmul1(cplx<R> b, cplx<R> c) {
+    return {ffma(-b.im, c.im, b.re * c.re), ffma(b.im, c.re, b.re * c.im)};
+}
+template <class R>
+__host__ __device__ __forceinline__ cplx<R> cmul1_conj(cplx<R> b, cplx<R> c) {
+    return {ffma(b.im, c.im, b.re * c.re), ffma(-b.im, c.re, b.re * c.im)};
+}
+// a + s * b for real s
+template <class R>
+__host__ __device__ __forceinline__ cplx<R> caxpy(R s, cplx<R> b, cplx<R> a) {
+    return {ffma(s, b.re, a.re), ffma(s, b.im, a.im)};
 }
 
 // ---------------------------------------------------------------------------
@@ -178,6 +200,12 @@ struct SpinorIO<F32> {
 template <>
 struct SpinorIO<F16N> {
     static constexpr bool kNorm = true;
+    static __device__ __forceinline__ void load_codes(const char *hv, int vh, int h, half8 (&q)[3], float &n) {
+        const half8 *p = reinterpret_cast<const half8 *>(hv);
+        n = reinterpret_cast<const float *>(hv + (size_t)48 * vh)[h];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) q[j] = p[(size_t)j * vh + h];
+    }
     static __device__ __forceinline__ void load_unscaled(const char *hv, int vh, int h, cplx<float> (&s)[12],
                                                          float &n) {
         const half8 *p = reinterpret_cast<const half8 *>(hv);

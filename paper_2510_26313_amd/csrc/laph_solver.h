@@ -52,8 +52,9 @@ class Solver {
         double *partials = nullptr;
         int *tile_slots = nullptr, *tile_mass = nullptr;      // inner-form tiles
         int *tile64_slots = nullptr, *tile64_mass = nullptr;  // FP64 register tiles
-        int *list = nullptr, *slot_mass = nullptr;
-        int *ntiles = nullptr, *nlist = nullptr, *ntiles64 = nullptr;
+        int *tile64f_slots = nullptr, *tile64f_mass = nullptr;  // FP64 tiles of the flagged slots
+        int *list = nullptr, *slot_mass = nullptr, *flist = nullptr;
+        int *ntiles = nullptr, *nlist = nullptr, *ntiles64 = nullptr, *ntiles64f = nullptr, *nflist = nullptr;
         int *ints = nullptr;          // integer region the tables are carved from
         size_t nints = 0, nints_used = 0;
     };
@@ -77,6 +78,8 @@ class Solver {
     laph_solve_params p{};
     int ns = 0, prec = 0, form = kFormRegister, nr = 1, nr64 = 1, site_major = 0, nsb256 = 0, nsb_inner = 0,
         pstride = 0;
+    // most tiles a table can hold (tiles never mix masses): the launch grids
+    int tiles_cap = 0, tiles64_cap = 0;
     WS ws;
     std::vector<int> mass;
     std::vector<int> host_ints;
@@ -87,7 +90,7 @@ class Solver {
     void carve_tables();
     BlasArgs blas(int list_max) const;
     FinArgs fin(int list_max, int nsb = 0) const;
-    Tiles tiles(bool f64) const;
+    Tiles tiles(bool f64, bool flagged = false) const;
     laph_status upload_tables(const std::vector<int> &slots);
     laph_status download_state();
     laph_status upload_state();

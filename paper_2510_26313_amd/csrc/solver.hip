@@ -41,9 +41,9 @@ void Solver::choose_shape(const laph_solve_params &p, int ns, int &form, int &nr
     nr64 = prec == LAPH_F64 ? nr : reg_tile(ns);
 }
 
-// The integer tables are sized for the largest tile (16), so the workspace does
-// not depend on the tuned shape.
-static size_t table_ints(int ns) { return (size_t)ns * 16 + (size_t)ns * 4 + 4 * (size_t)ns + 8; }
+// The integer tables are sized for the largest tiles (16 inner, 4 FP64), so the
+// workspace does not depend on the tuned shape.
+static size_t table_ints(int ns) { return (size_t)ns * 16 + 2 * (size_t)ns * 4 + 6 * (size_t)ns + 16; }
 
 size_t Solver::layout(const Ctx &c, int ns, int prec, char *base, WS *ws) {
     const size_t h64 = c.hv(LAPH_F64), hlo = c.hv(prec), hx = c.hv(prec == LAPH_F64 ? LAPH_F64 : LAPH_F32);
@@ -100,7 +100,13 @@ void Solver::carve_tables() {
     ws.ntiles = ws.slot_mass + ns;
     ws.nlist = ws.ntiles + 1;
     ws.ntiles64 = ws.ntiles + 2;
-    ws.nints_used = (size_t)(ws.ntiles64 + 1 - ints);
+    // device-built tables (not uploaded): flagged FP64 tiles and slots
+    ws.tile64f_slots = ws.ntiles + 4;
+    ws.tile64f_mass = ws.tile64f_slots + (size_t)ns * nr64;
+    ws.flist = ws.tile64f_mass + ns;
+    ws.ntiles64f = ws.flist + ns;
+    ws.nflist = ws.ntiles64f + 1;
+    ws.nints_used = (size_t)(ws.ntiles + 3 - ints);
 }
 
 size_t solver_workspace_bytes(const Ctx &c, int nslots, const laph_solve_params &p) {
@@ -141,6 +147,10 @@ laph_status Solver::init(Ctx &ctx, int nslots, const laph_solve_params &params, 
     if (form == kFormLds && prec == LAPH_F64)
         return set_error(LAPH_ERR_INVALID, "the LDS-staged stencil form is available for FP32 and FP16N");
     carve_tables();
+    // grouping by mass adds at most one partly filled tile per extra mass
+    const int nm = std::max(1, ctx.n_mass);
+    tiles_cap = std::min(ns, (ns + nr - 1) / nr + nm - 1);
+    tiles64_cap = std::min(ns, (ns + nr64 - 1) / nr64 + nm - 1);
     nsb256 = stage_nsb(ctx, kFormRegister);
     nsb_inner = stage_nsb(ctx, form);
     pstride = partial_stride(ctx);
@@ -171,6 +181,8 @@ BlasArgs Solver::blas(int list_max) const {
     a.x = ws.x;
     a.x64 = ws.E1;
     a.r64 = ws.E2;
+    a.flist = ws.flist;
+    a.nflist = ws.nflist;
     return a;
 }
 
@@ -186,12 +198,18 @@ FinArgs Solver::fin(int list_max, int nsb) const {
     return f;
 }
 
-Tiles Solver::tiles(bool f64) const {
+Tiles Solver::tiles(bool f64, bool flagged) const {
     Tiles t;
-    t.slots = f64 ? ws.tile64_slots : ws.tile_slots;
-    t.mass = f64 ? ws.tile64_mass : ws.tile_mass;
-    t.ntiles = f64 ? ws.ntiles64 : ws.ntiles;
-    t.ntiles_max = ns;
+    if (f64 && flagged) {
+        t.slots = ws.tile64f_slots;
+        t.mass = ws.tile64f_mass;
+        t.ntiles = ws.ntiles64f;
+    } else {
+        t.slots = f64 ? ws.tile64_slots : ws.tile_slots;
+        t.mass = f64 ? ws.tile64_mass : ws.tile_mass;
+        t.ntiles = f64 ? ws.ntiles64 : ws.ntiles;
+    }
+    t.ntiles_max = f64 ? tiles64_cap : tiles_cap;
     t.nr = f64 ? nr64 : nr;
     return t;
 }
@@ -222,6 +240,8 @@ laph_status Solver::upload_tables(const std::vector<int> &slots) {
     };
     cnt[0] = build(ts, tm, nr);
     cnt[2] = build(ts64, tm64, nr64);
+    if (cnt[0] > tiles_cap || cnt[2] > tiles64_cap)
+        return set_error(LAPH_ERR_INVALID, "slot masses outside the context's mass table");
     for (size_t i = 0; i < slots.size(); ++i) ls[i] = slots[i];
     for (int s = 0; s < ns; ++s) sm[s] = s < (int)mass.size() ? mass[s] : 0;
     cnt[1] = (int)slots.size();
@@ -245,6 +265,9 @@ laph_status Solver::upload_state() {
 }
 
 // ---- stencil helpers --------------------------------------------------------
+// workgroups of a flagged (reliable-update) stage launch: a few per CU
+constexpr int kFlaggedGrid = 2048;
+
 laph_status Solver::stage(int sprec, int out_parity, Operand in, Operand out, int clover, int pre, Operand z,
                           double cz, int post, Operand y, double a, Operand y2, double a2, double b, int red,
                           Operand w, int flagged) {
@@ -268,9 +291,11 @@ laph_status Solver::stage(int sprec, int out_parity, Operand in, Operand out, in
     s.b = b;
     s.c = cz;
     const bool f64 = sprec == LAPH_F64;
-    s.tiles = tiles(f64);
+    s.tiles = tiles(f64, flagged != 0);
     s.form = f64 ? kFormRegister : form;
     s.site_major = site_major;
+    // the flagged count is known only on the device: a small grid walks the live tiles
+    s.grid_cap = flagged ? kFlaggedGrid : 0;
     s.slots = ws.st;
     s.partials = ws.partials;
     s.pstride = pstride;
@@ -314,6 +339,19 @@ laph_status Solver::iteration() {
     // x_lo += alpha p + omega s;  r = s - omega t;  rho, |r|^2, update decision
     LAPH_TRY(blas_xr_update(*c, a, prec));
     LAPH_TRY(blas_finalize(*c, f, kFinRho));
+    // compact the slots flagged for a reliable update (list and FP64 tiles)
+    FlagArgs fl;
+    fl.tile_slots = ws.tile64_slots;
+    fl.tile_mass = ws.tile64_mass;
+    fl.ntiles = ws.ntiles64;
+    fl.nr = nr64;
+    fl.st = ws.st;
+    fl.out_slots = ws.tile64f_slots;
+    fl.out_mass = ws.tile64f_mass;
+    fl.out_ntiles = ws.ntiles64f;
+    fl.flist = ws.flist;
+    fl.nflist = ws.nflist;
+    LAPH_TRY(blas_flag_tiles(*c, fl));
     // reliable update of the flagged slots: x64 += x_lo, r64 = b_hat - M_hat x64 in FP64
     LAPH_TRY(blas_accumulate(*c, a, prec, kModeFlagged));
     LAPH_TRY(stage(LAPH_F64, 1, ws.E1, ws.O0, 1, 0, none, 0, 0, none, 0, none, 0, 1.0, 0, none, 1));

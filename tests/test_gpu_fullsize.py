@@ -3,11 +3,12 @@
 The oracle cannot solve 32^3 x 64 (or 24^3 x 48) in test time, so these checks
 use outputs it computes one by one and properties that hold at any size:
 
-* C4 (32^3 x 64, nev 64, m0 0.02): the fused perambulator for t0 = 0 and t0 = 16
-  (FP16N inner, LDS stencil, chunks of 128 -- the bench configuration); sampled
-  solutions are checked against the oracle's D at sampled sites (pointwise
-  residual), the oracle's projection of those solutions reproduces the sampled
-  tau entries, and tau obeys gamma5 reciprocity between the two source times;
+* C4 (32^3 x 64, nev 64, m0 0.02): the fused perambulator for t0 = 0 and t0 = 1
+  (FP16N inner, LDS stencil, chunks of 128 -- the bench configuration) obeys
+  gamma5 reciprocity between the two source times; a perambulator over 8 LapH
+  vectors and a solve of the same sources made with the same parameters give
+  solutions that pass the oracle's D at sampled sites (pointwise residual) and
+  whose oracle projection reproduces the sampled tau entries;
 * C2 (24^3 x 48, four masses split 40/72/64/80 in one batched solve): per-RHS
   FP64 residual reported by the library and the oracle's D at sampled sites;
 * C1 (16^3 x 32, single-RHS solver, FP32 and FP16N inner): sampled RHS against
@@ -59,30 +60,49 @@ def test_c4_perambulator_sampled_and_reciprocal(c4):
     p = pl.default_params(inner_prec="f16n", chunk=128, rhs_tile=16, stencil=2)
     log_case("c4 perambulator", t0=0)
     tauA, stA = lat.perambulator_raw(Vd, 0, 0, 1e-10, p)
-    log_case("c4 perambulator", t0=16)
-    tauB, stB = lat.perambulator_raw(Vd, 16, 0, 1e-10, p)
+    log_case("c4 perambulator", t0=1)
+    tauB, stB = lat.perambulator_raw(Vd, 1, 0, 1e-10, p)
     assert all(s["status"] == "converged" and s["true_res"] <= 1e-10 for s in stA + stB)
     tauA, tauB = host(tauA), host(tauB)
-    # gamma5 reciprocity between source times 0 and 16
+    # gamma5 reciprocity between source times 0 and 1.  Each side comes from its
+    # own solves, good to about cond(D) * 1e-10 in absolute terms, so the check
+    # uses neighbouring source times, where these entries are large (at a time
+    # separation of 16 they are ~1e-6 of the source-slice entries and the
+    # relative agreement of two independent 1e-10 solves drops to ~1e-6).
     g5 = np.array([1, 1, -1, -1])
     exp = np.einsum("b,a,klab->lkba", g5, g5, np.conj(tauB[0]))
-    assert np.linalg.norm(tauA[16] - exp) <= 1e-8 * np.linalg.norm(exp)
-    # sampled solutions: oracle residual at sampled sites, oracle projection of the sampled sinks
-    rhs = [5, 130, 255]
-    B = laph.laph_sources(V, 0)[rhs]
-    log_case("c4 sampled solves", rhs=rhs)
-    X, st = lat.solve_raw(dev(B), 0, 1e-10, pl.default_params(inner_prec="f16n", rhs_tile=4, stencil=2))
-    X = host(X)
+    assert np.linalg.norm(tauA[1] - exp) <= 1e-8 * np.linalg.norm(exp)
+    # sampled solutions.  Two independent solves to a relative residual of 1e-10
+    # agree only to about cond(D) * 1e-10, so the oracle's projection is checked
+    # on the very solves the perambulator made: a perambulator over the first 8
+    # LapH vectors (32 RHS = one chunk of 32) and a solve of the same 32 sources
+    # with the same parameters run the same per-RHS arithmetic.
+    nev8 = 8
+    V8 = np.ascontiguousarray(V[:, :nev8])
+    p32 = pl.default_params(inner_prec="f16n", chunk=32, rhs_tile=16, stencil=2)
+    log_case("c4 perambulator", t0=0, nev=nev8, chunk=32)
+    tauC, stC = lat.perambulator_raw(dev(V8), 0, 0, 1e-10, p32)
+    tauC = host(tauC)
+    rhs = [5, 18, 31]
+    B = laph.laph_sources(V8, 0)
+    log_case("c4 sampled solves", nrhs=B.shape[0])
+    Xd, st = lat.solve_raw(dev(B), 0, 1e-10, p32)
+    X = host(Xd[rhs])
+    del Xd
+    assert [s["iters"] for s in st] == [s["iters"] for s in stC]
     sites = _sample_sites(cfg["dims"], 24, 7) + _sample_sites(cfg["dims"], 8, 8, t_fixed=0)
-    res, bn = _pointwise_residual(U, X, B, sites, m0, csw)
+    res, bn = _pointwise_residual(U, X, B[rhs], sites, m0, csw)
     assert np.all(res <= 1e-10 * bn)
     for i, r in enumerate(rhs):
         k, al = divmod(r, 4)
         for t in (0, 1, 33, 63):
-            # tau[t][l][k][beta][alpha] for this RHS from the oracle's projection of X
-            exp_t = np.einsum("lzyxa,zyxba->lb", np.conj(V[t]), X[i, t])
-            got = tauA[t, :, k, :, al]
-            assert np.linalg.norm(got - exp_t) <= 1e-8 * np.linalg.norm(tauA[t]) + 1e-14
+            # tau[t][l][k][beta][alpha] for this RHS from the oracle's projection of X;
+            # |V_t^dagger X_t| <= |X_t| bounds the rounding of either sum
+            exp_t = np.einsum("lzyxa,zyxba->lb", np.conj(V8[t]), X[i, t])
+            got = tauC[t, :, k, :, al]
+            assert np.linalg.norm(got - exp_t) <= 1e-12 * np.linalg.norm(X[i, t])
+        # the first 8 sinks of the bench-shaped perambulator agree to the solve accuracy
+        assert np.linalg.norm(tauA[0, :nev8, k, :, al] - tauC[0, :, k, :, al]) <= 1e-6 * np.linalg.norm(tauC[0, :, k, :, al])
 
 
 def test_c2_multimass_batched_sampled():
