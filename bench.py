@@ -25,6 +25,7 @@ import numpy as np  # noqa: E402
 import laph_synth as ls  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFLOPS = 78.6
 # FP32 vector peak without packed-FP32 instructions (the build disables them):
 # 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz
 ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
@@ -124,6 +125,100 @@ def stored_traffic(key):
     return None
 
 
+def _timed(torch, fn):
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return r, time.perf_counter() - t
+
+
+def _solve_summary(st, n, dt):
+    return {"rhs_per_s": round(n / dt, 2), "mean_iters": round(float(np.mean([s["iters"] for s in st])), 2),
+            "mean_updates": round(float(np.mean([s["updates"] for s in st])), 2),
+            "max_true_res": max(s["true_res"] for s in st)}
+
+
+def extra_suite(laph, torch):
+    """Secondary measurements of the other workloads (outside the timed region):
+    16^3x32 single-RHS solves per inner precision, the 24^3x48 four-mass batched
+    solve against the plain FP64 single-RHS solver, and the forward / backward
+    times of the differentiable perambulator at 16^3x32."""
+    out = {}
+    tol = 1e-10
+    # 16^3 x 32: 128 RHS at t0 = 0, one RHS after another
+    cfg = ls.CONFIGS["c1"]
+    dims = cfg["dims"]
+    lat = laph.Lattice(dims)
+    lat.load_gauge(torch.from_numpy(ls.gauge_field(dims, cfg["seed_u"])).cuda())
+    lat.set_masses([cfg["masses"][0]], cfg["csw"])
+    Vd = torch.from_numpy(ls.orthonormal_laph_vectors(dims, cfg["nev"], cfg["seed_v"])).cuda()
+    B = lat.make_sources(Vd, 0)
+    c1 = {}
+    for prec in ("f64", "f32", "f16n"):
+        p = laph.default_params(inner_prec=prec, batched=0, rhs_tile=1, stencil=1, traversal=1)
+        lat.solve_raw(B[:2].contiguous(), 0, tol, p)
+        (_, st), dt = _timed(torch, lambda: lat.solve_raw(B, 0, tol, p))
+        c1["single_rhs_" + prec] = _solve_summary(st, B.shape[0], dt)
+    tuned = lat.autotune("f16n", B.shape[0], 0)
+    p = laph.default_params(inner_prec="f16n", stencil=tuned["stencil"], rhs_tile=tuned["rhs_tile"],
+                            traversal=tuned["traversal"])
+    (_, st), dt = _timed(torch, lambda: lat.solve_raw(B, 0, tol, p))
+    c1["batched_f16n"] = _solve_summary(st, B.shape[0], dt)
+    out["16x16x16x32_128rhs_m0.05"] = c1
+    del lat, Vd, B
+    torch.cuda.empty_cache()
+
+    # 24^3 x 48: 256 RHS over four masses in one batched solve
+    cfg = ls.CONFIGS["c2"]
+    dims = cfg["dims"]
+    lat = laph.Lattice(dims)
+    lat.load_gauge(torch.from_numpy(ls.gauge_field(dims, cfg["seed_u"])).cuda())
+    lat.set_masses(list(cfg["masses"]), cfg["csw"])
+    Vd = torch.from_numpy(ls.orthonormal_laph_vectors(dims, cfg["nev"], cfg["seed_v"])).cuda()
+    B = lat.make_sources(Vd, 0)
+    mi = ls.rhs_masses(cfg)
+    tuned = lat.autotune("f16n", B.shape[0], 0)
+    p = laph.default_params(inner_prec="f16n", stencil=tuned["stencil"], rhs_tile=tuned["rhs_tile"],
+                            traversal=tuned["traversal"])
+    (X, st), dt = _timed(torch, lambda: lat.solve_raw(B, mi, tol, p))
+    del X
+    c2 = {"batched_f16n": _solve_summary(st, B.shape[0], dt), "tuned": tuned, "per_mass": {}}
+    for m, m0 in enumerate(cfg["masses"]):
+        it = [s["iters"] for s, mm in zip(st, mi) if mm == m]
+        c2["per_mass"]["%g" % m0] = {"rhs": len(it), "iters_min": min(it), "iters_max": max(it)}
+    pick = [0, 39, 40, 111, 112, 175, 176, 255]   # two per mass
+    Bs = B[pick].contiguous()
+    p64 = laph.default_params(inner_prec="f64", batched=0, rhs_tile=1, stencil=1, traversal=1)
+    (_, st64), dt64 = _timed(torch, lambda: lat.solve_raw(Bs, [mi[r] for r in pick], tol, p64))
+    c2["single_rhs_f64_sample"] = _solve_summary(st64, len(pick), dt64)
+    c2["speedup_of_batched_mixed"] = round(c2["batched_f16n"]["rhs_per_s"] / c2["single_rhs_f64_sample"]["rhs_per_s"], 2)
+    out["24x24x24x48_256rhs_4masses"] = c2
+    del lat, Vd, B, Bs
+    torch.cuda.empty_cache()
+
+    # 16^3 x 32: differentiable perambulator, L = sum |tau[t = 8]|^2, FP32 inner
+    cfg = ls.CONFIGS["c3"]
+    dims = cfg["dims_timing"]
+    lat = laph.Lattice(dims)
+    lat.load_gauge(torch.from_numpy(ls.gauge_field(dims, cfg["seed_u"])).cuda())
+    lat.csw = cfg["csw"]
+    Vd = torch.from_numpy(ls.orthonormal_laph_vectors(dims, cfg["nev"], cfg["seed_v"])).cuda()
+    c3 = {}
+    for rep in range(2):   # the first pass warms up
+        B = lat.make_sources(Vd, 0).requires_grad_(True)
+        m0 = torch.tensor(cfg["masses"][0], dtype=torch.float64, requires_grad=True)
+        tau, tf = _timed(torch, lambda: laph.project(lat, laph.solve(lat, B, m0, tol, inner_prec="f32"), Vd))
+        L = (tau[cfg["t_sink_timing"]].abs() ** 2).sum()
+        _, tb = _timed(torch, lambda: L.backward())
+        c3 = {"rhs": int(B.shape[0]), "forward_s": round(tf, 4), "backward_s": round(tb, 4),
+              "backward_over_forward": round(tb / tf, 3), "grad_m0": float(m0.grad)}
+    out["16x16x16x32_gradients"] = c3
+    del lat, Vd
+    torch.cuda.empty_cache()
+    return out
+
+
 def stage_key(args, dims):
     return "%s/%s/n%d/s%d/t%d/v%d" % ("x".join(map(str, dims)), args.prec, args.chunk, args.stencil,
                                       args.rhs_tile, args.traversal)
@@ -166,6 +261,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--fp64-sample", type=int, default=4, help="RHS for the plain FP64 single-RHS comparison")
+    ap.add_argument("--extra", action="store_true",
+                    help="also measure the 16^3x32 single-RHS, 24^3x48 four-mass and gradient workloads")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch the dominant stage (and a 2 GiB copy for the counter scale), for "
                          "rocprofv3 --pmc runs; needs --stencil, --rhs-tile and --traversal")
@@ -242,6 +339,9 @@ def main():
                 "speedup_of_batched_mixed": round(value / (args.fp64_sample / dt), 2)}
         del B
 
+    # projection: 8 flop per complex multiply-add, nev sinks x 4 spins x 3 colours x L^3 sites x T
+    # timeslices per RHS
+    proj_flops = 8.0 * nev * 4 * 3 * dims[0] * dims[1] * dims[2] * dims[3] * n_rhs
     # dominant kernels: the two fused stencil stages, timed with HIP events on the lattice stream
     ms1, ms2 = lat.time_stages(args.prec, args.chunk, args.rhs_tile, 0, reps=20, stencil=args.stencil,
                                traversal=args.traversal)
@@ -288,11 +388,17 @@ def main():
                    "traversal": "tile_sweeps" if args.traversal == 2 else "site_block_tiles"},
         "roofline": roofline,
         "detail": {"solve_ms": round(ms_solve, 1), "project_ms": round(ms_proj, 1),
+                   "projection_tflops": round(proj_flops / (ms_proj * 1e-3) / 1e12, 2),
+                   "projection_fp64_mfma_frac": round(proj_flops / (ms_proj * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4),
                    "max_true_res": worst, "mean_iters": float(np.mean([s["iters"] for s in stats_all])),
                    "mean_updates": float(np.mean([s["updates"] for s in stats_all])),
                    "setup_s": round(setup_s, 1), "fp64_single_rhs": fp64, "autotuned": tuned,
                    "stage1_small_batches": dslash},
     }
+    if args.extra:
+        del tau, lat, Vd
+        torch.cuda.empty_cache()
+        out["detail"]["extra"] = extra_suite(laph, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, dims, U, v_src, args.cpu_seconds)
     print(json.dumps(out), flush=True)

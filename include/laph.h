@@ -88,6 +88,9 @@ typedef struct {
                           2 links staged in LDS (one wave per RHS); 0: chosen by the library */
     int traversal;     /* stencil workgroup order: 1 the tiles of one site block together,
                           2 each tile sweeps the lattice; 0: chosen by the library */
+    int stencil64;     /* form of the FP64 reliable-update stages when inner_prec is not FP64
+                          (1 register tiles, 2 LDS-staged links, 0: chosen by the library) */
+    int rhs_tile64;    /* their RHS per link load (as rhs_tile; <= 0: chosen by the library) */
 } laph_solve_params;
 
 typedef struct {

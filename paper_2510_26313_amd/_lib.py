@@ -27,7 +27,7 @@ class SolveParams(ctypes.Structure):
     _fields_ = [("inner_prec", c_int), ("batched", c_int), ("delta", c_double), ("maxiter", c_int),
                 ("graph_iters", c_int), ("use_graph", c_int), ("dagger", c_int), ("use_x0", c_int),
                 ("rhs_tile", c_int), ("chunk", c_int), ("stencil", c_int),
-                ("traversal", c_int)]
+                ("traversal", c_int), ("stencil64", c_int), ("rhs_tile64", c_int)]
 
 
 class RhsStats(ctypes.Structure):

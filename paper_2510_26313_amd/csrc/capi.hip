@@ -103,6 +103,8 @@ void laph_default_params(laph_solve_params *p) {
     p->chunk = 0;
     p->stencil = 0;
     p->traversal = 0;
+    p->stencil64 = 0;
+    p->rhs_tile64 = 0;
 }
 
 const char *laph_last_error(void) { return g_err.c_str(); }
@@ -324,8 +326,12 @@ static laph_status check_params(const laph_solve_params *p, double tol) {
     if (p->rhs_tile > 0 && p->rhs_tile != 1 && p->rhs_tile != 2 && p->rhs_tile != 4 && p->rhs_tile != 8 &&
         p->rhs_tile != 16)
         return set_error(LAPH_ERR_INVALID, "rhs_tile must be 1, 2, 4 (register tiles) or 4, 8, 16 (LDS links)");
-    if (p->stencil < 0 || p->stencil > 2 || p->traversal < 0 || p->traversal > 2)
-        return set_error(LAPH_ERR_INVALID, "stencil and traversal must be 0, 1 or 2");
+    if (p->rhs_tile64 > 0 && p->rhs_tile64 != 1 && p->rhs_tile64 != 2 && p->rhs_tile64 != 4 &&
+        p->rhs_tile64 != 8 && p->rhs_tile64 != 16)
+        return set_error(LAPH_ERR_INVALID, "rhs_tile64 must be 1, 2, 4 (register tiles) or 4, 8, 16 (LDS links)");
+    if (p->stencil < 0 || p->stencil > 2 || p->traversal < 0 || p->traversal > 2 || p->stencil64 < 0 ||
+        p->stencil64 > 2)
+        return set_error(LAPH_ERR_INVALID, "stencil, stencil64 and traversal must be 0, 1 or 2");
     return LAPH_OK;
 }
 
@@ -535,7 +541,7 @@ laph_status laph_time_stages(laph_ctx h, int prec, int nrhs, int stencil, int rh
     LAPH_TRY(check_ctx(h, true, true));
     Ctx &c = C(h);
     const int form = stencil == 2 ? kFormLds : kFormRegister;
-    const bool tile_ok = form == kFormLds ? (rhs_tile == 4 || rhs_tile == 8 || rhs_tile == 16) && prec != LAPH_F64
+    const bool tile_ok = form == kFormLds ? (rhs_tile == 4 || rhs_tile == 8 || rhs_tile == 16)
                                           : (rhs_tile == 1 || rhs_tile == 2 || rhs_tile == 4);
     if (!valid_prec(prec) || nrhs <= 0 || nrhs > 65535 || reps <= 0 || !ms_host2 || !tile_ok || mass_idx < 0 ||
         mass_idx >= c.n_mass || (stencil != 1 && stencil != 2) || (traversal != 1 && traversal != 2))

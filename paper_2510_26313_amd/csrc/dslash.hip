@@ -36,6 +36,7 @@ laph_status launch_stage(const Ctx &c, const StageSpec &s) {
     a.pstride = s.pstride;
     a.site_major = s.site_major;
     a.grid_cap = s.grid_cap;
+    a.flag_filter = s.flagged;
     a.one = 1.0f;
     a.st = s.slots;
     a.partials = s.partials;
@@ -43,7 +44,9 @@ laph_status launch_stage(const Ctx &c, const StageSpec &s) {
     if (s.red && s.pstride < a.nsb) return set_error(LAPH_ERR_INVALID, "partial-sum stride too small");
     bool ok = false;
     if (s.form == kFormLds) {
-        if (s.prec == LAPH_F32)
+        if (s.prec == LAPH_F64)
+            ok = launch_stage_lds_f64(s, a, c.stream);
+        else if (s.prec == LAPH_F32)
             ok = launch_stage_lds_f32(s, a, c.stream);
         else if (s.prec == LAPH_F16N)
             ok = launch_stage_lds_f16(s, a, c.stream);

@@ -49,6 +49,7 @@ struct StageArgs {
     double *partials;
     float one;   // 1.0f, opaque to the compiler (keeps FP16N projections as mixed-precision FMAs)
     int grid_cap;   // launch only: at most this many workgroups (0: one per item)
+    int flag_filter;   // LDS form: skip slots not flagged for a reliable update
 };
 
 // Work items of a stage launch are (site block, tile) pairs of the live tiles:

@@ -106,6 +106,7 @@ __device__ __forceinline__ void stage_lds_body(const StageArgs &A, int sb, int t
     for (int rw = 0; rw < RW; ++rw) {
         const int slot = A.tile_slots[tile * NT + rw * 4 + wave];
         if (slot < 0) continue;   // wave-uniform
+        if (A.flag_filter && !(A.st[slot].flag != 0 && A.st[slot].status == LAPH_RHS_ACTIVE)) continue;
         double part[NQ > 0 ? NQ : 1];
 #pragma unroll
         for (int q = 0; q < (NQ > 0 ? NQ : 1); ++q) part[q] = 0.0;
@@ -231,15 +232,27 @@ inline void launch_lds_t(const StageArgs &a, hipStream_t st) {
 
 template <class P, int RW, bool DAG>
 inline bool launch_lds_combo(const StageSpec &s, const StageArgs &a, hipStream_t st) {
-    if (s.flagged) return false;
+    constexpr bool is64 = std::is_same<P, F64>::value;
+    // masked (reliable-update) stages exist in FP64 only; the kernel skips unflagged slots
+    if (s.flagged && !is64) return false;
     const int key = s.clover * 1000 + s.pre * 100 + s.post * 10 + s.red;
     switch (key) {
         case 0: launch_lds_t<P, RW, DAG, false, false, 0, 0>(a, st); return true;       // bare hop
         case 1000: launch_lds_t<P, RW, DAG, true, false, 0, 0>(a, st); return true;    // A^-1 H in
         case 1011: launch_lds_t<P, RW, DAG, true, false, 1, 1>(a, st); return true;    // v = p - A^-1 H t, <r^, v>
         case 1012: launch_lds_t<P, RW, DAG, true, false, 1, 2>(a, st); return true;    // t = s - A^-1 H t, <t,s>,|t|^2
-        default: return false;
+        default: break;
     }
+    if constexpr (is64) {
+        switch (key) {
+            case 10: launch_lds_t<P, RW, DAG, false, false, 1, 0>(a, st); return true;     // y + b H in
+            case 13: launch_lds_t<P, RW, DAG, false, false, 1, 3>(a, st); return true;     // residual part
+            case 1023: launch_lds_t<P, RW, DAG, true, false, 2, 3>(a, st); return true;    // r64, |r64|^2
+            case 1100: launch_lds_t<P, RW, DAG, true, true, 0, 0>(a, st); return true;     // A^-1 (c z + H in)
+            default: break;
+        }
+    }
+    return false;
 }
 
 template <class P>
@@ -253,6 +266,7 @@ inline bool launch_lds_p(const StageSpec &s, const StageArgs &a, hipStream_t st)
     }
 }
 
+bool launch_stage_lds_f64(const StageSpec &s, const StageArgs &a, hipStream_t st);
 bool launch_stage_lds_f32(const StageSpec &s, const StageArgs &a, hipStream_t st);
 bool launch_stage_lds_f16(const StageSpec &s, const StageArgs &a, hipStream_t st);
 

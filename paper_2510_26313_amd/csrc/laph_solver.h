@@ -59,7 +59,7 @@ class Solver {
         size_t nints = 0, nints_used = 0;
     };
 
-    static void choose_shape(const laph_solve_params &p, int ns, int &form, int &nr, int &nr64);
+    static void choose_shape(const laph_solve_params &p, int ns, int &form, int &nr, int &form64, int &nr64);
     static size_t layout(const Ctx &c, int ns, int prec, char *base, WS *ws);
     // tune_mass >= 0: with stencil == 0 and rhs_tile <= 0, measure the stencil shape
     // for this batch if no tuned choice exists yet (on the workspace, before use)
@@ -78,6 +78,7 @@ class Solver {
     laph_solve_params p{};
     int ns = 0, prec = 0, form = kFormRegister, nr = 1, nr64 = 1, site_major = 0, nsb256 = 0, nsb_inner = 0,
         pstride = 0;
+    int form64 = kFormRegister, site_major64 = 0, nsb64 = 0;   // shape of the FP64 stages
     // most tiles a table can hold (tiles never mix masses): the launch grids
     int tiles_cap = 0, tiles64_cap = 0;
     WS ws;

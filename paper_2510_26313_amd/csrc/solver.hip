@@ -29,21 +29,30 @@ static int reg_tile(int ns) { return ns >= 4 ? 4 : (ns >= 2 ? 2 : 1); }
 // or no tuned choice exists: FP64 keeps the register tiles (its LDS link stage
 // would need twice the LDS); FP32 / FP16N use the LDS-staged links with up to
 // 16 RHS sharing each link load.
-void Solver::choose_shape(const laph_solve_params &p, int ns, int &form, int &nr, int &nr64) {
+void Solver::choose_shape(const laph_solve_params &p, int ns, int &form, int &nr, int &form64, int &nr64) {
     const int prec = p.inner_prec;
     form = prec == LAPH_F64 ? kFormRegister : kFormLds;
     if (p.stencil == 1) form = kFormRegister;
-    if (p.stencil == 2 && prec != LAPH_F64) form = kFormLds;
+    if (p.stencil == 2) form = kFormLds;
     if (form == kFormLds)
         nr = p.rhs_tile > 0 ? p.rhs_tile : (ns >= 16 ? 16 : (ns >= 8 ? 8 : 4));
     else
         nr = p.rhs_tile > 0 ? p.rhs_tile : reg_tile(ns);
-    nr64 = prec == LAPH_F64 ? nr : reg_tile(ns);
+    if (prec == LAPH_F64) {
+        form64 = form;
+        nr64 = nr;
+        return;
+    }
+    form64 = p.stencil64 == 2 ? kFormLds : kFormRegister;
+    if (form64 == kFormLds)
+        nr64 = p.rhs_tile64 > 0 ? p.rhs_tile64 : (ns >= 8 ? 8 : 4);
+    else
+        nr64 = p.rhs_tile64 > 0 ? p.rhs_tile64 : reg_tile(ns);
 }
 
-// The integer tables are sized for the largest tiles (16 inner, 4 FP64), so the
-// workspace does not depend on the tuned shape.
-static size_t table_ints(int ns) { return (size_t)ns * 16 + 2 * (size_t)ns * 4 + 6 * (size_t)ns + 16; }
+// The integer tables are sized for the largest tiles (16 RHS), so the workspace
+// does not depend on the tuned shapes.
+static size_t table_ints(int ns) { return 3 * (size_t)ns * 16 + 6 * (size_t)ns + 16; }
 
 size_t Solver::layout(const Ctx &c, int ns, int prec, char *base, WS *ws) {
     const size_t h64 = c.hv(LAPH_F64), hlo = c.hv(prec), hx = c.hv(prec == LAPH_F64 ? LAPH_F64 : LAPH_F32);
@@ -123,29 +132,46 @@ laph_status Solver::init(Ctx &ctx, int nslots, const laph_solve_params &params, 
     if (!work || bytes < need)
         return set_error(LAPH_ERR_WORKSPACE, "solver workspace too small: %zu < %zu bytes", bytes, need);
     layout(ctx, ns, prec, work, &ws);
-    choose_shape(p, ns, form, nr, nr64);
+    choose_shape(p, ns, form, nr, form64, nr64);
     site_major = p.traversal == 2 ? 1 : 0;
-    if (p.stencil == 0 && p.rhs_tile <= 0) {
-        // autotuned shape: reuse a choice for this (precision, batch) or measure one now
-        auto it = ctx.tuned.find({prec, ns});
+    site_major64 = prec == LAPH_F64 ? site_major : 0;
+    // autotuned shapes: reuse a choice for this (precision, batch) or measure one now,
+    // for the inner iterations and for the FP64 stages of the reliable updates
+    // (timed on the FP64 half-vectors E0..O0, not in use yet)
+    auto shape_of = [&](int pr, char *fields, Ctx::Shape &out) -> laph_status {
+        auto it = ctx.tuned.find({pr, ns});
         if (it == ctx.tuned.end() && tune_mass >= 0) {
             Ctx::Shape sh{};
-            LAPH_TRY(autotune_stencil(ctx, prec, ns, tune_mass, ws.r.base, ws.partials, ws.ints, &sh, nullptr));
-            it = ctx.tuned.find({prec, ns});
+            LAPH_TRY(autotune_stencil(ctx, pr, ns, tune_mass, fields, ws.partials, ws.ints, &sh, nullptr));
+            it = ctx.tuned.find({pr, ns});
         }
-        if (it != ctx.tuned.end()) {
-            form = it->second.form;
-            nr = it->second.tile;
-            if (p.traversal == 0) site_major = it->second.site_major;
-            if (prec == LAPH_F64) nr64 = nr;
+        if (it == ctx.tuned.end()) return LAPH_ERR_INVALID;   // no choice: keep the defaults
+        out = it->second;
+        return LAPH_OK;
+    };
+    Ctx::Shape sh{};
+    if (p.stencil == 0 && p.rhs_tile <= 0 && shape_of(prec, prec == LAPH_F64 ? ws.E0.base : ws.r.base, sh) == LAPH_OK) {
+        form = sh.form;
+        nr = sh.tile;
+        if (p.traversal == 0) site_major = sh.site_major;
+        if (prec == LAPH_F64) {
+            form64 = form;
+            nr64 = nr;
+            site_major64 = site_major;
         }
     }
-    if (form == kFormRegister && nr != 1 && nr != 2 && nr != 4)
-        return set_error(LAPH_ERR_INVALID, "rhs_tile must be 1, 2 or 4 for register tiles");
-    if (form == kFormLds && (nr != 4 && nr != 8 && nr != 16))
-        return set_error(LAPH_ERR_INVALID, "rhs_tile must be 4, 8 or 16 for LDS-staged links");
-    if (form == kFormLds && prec == LAPH_F64)
-        return set_error(LAPH_ERR_INVALID, "the LDS-staged stencil form is available for FP32 and FP16N");
+    if (prec != LAPH_F64 && p.stencil64 == 0 && p.rhs_tile64 <= 0 && shape_of(LAPH_F64, ws.E0.base, sh) == LAPH_OK) {
+        form64 = sh.form;
+        nr64 = sh.tile;
+        site_major64 = sh.site_major;
+    }
+    for (int k = 0; k < 2; ++k) {
+        const int f = k ? form64 : form, t = k ? nr64 : nr;
+        if (f == kFormRegister && t != 1 && t != 2 && t != 4)
+            return set_error(LAPH_ERR_INVALID, "rhs_tile must be 1, 2 or 4 for register tiles");
+        if (f == kFormLds && t != 4 && t != 8 && t != 16)
+            return set_error(LAPH_ERR_INVALID, "rhs_tile must be 4, 8 or 16 for LDS-staged links");
+    }
     carve_tables();
     // grouping by mass adds at most one partly filled tile per extra mass
     const int nm = std::max(1, ctx.n_mass);
@@ -153,6 +179,7 @@ laph_status Solver::init(Ctx &ctx, int nslots, const laph_solve_params &params, 
     tiles64_cap = std::min(ns, (ns + nr64 - 1) / nr64 + nm - 1);
     nsb256 = stage_nsb(ctx, kFormRegister);
     nsb_inner = stage_nsb(ctx, form);
+    nsb64 = stage_nsb(ctx, form64);
     pstride = partial_stride(ctx);
     host_ints.assign(ws.nints_used, 0);
     host_st.assign(ns, SlotState{});
@@ -292,8 +319,8 @@ laph_status Solver::stage(int sprec, int out_parity, Operand in, Operand out, in
     s.c = cz;
     const bool f64 = sprec == LAPH_F64;
     s.tiles = tiles(f64, flagged != 0);
-    s.form = f64 ? kFormRegister : form;
-    s.site_major = site_major;
+    s.form = f64 ? form64 : form;
+    s.site_major = f64 ? site_major64 : site_major;
     // the flagged count is known only on the device: a small grid walks the live tiles
     s.grid_cap = flagged ? kFlaggedGrid : 0;
     s.slots = ws.st;
@@ -356,7 +383,7 @@ laph_status Solver::iteration() {
     LAPH_TRY(blas_accumulate(*c, a, prec, kModeFlagged));
     LAPH_TRY(stage(LAPH_F64, 1, ws.E1, ws.O0, 1, 0, none, 0, 0, none, 0, none, 0, 1.0, 0, none, 1));
     LAPH_TRY(stage(LAPH_F64, 0, ws.O0, ws.E2, 1, 0, none, 0, 2, ws.E0, 1.0, ws.E1, -1.0, 0.25, 3, none, 1));
-    LAPH_TRY(blas_finalize(*c, f, kFinUpdate));
+    LAPH_TRY(blas_finalize(*c, fin(ns, nsb64), kFinUpdate));
     LAPH_TRY(blas_lower(*c, a, prec, kModeFlagged, 0));
     LAPH_TRY(blas_finalize(*c, f, kFinRho2));
     return LAPH_OK;
@@ -465,7 +492,8 @@ laph_status Solver::solve(const SourceSpec &src, const std::vector<int> &slot_ma
             LAPH_TRY(blas_copy64(*c, a, ws.E2, ws.E0, kModeActive));
             LAPH_TRY(blas_norm2(*c, a, ws.E2, none, kModeActive));
         }
-        LAPH_TRY(blas_finalize(*c, f, kFinR64));
+        // partials of the FP64 stage (warm start) or of the norm kernel
+        LAPH_TRY(blas_finalize(*c, have_x ? fin(ncur, nsb64) : f, kFinR64));
         LAPH_TRY(blas_lower(*c, a, prec, kModeActive, 1));
         LAPH_TRY(blas_finalize(*c, f, kFinInit));
         // iterate; the captured graph always spans ns slots (tables say which are live)
@@ -503,10 +531,10 @@ laph_status Solver::solve(const SourceSpec &src, const std::vector<int> &slot_ma
         LAPH_TRY(load_sources(src));
         LAPH_TRY(clover(0, 0, ws.E1, ws.E0, 1, ws.E0, 1.0, -1.0, n));
         LAPH_TRY(stage(LAPH_F64, 0, ws.O0, ws.E0, 0, 0, none, 0, 1, ws.E0, 1.0, none, 0, 0.5, 3, none, 0));
-        LAPH_TRY(blas_finalize(*c, f, kFinTrueRes));
+        LAPH_TRY(blas_finalize(*c, fin(n, nsb64), kFinTrueRes));
         LAPH_TRY(clover(1, 0, ws.O0, ws.O1, 1, ws.O1, 1.0, -1.0, n));
         LAPH_TRY(stage(LAPH_F64, 1, ws.E1, ws.O1, 0, 0, none, 0, 1, ws.O1, 1.0, none, 0, 0.5, 3, none, 0));
-        LAPH_TRY(blas_finalize(*c, f, kFinTrueRes));
+        LAPH_TRY(blas_finalize(*c, fin(n, nsb64), kFinTrueRes));
         LAPH_TRY(download_state());
         // slots that converged on the even-odd residual but miss tol on the full one go again
         std::vector<int> redo;

@@ -77,9 +77,8 @@ static std::vector<Ctx::Shape> candidates(int prec, int nrhs) {
     for (int sm : {0, 1}) {
         for (int t : {1, 2, 4})
             if (t <= nrhs || t == 1) out.push_back({kFormRegister, t, sm});
-        if (prec != LAPH_F64)
-            for (int t : {4, 8, 16})
-                if (t <= nrhs || t == 4) out.push_back({kFormLds, t, sm});
+        for (int t : {4, 8, 16})
+            if (t <= nrhs || t == 4) out.push_back({kFormLds, t, sm});
     }
     return out;
 }

@@ -195,8 +195,6 @@ def test_solve_mixed_precision(ragged, ragged_ref, prec, batched, tile, stencil,
     import paper_2510_26313_amd as pl
     U, lat = ragged
     b, x_ref = ragged_ref
-    if prec == "f64" and stencil == 2:
-        tile, stencil = 2, 1      # FP64 runs the register-tile form only
     log_case("solve", prec=prec, batched=batched, tile=tile, stencil=stencil, graph=graph)
     p = pl.default_params(inner_prec=prec, batched=batched, rhs_tile=tile, stencil=stencil, traversal=trav,
                           use_graph=graph, graph_iters=4)
@@ -206,6 +204,21 @@ def test_solve_mixed_precision(ragged, ragged_ref, prec, batched, tile, stencil,
     assert all(s["status"] == "converged" and s["true_res"] <= 1e-10 for s in st), st
     if prec != "f64":
         assert all(s["updates"] >= 2 for s in st)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16n"])
+@pytest.mark.parametrize("stencil64,tile64", [(1, 1), (1, 4), (2, 4), (2, 8), (2, 16)])
+def test_solve_fp64_update_shapes(ragged, ragged_ref, prec, stencil64, tile64):
+    """The FP64 reliable-update stages in each form (they act on the flagged RHS only)."""
+    import paper_2510_26313_amd as pl
+    U, lat = ragged
+    b, x_ref = ragged_ref
+    log_case("solve_fp64_updates", prec=prec, stencil64=stencil64, tile64=tile64)
+    p = pl.default_params(inner_prec=prec, rhs_tile=4, stencil=2, traversal=1, stencil64=stencil64,
+                          rhs_tile64=tile64, graph_iters=4)
+    X, st = lat.solve_raw(dev(b), 1, 1e-10, p)
+    assert per_rhs_rel(host(X), x_ref).max() < 1e-8, st
+    assert all(s["status"] == "converged" and s["true_res"] <= 1e-10 and s["updates"] >= 2 for s in st), st
 
 
 def test_solve_dagger(ragged, ragged_ref):
@@ -255,7 +268,7 @@ def test_solve_multimass_lds(ragged):
 
 
 @pytest.mark.parametrize("prec,stencil,tile,trav", [("f16n", 2, 16, 2), ("f16n", 1, 4, 1), ("f32", 2, 8, 1),
-                                                   ("f64", 1, 2, 2)])
+                                                   ("f64", 1, 2, 2), ("f64", 2, 8, 1)])
 def test_time_stages_runs(ragged, prec, stencil, tile, trav):
     U, lat = ragged
     log_case("time_stages", prec=prec, stencil=stencil, tile=tile, traversal=trav)
