@@ -161,6 +161,7 @@ def extra_suite(laph, torch):
         (_, st), dt = _timed(torch, lambda: lat.solve_raw(B, 0, tol, p))
         c1["single_rhs_" + prec] = _solve_summary(st, B.shape[0], dt)
     tuned = lat.autotune("f16n", B.shape[0], 0)
+    lat.autotune("f64", B.shape[0], 0)   # the reliable-update stages' shape, outside the timing
     p = laph.default_params(inner_prec="f16n", stencil=tuned["stencil"], rhs_tile=tuned["rhs_tile"],
                             traversal=tuned["traversal"])
     (_, st), dt = _timed(torch, lambda: lat.solve_raw(B, 0, tol, p))
@@ -179,6 +180,7 @@ def extra_suite(laph, torch):
     B = lat.make_sources(Vd, 0)
     mi = ls.rhs_masses(cfg)
     tuned = lat.autotune("f16n", B.shape[0], 0)
+    lat.autotune("f64", B.shape[0], 0)
     p = laph.default_params(inner_prec="f16n", stencil=tuned["stencil"], rhs_tile=tuned["rhs_tile"],
                             traversal=tuned["traversal"])
     (X, st), dt = _timed(torch, lambda: lat.solve_raw(B, mi, tol, p))
@@ -299,6 +301,8 @@ def main():
         # the library's autotuner picks the stencil form and RHS per link load for this batch
         tuned = lat.autotune(args.prec, args.chunk, 0)
         args.stencil, args.rhs_tile, args.traversal = tuned["stencil"], tuned["rhs_tile"], tuned["traversal"]
+        # and the shape of the FP64 reliable-update stages (the solver reuses both choices)
+        tuned["fp64_stages"] = lat.autotune("f64", args.chunk, 0)
     params = laph.default_params(inner_prec=args.prec, batched=1, chunk=args.chunk, rhs_tile=args.rhs_tile,
                                  stencil=args.stencil, traversal=args.traversal)
     setup_s = time.perf_counter() - t_setup

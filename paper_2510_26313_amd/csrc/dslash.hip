@@ -78,47 +78,51 @@ struct CloverArgs {
     int n;
 };
 
+// One thread per site; a block row takes kCloverRhs RHS in turn, so the clover
+// blocks of its sites come from HBM once and from the caches for the other RHS
+// (a grid row per RHS streamed the whole clover field once per RHS).
+constexpr int kCloverRhs = 4;
+
 template <class P, bool POST>
 __global__ __launch_bounds__(kBlock) void clover_kernel(CloverArgs A) {
     using R = typename P::real;
     const int h = blockIdx.x * kBlock + threadIdx.x;
-    const int j = blockIdx.y;
-    if (h >= A.vh || j >= A.n) return;
-    const int slot = A.slot_list ? A.slot_list[j] : j;
-    const int mass = A.slot_mass ? A.slot_mass[slot] : A.mass_idx;
-    cplx<R> in[12], out[12];
-    SpinorIO<P>::load(A.in.at(slot), A.vh, h, in);
-    if (A.inverse) {
-        const char *m = A.mat + (size_t)mass * A.mass_stride;
+    if (h >= A.vh) return;
+#pragma unroll 1
+    for (int jj = 0; jj < kCloverRhs; ++jj) {
+        const int j = blockIdx.y * kCloverRhs + jj;
+        if (j >= A.n) break;
+        const int slot = A.slot_list ? A.slot_list[j] : j;
+        const int mass = A.slot_mass ? A.slot_mass[slot] : A.mass_idx;
+        cplx<R> in[12], out[12];
+        SpinorIO<P>::load(A.in.at(slot), A.vh, h, in);
 #pragma unroll
         for (int blk = 0; blk < 2; ++blk) {
             R mm[36];
-            CloverIO<P>::load(m, blk, A.vh, h, mm);
-            herm6_apply(mm, &in[6 * blk], &out[6 * blk]);
+            if (A.inverse) {
+                CloverIO<P>::load(A.mat + (size_t)mass * A.mass_stride, blk, A.vh, h, mm);
+                herm6_apply(mm, &in[6 * blk], &out[6 * blk]);
+            } else {
+                // the clover term is kept in FP64 only; A = (4 + m0) + term
+                double md[36];
+                CloverIO<F64>::load(A.mat, blk, A.vh, h, md);
+#pragma unroll
+                for (int k = 0; k < 36; ++k) mm[k] = R(md[k]);
+                herm6_apply(mm, &in[6 * blk], &out[6 * blk], R(A.diag[mass]));
+            }
         }
-    } else {
-        // the clover term is kept in FP64 only; A = (4 + m0) + term
+        const R bb = R(A.b);
 #pragma unroll
-        for (int blk = 0; blk < 2; ++blk) {
-            double md[36];
-            CloverIO<F64>::load(A.mat, blk, A.vh, h, md);
-            R mm[36];
+        for (int c = 0; c < 12; ++c) out[c] = bb * out[c];
+        if (POST) {
+            cplx<R> yy[12];
+            SpinorIO<P>::load(A.y.at(slot), A.vh, h, yy);
+            const R aa = R(A.a);
 #pragma unroll
-            for (int k = 0; k < 36; ++k) mm[k] = R(md[k]);
-            herm6_apply(mm, &in[6 * blk], &out[6 * blk], R(A.diag[mass]));
+            for (int c = 0; c < 12; ++c) out[c] = out[c] + aa * yy[c];
         }
+        SpinorIO<P>::store(A.out.at(slot), A.vh, h, out);
     }
-    const R bb = R(A.b);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) out[c] = bb * out[c];
-    if (POST) {
-        cplx<R> yy[12];
-        SpinorIO<P>::load(A.y.at(slot), A.vh, h, yy);
-        const R aa = R(A.a);
-#pragma unroll
-        for (int c = 0; c < 12; ++c) out[c] = out[c] + aa * yy[c];
-    }
-    SpinorIO<P>::store(A.out.at(slot), A.vh, h, out);
 }
 
 laph_status launch_clover(const Ctx &c, const CloverSpec &s) {
@@ -138,7 +142,7 @@ laph_status launch_clover(const Ctx &c, const CloverSpec &s) {
     a.slot_mass = s.slot_mass;
     a.mass_idx = s.mass_idx;
     a.n = s.n;
-    dim3 grid((c.g.vh + kBlock - 1) / kBlock, s.n);
+    dim3 grid((c.g.vh + kBlock - 1) / kBlock, (s.n + kCloverRhs - 1) / kCloverRhs);
 #define LAPH_CL(PT)                                                                                   \
     if (s.post)                                                                                       \
         hipLaunchKernelGGL((clover_kernel<PT, true>), grid, dim3(kBlock), 0, c.stream, a);           \
