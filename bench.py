@@ -369,13 +369,26 @@ def main():
                      "hbm_frac": round(gbs1 / HBM_PEAK_GBS, 4), "tflops": round(tfl1, 3),
                      "stage2_ms_per_launch": round(ms2, 4)})
 
+    # a plain device-to-device copy of 2 GiB: the HBM rate a streaming kernel reaches here
+    xa = torch.empty(2 ** 29, dtype=torch.float32, device="cuda").fill_(1.0)
+    xb = torch.empty_like(xa)
+    xb.copy_(xa)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        xb.copy_(xa)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * xa.numel() * 4 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del xa, xb
     # the stencil at small batches, where it is bound by HBM (algorithmic bytes / time)
-    dslash = {}
+    dslash = {"copy_gbs": round(copy_gbs, 1)}
     for prec, nrhs, st, tile in (("f32", 1, 1, 1), ("f16n", 1, 1, 1), ("f32", 8, 2, 8), ("f16n", 8, 2, 8)):
         m1, _ = lat.time_stages(prec, nrhs, tile, 0, reps=10, stencil=st, traversal=1)
         gb = stage_bytes_per_site(prec, nrhs, 1) * vh / (m1 * 1e-3) / 1e9
         dslash["%s_nrhs%d" % (prec, nrhs)] = {"ms": round(m1, 4), "gbs": round(gb, 1),
-                                              "hbm_frac": round(gb / HBM_PEAK_GBS, 4)}
+                                              "hbm_frac": round(gb / HBM_PEAK_GBS, 4),
+                                              "of_copy": round(gb / copy_gbs, 4)}
 
     out = {
         "metric": "perambulator RHS solved/s at rel. residual 1e-10; Dslash HBM GB/s vs peak",

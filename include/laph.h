@@ -75,7 +75,7 @@ typedef struct {
     int inner_prec;    /* laph_prec of the Krylov iterations (FP64 reliable updates always) */
     int batched;       /* 1: all RHS in one solver invocation; 0: one RHS after another */
     double delta;      /* reliable update when |r_inner| < delta * |r| at the last update;
-                          <= 0 picks 0.01 (F16N), 0.001 (F32), 0 (F64: update only at the end) */
+                          <= 0 picks 0.005 (F16N), 0.001 (F32), 0 (F64: update only at the end) */
     int maxiter;       /* per RHS; <= 0 picks 10000 */
     int graph_iters;   /* iterations per captured HIP graph between host polls; <= 0 picks 8 */
     int use_graph;     /* 1: replay captured HIP graphs; 0: plain launches */

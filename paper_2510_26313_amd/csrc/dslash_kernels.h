@@ -50,6 +50,9 @@ struct StageArgs {
     float one;   // 1.0f, opaque to the compiler (keeps FP16N projections as mixed-precision FMAs)
     int grid_cap;   // launch only: at most this many workgroups (0: one per item)
     int flag_filter;   // LDS form: skip slots not flagged for a reliable update
+    // LDS form: order of the 64-site blocks as 4-D tiles (nyb blocks of y rows x
+    // tz z-planes x tt timeslices); tz == 0: memory order
+    int nyb, tz, tt;
 };
 
 // Work items of a stage launch are (site block, tile) pairs of the live tiles:
@@ -78,6 +81,23 @@ __device__ __forceinline__ void stage_item(int w, int site_major, int nsb, int n
         sb = w / ntiles;
         tile = w - sb * ntiles;
     }
+}
+// Physical site block of the L-th block in the tiled order: within a tile the y
+// blocks run fastest, then tz z-planes, then tt timeslices; tiles go in z, then t.
+// Blocks that run at the same time then hold each other's z and t neighbours,
+// which stay in L2 instead of being fetched again from HBM.
+__device__ __forceinline__ int tiled_block(int L, int nyb, int tz, int tt, int lz) {
+    if (tz == 0) return L;
+    const int yb = L % nyb;
+    int r = L / nyb;
+    const int zl = r % tz;
+    r /= tz;
+    const int tl = r % tt;
+    r /= tt;
+    const int nzt = lz / tz;
+    const int ztile = r % nzt;
+    const int ttile = r / nzt;
+    return ((ttile * tt + tl) * lz + ztile * tz + zl) * nyb + yb;
 }
 // grid of a stage launch: every item, or at most cap workgroups (cap > 0)
 inline int stage_grid(int items_max, int cap) {

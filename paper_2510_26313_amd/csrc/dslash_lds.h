@@ -216,7 +216,7 @@ __global__ __launch_bounds__(256) void stage_lds_kernel(StageArgs A) {
     for (int w = first; w < end; w += step) {
         int sb, tile;
         stage_item(w, A.site_major, A.nsb, nt, sb, tile);
-        stage_lds_body<P, RW, DAG, CLOVER, PRE, POST, RED>(A, sb, tile);
+        stage_lds_body<P, RW, DAG, CLOVER, PRE, POST, RED>(A, tiled_block(sb, A.nyb, A.tz, A.tt, A.g.lz), tile);
         __syncthreads();   // the next item stages its links in the same LDS
     }
 }

@@ -443,10 +443,11 @@ laph_status Solver::solve(const SourceSpec &src, const std::vector<int> &slot_ma
     for (int i = 0; i < n; ++i) all[i] = i;
     LAPH_TRY(upload_tables(all));
     double delta = p.delta;
-    // defaults measured on the 32^3 x 64 perambulator: delta 0.1 / 0.05 / 0.02 / 0.01 gave
-    // 8.8 / 7.0 / 5.9 / 5.0 FP64 updates per RHS at 29.0-29.4 iterations (FP16N inner);
-    // FP32 inner kept its iteration count down to 0.001 (3.9 updates)
-    if (delta <= 0) delta = prec == LAPH_F16N ? 0.01 : (prec == LAPH_F32 ? 0.001 : 0.0);
+    // defaults measured on the 32^3 x 64 perambulator: delta 0.1 / 0.02 / 0.01 / 0.005 /
+    // 0.002 gave 8.8 / 5.9 / 5.0 / 4.45 / 4.0 FP64 updates per RHS at 29.0 / 29.2 / 29.4 /
+    // 29.7 / 30.2 iterations (FP16N inner); FP32 inner kept its iteration count down to
+    // 0.001 (3.9 updates)
+    if (delta <= 0) delta = prec == LAPH_F16N ? 0.005 : (prec == LAPH_F32 ? 0.001 : 0.0);
     const int maxiter = p.maxiter > 0 ? p.maxiter : 10000;
     for (int s = 0; s < ns; ++s) {
         SlotState z{};

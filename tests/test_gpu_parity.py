@@ -221,6 +221,27 @@ def test_solve_fp64_update_shapes(ragged, ragged_ref, prec, stencil64, tile64):
     assert all(s["status"] == "converged" and s["true_res"] <= 1e-10 and s["updates"] >= 2 for s in st), st
 
 
+# 16 x 8 x 4 x 4: 64 sites per parity are whole y rows, so the LDS-form stages run
+# their site blocks in 4-D tiles (4 z-planes x 4 timeslices, FP64 2 x 2)
+DIMS_TILED = (16, 8, 4, 4)
+
+
+@pytest.mark.parametrize("prec,stencil64", [("f16n", 2), ("f32", 1), ("f64", 0)])
+def test_solve_tiled_block_order(prec, stencil64):
+    import paper_2510_26313_amd as pl
+    U = ls.gauge_field(DIMS_TILED, 43)
+    lat = make_lattice(DIMS_TILED, U, masses=(0.05,))
+    b = ls.random_spinor(ls.spinor_shape(DIMS_TILED, 8), 5030)
+    x_ref, _ = solvers.bicgstab(dirac.WilsonClover(U, 0.05, 1.0).apply, b, tol=1e-13)
+    log_case("solve_tiled", prec=prec, stencil64=stencil64)
+    kw = dict(inner_prec=prec, rhs_tile=8, stencil=2, traversal=2)
+    if prec != "f64":
+        kw.update(stencil64=stencil64, rhs_tile64=4 if stencil64 == 1 else 8)
+    X, st = lat.solve_raw(dev(b), 0, 1e-10, pl.default_params(**kw))
+    assert per_rhs_rel(host(X), x_ref).max() < 1e-8, st
+    assert all(s["status"] == "converged" and s["true_res"] <= 1e-10 for s in st), st
+
+
 def test_solve_dagger(ragged, ragged_ref):
     import paper_2510_26313_amd as pl
     U, lat = ragged
