@@ -214,10 +214,11 @@ laph_status laph_time_stages(laph_ctx ctx, int prec, int nrhs, int stencil, int 
 /* Autotuner (the paper tunes launch parameters per machine, Sec. "QUDA"):
  * time every stencil form / RHS-per-link-load candidate for nrhs RHS of
  * mass_idx as laph_time_stages does, keep the fastest for this context and
- * (inner precision, nrhs), and return it (stencil 1 or 2, rhs_tile, traversal).
+ * (precision, nrhs), and return it (stencil 1 or 2, rhs_tile, traversal).
  * laph_solve / laph_perambulator with stencil = 0 and rhs_tile <= 0 use the
- * tuned choice for their batch size, tuning on first use on their own
- * workspace.  If the environment variable LAPH_TUNE_CACHE names a file,
+ * tuned choice for their inner precision and batch size, and with
+ * stencil64 = 0 and rhs_tile64 <= 0 the LAPH_F64 choice for the FP64
+ * reliable-update stages, tuning on first use on their own workspace.  If the environment variable LAPH_TUNE_CACHE names a file,
  * choices are appended there and read back by later contexts of the same
  * lattice.  work: laph_time_stages_workspace_bytes(ctx, prec, nrhs, 16). */
 laph_status laph_autotune(laph_ctx ctx, int prec, int nrhs, int mass_idx, void *work, size_t work_bytes,
