@@ -138,32 +138,40 @@ laph_status Solver::init(Ctx &ctx, int nslots, const laph_solve_params &params, 
     // autotuned shapes: reuse a choice for this (precision, batch) or measure one now,
     // for the inner iterations and for the FP64 stages of the reliable updates
     // (timed on the FP64 half-vectors E0..O0, not in use yet)
-    auto shape_of = [&](int pr, char *fields, Ctx::Shape &out) -> laph_status {
+    // found: whether a choice exists (errors of the tuning runs are returned)
+    auto shape_of = [&](int pr, char *fields, Ctx::Shape &out, bool &found) -> laph_status {
         auto it = ctx.tuned.find({pr, ns});
         if (it == ctx.tuned.end() && tune_mass >= 0) {
             Ctx::Shape sh{};
             LAPH_TRY(autotune_stencil(ctx, pr, ns, tune_mass, fields, ws.partials, ws.ints, &sh, nullptr));
             it = ctx.tuned.find({pr, ns});
         }
-        if (it == ctx.tuned.end()) return LAPH_ERR_INVALID;   // no choice: keep the defaults
-        out = it->second;
+        found = it != ctx.tuned.end();
+        if (found) out = it->second;
         return LAPH_OK;
     };
     Ctx::Shape sh{};
-    if (p.stencil == 0 && p.rhs_tile <= 0 && shape_of(prec, prec == LAPH_F64 ? ws.E0.base : ws.r.base, sh) == LAPH_OK) {
-        form = sh.form;
-        nr = sh.tile;
-        if (p.traversal == 0) site_major = sh.site_major;
-        if (prec == LAPH_F64) {
-            form64 = form;
-            nr64 = nr;
-            site_major64 = site_major;
+    bool found = false;
+    if (p.stencil == 0 && p.rhs_tile <= 0) {
+        LAPH_TRY(shape_of(prec, prec == LAPH_F64 ? ws.E0.base : ws.r.base, sh, found));
+        if (found) {
+            form = sh.form;
+            nr = sh.tile;
+            if (p.traversal == 0) site_major = sh.site_major;
+            if (prec == LAPH_F64) {
+                form64 = form;
+                nr64 = nr;
+                site_major64 = site_major;
+            }
         }
     }
-    if (prec != LAPH_F64 && p.stencil64 == 0 && p.rhs_tile64 <= 0 && shape_of(LAPH_F64, ws.E0.base, sh) == LAPH_OK) {
-        form64 = sh.form;
-        nr64 = sh.tile;
-        site_major64 = sh.site_major;
+    if (prec != LAPH_F64 && p.stencil64 == 0 && p.rhs_tile64 <= 0) {
+        LAPH_TRY(shape_of(LAPH_F64, ws.E0.base, sh, found));
+        if (found) {
+            form64 = sh.form;
+            nr64 = sh.tile;
+            site_major64 = sh.site_major;
+        }
     }
     for (int k = 0; k < 2; ++k) {
         const int f = k ? form64 : form, t = k ? nr64 : nr;
