@@ -54,7 +54,7 @@ laph_status launch_stage(const Ctx &c, const StageSpec &s) {
     a.site_major = s.site_major;
     a.grid_cap = s.grid_cap;
     lds_block_tiles(c, s, a);
-    a.slot_filter = s.flagged ? 1 : (s.active_only ? 2 : 0);
+    a.flag_filter = s.flagged;
     a.one = 1.0f;
     a.st = s.slots;
     a.partials = s.partials;

@@ -49,9 +49,7 @@ struct StageArgs {
     double *partials;
     float one;   // 1.0f, opaque to the compiler (keeps FP16N projections as mixed-precision FMAs)
     int grid_cap;   // launch only: at most this many workgroups (0: one per item)
-    // slots to skip: 0 none; 1 all but those flagged for a reliable update (LDS
-    // form; the register form takes FLAGGED); 2 all but the active ones
-    int slot_filter;
+    int flag_filter;   // LDS form: skip slots not flagged for a reliable update
     // LDS form: order of the 64-site blocks as 4-D tiles (nyb blocks of y rows x
     // tz z-planes x tt timeslices); tz == 0: memory order
     int nyb, tz, tt;
@@ -100,13 +98,6 @@ __device__ __forceinline__ int tiled_block(int L, int nyb, int tz, int tt, int l
     const int ztile = r % nzt;
     const int ttile = r / nzt;
     return ((ttile * tt + tl) * lz + ztile * tz + zl) * nyb + yb;
-}
-// Whether a slot takes part in a launch with the given slot filter.
-__device__ __forceinline__ bool slot_live(const StageArgs &A, int s) {
-    if (A.slot_filter == 0) return true;
-    const SlotState &st = A.st[s];
-    if (st.status != LAPH_RHS_ACTIVE) return false;
-    return A.slot_filter == 2 || st.flag != 0;
 }
 // grid of a stage launch: every item, or at most cap workgroups (cap > 0)
 inline int stage_grid(int items_max, int cap) {
@@ -338,7 +329,6 @@ __device__ __forceinline__ void stage_body(const StageArgs &A, int sb, int tile)
     for (int r = 0; r < NR; ++r) {
         int s = A.tile_slots[tile * NR + r];
         if (FLAGGED && s >= 0 && !(A.st[s].flag != 0 && A.st[s].status == LAPH_RHS_ACTIVE)) s = -1;
-        if (s >= 0 && A.slot_filter == 2 && A.st[s].status != LAPH_RHS_ACTIVE) s = -1;
         slots[r] = s;
         any |= s >= 0;
     }

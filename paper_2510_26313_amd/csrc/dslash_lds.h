@@ -45,15 +45,6 @@ __device__ __forceinline__ void stage_lds_body(const StageArgs &A, int sb, int t
     constexpr int NT = 4 * RW;
     __shared__ R lnk[8][18][kLdsSites];
     __shared__ int nbr[8][kLdsSites];
-    if (A.slot_filter) {
-        // a tile whose slots all sit out skips its link staging too (block-uniform)
-        bool any = false;
-        for (int k = 0; k < NT; ++k) {
-            const int s = A.tile_slots[tile * NT + k];
-            any |= s >= 0 && slot_live(A, s);
-        }
-        if (!any) return;
-    }
     const Geom &g = A.g;
     const int p = A.out_parity;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -115,7 +106,7 @@ __device__ __forceinline__ void stage_lds_body(const StageArgs &A, int sb, int t
     for (int rw = 0; rw < RW; ++rw) {
         const int slot = A.tile_slots[tile * NT + rw * 4 + wave];
         if (slot < 0) continue;   // wave-uniform
-        if (!slot_live(A, slot)) continue;   // wave-uniform
+        if (A.flag_filter && !(A.st[slot].flag != 0 && A.st[slot].status == LAPH_RHS_ACTIVE)) continue;
         double part[NQ > 0 ? NQ : 1];
 #pragma unroll
         for (int q = 0; q < (NQ > 0 ? NQ : 1); ++q) part[q] = 0.0;

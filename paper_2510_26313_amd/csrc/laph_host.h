@@ -122,7 +122,6 @@ struct StageSpec {
     int post = 0;     // number of post terms (0, 1, 2)
     int red = 0;
     int flagged = 0;  // only slots whose SlotState.flag != 0 (and status active)
-    int active_only = 0;   // only slots whose status is active (inner iterations)
     Operand in, out, y, y2, z, w;
     double a = 0, a2 = 0, b = 1, c = 0;
     Tiles tiles;

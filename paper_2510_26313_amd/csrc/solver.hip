@@ -305,7 +305,7 @@ constexpr int kFlaggedGrid = 2048;
 
 laph_status Solver::stage(int sprec, int out_parity, Operand in, Operand out, int clover, int pre, Operand z,
                           double cz, int post, Operand y, double a, Operand y2, double a2, double b, int red,
-                          Operand w, int flagged, int active_only) {
+                          Operand w, int flagged) {
     StageSpec s;
     s.prec = sprec;
     s.out_parity = out_parity;
@@ -327,7 +327,6 @@ laph_status Solver::stage(int sprec, int out_parity, Operand in, Operand out, in
     s.c = cz;
     const bool f64 = sprec == LAPH_F64;
     s.tiles = tiles(f64, flagged != 0);
-    s.active_only = active_only;
     s.form = f64 ? form64 : form;
     s.site_major = f64 ? site_major64 : site_major;
     // the flagged count is known only on the device: a small grid walks the live tiles
@@ -362,15 +361,15 @@ laph_status Solver::iteration() {
     BlasArgs a = blas(ns);
     FinArgs f = fin(ns);
     LAPH_TRY(blas_p_update(*c, a, prec));
-    // v = M_hat p,  <r^, v>  (the inner stages skip RHS that converged since the last poll)
-    LAPH_TRY(stage(prec, 1, ws.p, ws.tmp, 1, 0, none, 0, 0, none, 0, none, 0, 1.0, 0, none, 0, 1));
-    LAPH_TRY(stage(prec, 0, ws.tmp, ws.v, 1, 0, none, 0, 1, ws.p, 1.0, none, 0, -0.25, 1, ws.rh, 0, 1));
+    // v = M_hat p,  <r^, v>
+    LAPH_TRY(stage(prec, 1, ws.p, ws.tmp, 1, 0, none, 0, 0, none, 0, none, 0, 1.0, 0, none, 0));
+    LAPH_TRY(stage(prec, 0, ws.tmp, ws.v, 1, 0, none, 0, 1, ws.p, 1.0, none, 0, -0.25, 1, ws.rh, 0));
     LAPH_TRY(blas_finalize(*c, fin(ns, nsb_inner), kFinAlpha));
     // s = r - alpha v (in r)
     LAPH_TRY(blas_s_update(*c, a, prec));
     // t = M_hat s,  <t, s>, |t|^2
-    LAPH_TRY(stage(prec, 1, ws.r, ws.tmp, 1, 0, none, 0, 0, none, 0, none, 0, 1.0, 0, none, 0, 1));
-    LAPH_TRY(stage(prec, 0, ws.tmp, ws.t, 1, 0, none, 0, 1, ws.r, 1.0, none, 0, -0.25, 2, none, 0, 1));
+    LAPH_TRY(stage(prec, 1, ws.r, ws.tmp, 1, 0, none, 0, 0, none, 0, none, 0, 1.0, 0, none, 0));
+    LAPH_TRY(stage(prec, 0, ws.tmp, ws.t, 1, 0, none, 0, 1, ws.r, 1.0, none, 0, -0.25, 2, none, 0));
     LAPH_TRY(blas_finalize(*c, fin(ns, nsb_inner), kFinOmega));
     // x_lo += alpha p + omega s;  r = s - omega t;  rho, |r|^2, update decision
     LAPH_TRY(blas_xr_update(*c, a, prec));
