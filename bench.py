@@ -142,8 +142,9 @@ def _solve_summary(st, n, dt):
 def extra_suite(laph, torch):
     """Secondary measurements of the other workloads (outside the timed region):
     16^3x32 single-RHS solves per inner precision, the 24^3x48 four-mass batched
-    solve against the plain FP64 single-RHS solver, and the forward / backward
-    times of the differentiable perambulator at 16^3x32."""
+    solve against the plain FP64 single-RHS solver, the forward / backward times of
+    the differentiable perambulator at 16^3x32, and the LapH vectors (64 lowest
+    eigenpairs of -Delta per timeslice) at 32^3x64."""
     out = {}
     tol = 1e-10
     # 16^3 x 32: 128 RHS at t0 = 0, one RHS after another
@@ -217,6 +218,31 @@ def extra_suite(laph, torch):
               "backward_over_forward": round(tb / tf, 3), "grad_m0": float(m0.grad)}
     out["16x16x16x32_gradients"] = c3
     del lat, Vd
+    torch.cuda.empty_cache()
+
+    # 32^3 x 64: the 64 lowest eigenpairs of -Delta on all 64 timeslices (the LapH vectors)
+    cfg = ls.CONFIGS["c4"]
+    dims = cfg["dims"]
+    lat = laph.Lattice(dims)
+    lat.load_gauge(torch.from_numpy(ls.gauge_field(dims, cfg["seed_u"])).cuda())
+    (V, lam, info), dt = _timed(torch, lambda: lat.laplacian_eigvecs(cfg["nev"], tol=1e-10))
+    X = V[:, :8].contiguous()
+    lat.apply_laplacian(X)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        lat.apply_laplacian(X)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    vs = dims[0] * dims[1] * dims[2]
+    # algorithmic bytes per vector and site: in + out (96 B) + 6 links (864 B) / 4 vectors per link load
+    gb = (8 * 96 + 8 / 4 * 864) * vs * dims[3] / (ms * 1e-3) / 1e9
+    out["32x32x32x64_laph_vectors_nev64"] = {
+        "seconds": round(dt, 3), "iterations": info["iters"], "max_residual": info["residual"],
+        "lowest_eigenvalue": float(lam.min()), "largest_returned_eigenvalue": float(lam.max()),
+        "laplacian_8vec_ms": round(ms, 4), "laplacian_8vec_gbs": round(gb, 1)}
+    del lat, V, X
     torch.cuda.empty_cache()
     return out
 

@@ -193,6 +193,31 @@ laph_status laph_project(laph_ctx ctx, double *tau, const double *X, const doubl
 laph_status laph_project_adjoint(laph_ctx ctx, double *GX, const double *Gtau, const double *V,
                                  int nev, int nev_src);
 
+/* LapH vectors on the GPU (Sec. "LapH", "QUDA": the LapH subspace of each time
+ * slice is spanned by the lowest eigenvectors of the gauge-covariant 3-D
+ * Laplacian).  -Delta acts on colour fields of one timeslice,
+ *   (-Delta f)(x) = sum_{k=x,y,z} [2 f(x) - U_k(x) f(x+k) - U_k(x-k)^dagger f(x-k)],
+ * periodic, with the loaded gauge field's spatial links.
+ *  laph_apply_laplacian: out[t][j] = (-Delta) in[t][j] for every timeslice t and
+ *    j < nvec; in, out: c128 [Lt][nvec][Lz][Ly][Lx][3] device arrays (no aliasing).
+ *  laph_laplacian_eigvecs: the nev lowest eigenpairs of -Delta on every timeslice
+ *    (1 <= nev <= 64) by Chebyshev-filtered subspace iteration on the device:
+ *    V = c128 [Lt][nev][Lz][Ly][Lx][3] (device; the layout laph_perambulator
+ *    takes), each vector of unit norm with its largest-modulus component real
+ *    positive (the lowest index among those within 1e-12 of the largest);
+ *    lambda_host = [Lt][nev] ascending.  It stops when every returned pair has
+ *    ||(-Delta) v - lambda v|| <= tol (absolute; the spectrum lies in [0, 12]) or
+ *    after max_iter iterations (then LAPH_ERR_NOCONV; V is not written).  degree:
+ *    Chebyshev filter degree per iteration (<= 1: 16).  iters_host and
+ *    residual_host (may be null) receive the iterations used and the largest
+ *    residual norm.  work: laph_laplacian_workspace_bytes(ctx, nev) bytes of device
+ *    memory (about 4 Lt (nev + nev/2) 3 Lx Ly Lz complex doubles). */
+size_t laph_laplacian_workspace_bytes(laph_ctx ctx, int nev);
+laph_status laph_apply_laplacian(laph_ctx ctx, double *out, const double *in, int nvec);
+laph_status laph_laplacian_eigvecs(laph_ctx ctx, double *V, double *lambda_host, int nev, double tol, int max_iter,
+                                   int degree, void *work, size_t work_bytes, int *iters_host,
+                                   double *residual_host);
+
 /* Milliseconds of the last laph_solve / laph_perambulator split as
  * [0] total, [1] solve, [2] projection (HIP events on the context stream). */
 laph_status laph_last_timings(laph_ctx ctx, double *ms_host3);

@@ -58,6 +58,10 @@ _SIGS = [
     ("laph_perambulator", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_double,
                                   P(SolveParams), P(RhsStats), c_void_p, c_size_t]),
     ("laph_make_sources", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int]),
+    ("laph_laplacian_workspace_bytes", c_size_t, [c_void_p, c_int]),
+    ("laph_apply_laplacian", c_int, [c_void_p, c_void_p, c_void_p, c_int]),
+    ("laph_laplacian_eigvecs", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_double, c_int, c_int, c_void_p,
+                                       c_size_t, P(c_int), P(c_double)]),
     ("laph_project_workspace_bytes", c_size_t, [c_void_p, c_int, c_int]),
     ("laph_project", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p, c_size_t]),
     ("laph_project_adjoint", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int]),

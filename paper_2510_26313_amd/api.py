@@ -8,6 +8,7 @@ canonical layouts documented in ``include/laph.h``.
 import contextlib
 import ctypes
 
+import numpy as np
 import torch
 
 from . import _lib as L
@@ -228,6 +229,28 @@ class Lattice:
         L.check(self._run(self.lib.laph_autotune, self.ctx, L.PREC[prec], nrhs, mass_idx, _ptr(w), w.numel(),
                           ctypes.byref(st), ctypes.byref(tile), ctypes.byref(trav), ctypes.byref(ms)))
         return dict(stencil=st.value, rhs_tile=tile.value, traversal=trav.value, ms=ms.value)
+
+    def apply_laplacian(self, X):
+        """(-Delta) X on every timeslice; X: complex128 [Lt][nvec][Lz][Ly][Lx][3] on the device."""
+        nvec = X.shape[1]
+        _check_tensor(X, self.laph_shape(nvec), "X")
+        out = torch.empty_like(X)
+        L.check(self._run(self.lib.laph_apply_laplacian, self.ctx, _ptr(out), _ptr(X), nvec))
+        return out
+
+    def laplacian_eigvecs(self, nev, tol=1e-10, max_iter=200, degree=16):
+        """Lowest nev eigenpairs of -Delta on every timeslice: (V [Lt][nev][Lz][Ly][Lx][3]
+        on the device, eigenvalues [Lt][nev] (numpy), dict(iters, residual))."""
+        lt = self.dims[3]
+        V = torch.empty(self.laph_shape(nev), dtype=torch.complex128, device=self.device)
+        lam = np.zeros((lt, nev))
+        w = self._workspace(self.lib.laph_laplacian_workspace_bytes(self.ctx, nev))
+        its, res = ctypes.c_int(0), ctypes.c_double(0)
+        st = self._run(self.lib.laph_laplacian_eigvecs, self.ctx, _ptr(V),
+                       lam.ctypes.data_as(ctypes.c_void_p), int(nev), float(tol), int(max_iter), int(degree),
+                       _ptr(w), w.numel(), ctypes.byref(its), ctypes.byref(res))
+        L.check(st)
+        return V, lam, dict(iters=its.value, residual=res.value)
 
     def make_sources(self, V, t0):
         nev = V.shape[1]

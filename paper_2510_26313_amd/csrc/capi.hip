@@ -464,6 +464,26 @@ laph_status laph_perambulator(laph_ctx h, double *tau, const double *V, int nev,
     return LAPH_OK;
 }
 
+size_t laph_laplacian_workspace_bytes(laph_ctx h, int nev) {
+    if (!h || nev < 1 || nev > 64) return 0;
+    return laplacian_eig_workspace_bytes(C(h), nev);
+}
+
+laph_status laph_apply_laplacian(laph_ctx h, double *out, const double *in, int nvec) {
+    LAPH_TRY(check_ctx(h, true, false));
+    if (!out || !in || nvec <= 0 || nvec > 65535 || out == in) return set_error(LAPH_ERR_INVALID, "bad arguments");
+    return apply_neg_laplacian(C(h), out, in, nvec);
+}
+
+laph_status laph_laplacian_eigvecs(laph_ctx h, double *V, double *lambda_host, int nev, double tol, int max_iter,
+                                   int degree, void *work, size_t work_bytes, int *iters_host,
+                                   double *residual_host) {
+    LAPH_TRY(check_ctx(h, true, false));
+    if (!V || !lambda_host) return set_error(LAPH_ERR_INVALID, "null V or lambda");
+    return laplacian_eigvecs(C(h), V, lambda_host, nev, tol, max_iter, degree, reinterpret_cast<char *>(work),
+                             work_bytes, iters_host, residual_host);
+}
+
 laph_status laph_make_sources(laph_ctx h, double *B, const double *V, int nev, int t0) {
     LAPH_TRY(check_ctx(h));
     Ctx &c = C(h);

@@ -43,6 +43,14 @@ laph_status project(const Ctx &c, const ProjectSpec &s);
 laph_status project_adjoint(const Ctx &c, double *GX, const double *Gtau, const double *V, int nev, int nev_src);
 laph_status make_sources_canonical(const Ctx &c, double *B, const double *V, int nev, int t0);
 
+// LapH eigenvectors (laplace.hip): out[t][j] = (-Delta) in[t][j] per timeslice, and the
+// lowest nev eigenpairs of -Delta on every timeslice (Chebyshev-filtered subspace
+// iteration; V[t][l][z][y][x][a], lambda_host[t][l] ascending).
+laph_status apply_neg_laplacian(const Ctx &c, double *out, const double *in, int nvec);
+size_t laplacian_eig_workspace_bytes(const Ctx &c, int nev);
+laph_status laplacian_eigvecs(Ctx &c, double *V, double *lambda_host, int nev, double tol, int max_iter, int degree,
+                              char *work, size_t bytes, int *iters_out, double *res_host);
+
 class Solver {
    public:
     struct WS {

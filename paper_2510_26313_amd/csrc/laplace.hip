@@ -1,0 +1,740 @@
+// LapH eigenvectors on the GPU: the lowest nev eigenpairs of the gauge-covariant
+// 3-D Laplacian -Delta on every timeslice (the paper's Sec. "LapH" / "QUDA": the
+// LapH subspace is spanned by the lowest eigenvectors of the gauge-covariant
+// Laplacian of each time slice; computing them on the GPU is the paper's new step).
+//
+// (-Delta f)(x) = sum_{k=x,y,z} [2 f(x) - U_k(x) f(x+k) - U_k(x-k)^dagger f(x-k)],
+// periodic, no boundary phase; spectrum inside [0, 12] for unitary links.
+//
+// Method: Chebyshev-filtered subspace iteration, all timeslices at once.  Per
+// iteration and timeslice, a block of m = nev + guard vectors is filtered by the
+// degree-d Chebyshev polynomial that damps [lambda_cut, 12] (lambda_cut = the
+// largest Ritz value of the block), made orthonormal by three Loewdin passes
+// (Hermitian eigendecomposition of the Gram matrix, Y <- Y Q Lambda^{-1/2}; the
+// first pass shifted by 1e-15 of the largest Gram eigenvalue), and rotated to Ritz
+// vectors by a Rayleigh-Ritz step; it stops when every one of the nev lowest Ritz
+// pairs has ||(-Delta) y - lambda y|| <= tol.  Every vector operation runs here:
+// the stencil (register-tiled over vectors, FP64), the Gram matrices (FP64 matrix
+// cores), the small Hermitian eigenproblems (cyclic Jacobi in one workgroup per
+// timeslice, matrix in LDS), the block rotations and the residual norms.
+//
+// Layout of a block: [t][j][z][y][x][a] complex double (the canonical V layout),
+// vectors of one timeslice contiguous.
+#include <cmath>
+#include <initializer_list>
+#include <vector>
+
+#include "laph_solver.h"
+
+namespace laph {
+
+namespace {
+
+constexpr int kLB = 256;          // threads per block of the vector kernels
+constexpr int kLapNV = 4;         // vectors per thread in the stencil
+constexpr int kRotNJ = 16;        // output vectors per thread in the rotation
+constexpr int kEigMaxM = 96;      // largest block (Jacobi matrix in LDS)
+constexpr int kJB = 256;          // threads of the Jacobi workgroup
+constexpr int kGT = 64;           // Gram tile (rows and columns)
+constexpr int kGKC = 16;          // Gram K chunk
+constexpr int kLmax = 12;         // upper bound of the spectrum
+
+// ---- stencil: out = ca[t] (-Delta) in + cb[t] in + cc[t] z ------------------------
+struct LapArgs {
+    Geom g;
+    GaugePtrs gp;
+    const double2 *in, *z;
+    double2 *out;
+    int m;                  // vectors per timeslice in the block
+    int nvec;               // vectors to process (first nvec of each timeslice)
+    const double *coef;     // [lt][3] (ca, cb, cc); null: (1, 0, 0)
+};
+
+__device__ __forceinline__ void site3(const Geom &g, int s, int &x, int &y, int &z) {
+    x = s % g.lx;
+    const int r = s / g.lx;
+    y = r % g.ly;
+    z = r / g.ly;
+}
+
+__global__ __launch_bounds__(kLB) void lap_kernel(LapArgs A) {
+    const Geom &g = A.g;
+    const int vs = g.lx * g.ly * g.lz;
+    const int s = blockIdx.x * kLB + threadIdx.x;
+    const int j0 = blockIdx.y * kLapNV;
+    const int t = blockIdx.z;
+    if (s >= vs) return;
+    int x, y, z;
+    site3(g, s, x, y, z);
+    const size_t tb = (size_t)t * A.m;
+    cplx<double> acc[kLapNV][3];
+#pragma unroll
+    for (int v = 0; v < kLapNV; ++v)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) acc[v][a] = {0.0, 0.0};
+    // fully unrolled: the direction indexes a local array (no scratch)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+#pragma unroll
+        for (int fb = 0; fb < 2; ++fb) {
+            int n[3] = {x, y, z};
+            const int ext = k == 0 ? g.lx : (k == 1 ? g.ly : g.lz);
+            n[k] = fb == 0 ? (n[k] + 1 == ext ? 0 : n[k] + 1) : (n[k] == 0 ? ext - 1 : n[k] - 1);
+            const int sn = n[0] + g.lx * (n[1] + g.ly * n[2]);
+            // forward: U_k(x) f(x+k); backward: U_k(x-k)^dagger f(x-k)
+            const int lx_ = fb == 0 ? x : n[0], ly_ = fb == 0 ? y : n[1], lz_ = fb == 0 ? z : n[2];
+            const int par = (lx_ + ly_ + lz_ + t) & 1;
+            const int h = cb_index(g, lx_, ly_, lz_, t);
+            cplx<double> L[9];
+            GaugeIO<F64>::load(A.gp, par, k, g.vh, h, L);
+#pragma unroll
+            for (int v = 0; v < kLapNV; ++v) {
+                if (j0 + v >= A.nvec) break;
+                const double2 *f = A.in + ((tb + j0 + v) * vs + sn) * 3;
+                cplx<double> fn[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) fn[a] = {f[a].x, f[a].y};
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        if (fb == 0)
+                            cmac(acc[v][a], L[a * 3 + b], fn[b]);
+                        else
+                            cmac_conj(acc[v][a], L[b * 3 + a], fn[b]);
+                    }
+            }
+        }
+    }
+    double ca = 1.0, cb = 0.0, cc = 0.0;
+    if (A.coef) {
+        ca = A.coef[3 * t];
+        cb = A.coef[3 * t + 1];
+        cc = A.coef[3 * t + 2];
+    }
+#pragma unroll
+    for (int v = 0; v < kLapNV; ++v) {
+        if (j0 + v >= A.nvec) break;
+        const size_t e = ((tb + j0 + v) * vs + s) * 3;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double2 f = A.in[e + a];
+            // (-Delta f) = 6 f - hops
+            double re = ca * (6.0 * f.x - acc[v][a].re) + cb * f.x;
+            double im = ca * (6.0 * f.y - acc[v][a].im) + cb * f.y;
+            if (A.z) {
+                const double2 zz = A.z[e + a];
+                re += cc * zz.x;
+                im += cc * zz.y;
+            }
+            A.out[e + a] = make_double2(re, im);
+        }
+    }
+}
+
+// ---- Gram matrices C[t][i][j] = sum_e conj(P[t][i][e]) R[t][j][e] ---------------------
+using d4 = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+
+struct GramArgs {
+    const double2 *P, *R;   // blocks [lt][m][ne]
+    int m, ne, lt;
+    int ntile;              // tiles per dimension
+    int nsplit, nchunk;
+    double2 *scratch;       // [split][lt][m][m]
+};
+
+__global__ __launch_bounds__(256) void gram_kernel(GramArgs A) {
+    __shared__ double Pr[kGT][kGKC + 1], Pi[kGT][kGKC + 1], Rr[kGT][kGKC + 1], Ri[kGT][kGKC + 1];
+    int bid = blockIdx.x;
+    const int split = bid % A.nsplit;
+    bid /= A.nsplit;
+    const int tj = bid % A.ntile;
+    bid /= A.ntile;
+    const int ti = bid % A.ntile;
+    const int t = bid / A.ntile;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    d4 cre[4], cim[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        cre[j] = d4{0, 0, 0, 0};
+        cim[j] = d4{0, 0, 0, 0};
+    }
+    const int c0 = (int)((long)A.nchunk * split / A.nsplit), c1 = (int)((long)A.nchunk * (split + 1) / A.nsplit);
+    const int krow = tid & 15, rsub = tid >> 4;
+    for (int ch = c0; ch < c1; ++ch) {
+        const int e = ch * kGKC + krow;
+        const bool kin = e < A.ne;
+#pragma unroll
+        for (int q = 0; q < kGT / 16; ++q) {
+            const int r = rsub + 16 * q;
+            const int i = ti * kGT + r, jj = tj * kGT + r;
+            double2 pv = make_double2(0, 0), rv = make_double2(0, 0);
+            if (kin && i < A.m) pv = A.P[((size_t)t * A.m + i) * A.ne + e];
+            if (kin && jj < A.m) rv = A.R[((size_t)t * A.m + jj) * A.ne + e];
+            Pr[r][krow] = pv.x;
+            Pi[r][krow] = pv.y;
+            Rr[r][krow] = rv.x;
+            Ri[r][krow] = rv.y;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k4 = 0; k4 < kGKC; k4 += 4) {
+            const int arow = wave * 16 + (lane & 15);
+            const int kk = k4 + (lane >> 4);
+            const double ar = Pr[arow][kk], ai = Pi[arow][kk], nai = -ai;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int bcol = q * 16 + (lane & 15);
+                const double br = Rr[bcol][kk], bi = Ri[bcol][kk];
+                // conj(P) R = (Pr Rr + Pi Ri) + i (Pr Ri - Pi Rr)
+                cre[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, cre[q], 0, 0, 0);
+                cre[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, cre[q], 0, 0, 0);
+                cim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, cim[q], 0, 0, 0);
+                cim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, br, cim[q], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // the 16x16x4 FP64 MFMA leaves C[row][col] in lane col + 16 (row % 4), register row / 4
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int j = tj * kGT + q * 16 + (lane & 15);
+        if (j >= A.m) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = ti * kGT + wave * 16 + (lane >> 4) + 4 * r;
+            if (i >= A.m) continue;
+            A.scratch[(((size_t)split * A.lt + t) * A.m + i) * A.m + j] = make_double2(cre[q][r], cim[q][r]);
+        }
+    }
+}
+
+__global__ void gram_reduce_kernel(GramArgs A, double2 *C) {
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    const long total = (long)A.lt * A.m * A.m;
+    if (idx >= total) return;
+    double2 s = make_double2(0, 0);
+    for (int sp = 0; sp < A.nsplit; ++sp) {
+        const double2 v = A.scratch[(size_t)sp * total + idx];
+        s.x += v.x;
+        s.y += v.y;
+    }
+    C[idx] = s;
+}
+
+// ---- Hermitian eigensolver: cyclic Jacobi, round-robin parallel ordering ---------------
+// One workgroup per timeslice.  C[t] (m x m, made Hermitian) -> eigenvalues w[t][m]
+// ascending and Z[t][k][j]: mode 0 the eigenvector matrix, mode 1 Q Lambda^{-1/2}
+// (columns of the Gram matrix's eigenvectors scaled; shift added to the eigenvalues).
+struct JacArgs {
+    const double2 *C;     // [lt][m][m]
+    double2 *Q;           // [lt][m][m] work (eigenvectors, columns)
+    double2 *Z;           // [lt][m][m] output
+    double *w;            // [lt][m] output
+    int m;
+    int mode;
+    double shift_rel;     // mode 1: shift = shift_rel * largest eigenvalue
+    int max_sweeps;
+};
+
+__global__ __launch_bounds__(kJB) void jacobi_kernel(JacArgs A) {
+    __shared__ double hr[kEigMaxM * kEigMaxM], hi[kEigMaxM * kEigMaxM];
+    __shared__ double rc[kEigMaxM / 2], rs[kEigMaxM / 2], rer[kEigMaxM / 2], rei[kEigMaxM / 2];
+    __shared__ int rp[kEigMaxM / 2], rq[kEigMaxM / 2];
+    __shared__ double red[kJB / 64][2];
+    __shared__ int order[kEigMaxM];
+    const int m = A.m, t = blockIdx.x, tid = threadIdx.x;
+    const double2 *C = A.C + (size_t)t * m * m;
+    double2 *Q = A.Q + (size_t)t * m * m;
+    for (int e = tid; e < m * m; e += kJB) {
+        const int i = e / m, j = e - i * m;
+        const double2 a = C[i * m + j], b = C[j * m + i];
+        hr[e] = 0.5 * (a.x + b.x);   // (C + C^dagger) / 2
+        hi[e] = 0.5 * (a.y - b.y);
+        Q[e] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    const int half = m / 2;
+    for (int sweep = 0; sweep < A.max_sweeps; ++sweep) {
+        // off-diagonal and total Frobenius norms (block reduction, fixed order)
+        double off = 0, tot = 0;
+        for (int e = tid; e < m * m; e += kJB) {
+            const double v = hr[e] * hr[e] + hi[e] * hi[e];
+            tot += v;
+            if (e / m != e % m) off += v;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            off += __shfl_xor(off, o, 64);
+            tot += __shfl_xor(tot, o, 64);
+        }
+        if ((tid & 63) == 0) {
+            red[tid >> 6][0] = off;
+            red[tid >> 6][1] = tot;
+        }
+        __syncthreads();
+        off = tot = 0;
+        for (int wv = 0; wv < kJB / 64; ++wv) {
+            off += red[wv][0];
+            tot += red[wv][1];
+        }
+        __syncthreads();
+        if (!(off > 1e-30 * tot) || tot == 0.0) break;   // uniform over the block
+        for (int r = 0; r < m - 1; ++r) {
+            // pairs of this round (circle method: player 0 fixed, the others rotate)
+            if (tid < half) {
+                auto player = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + r) % (m - 1); };
+                int p = player(tid), q = player(m - 1 - tid);
+                if (p > q) {
+                    const int tmp = p;
+                    p = q;
+                    q = tmp;
+                }
+                const double a = hr[p * m + p], d = hr[q * m + q];
+                const double br = hr[p * m + q], bi = hi[p * m + q];
+                const double ab = sqrt(br * br + bi * bi);
+                double c = 1.0, s = 0.0, er = 1.0, ei = 0.0;
+                if (ab > 1e-300) {
+                    er = br / ab;
+                    ei = bi / ab;
+                    const double tau = (d - a) / (2.0 * ab);
+                    const double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    c = 1.0 / sqrt(1.0 + tt * tt);
+                    s = tt * c;
+                }
+                rp[tid] = p;
+                rq[tid] = q;
+                rc[tid] = c;
+                rs[tid] = s;
+                rer[tid] = er;
+                rei[tid] = ei;
+            }
+            __syncthreads();
+            // J = [[c, s], [-s conj(e), c conj(e)]] on (p, q).  Rows: H <- J^dagger H
+            for (int e = tid; e < half * m; e += kJB) {
+                const int k = e / m, col = e - k * m;
+                const int p = rp[k], q = rq[k];
+                const double c = rc[k], s = rs[k], er = rer[k], ei = rei[k];
+                const double pr = hr[p * m + col], pi = hi[p * m + col];
+                const double qr = hr[q * m + col], qi = hi[q * m + col];
+                // conj(j00) = c, conj(j10) = -s e, conj(j01) = s, conj(j11) = c e
+                hr[p * m + col] = c * pr - s * (er * qr - ei * qi);
+                hi[p * m + col] = c * pi - s * (er * qi + ei * qr);
+                hr[q * m + col] = s * pr + c * (er * qr - ei * qi);
+                hi[q * m + col] = s * pi + c * (er * qi + ei * qr);
+            }
+            __syncthreads();
+            // columns: H <- H J, Q <- Q J
+            for (int e = tid; e < half * m; e += kJB) {
+                const int k = e / m, row = e - k * m;
+                const int p = rp[k], q = rq[k];
+                const double c = rc[k], s = rs[k], er = rer[k], ei = rei[k];
+                // j00 = c, j10 = -s conj(e), j01 = s, j11 = c conj(e)
+                {
+                    const double pr = hr[row * m + p], pi = hi[row * m + p];
+                    const double qr = hr[row * m + q], qi = hi[row * m + q];
+                    hr[row * m + p] = c * pr - s * (qr * er + qi * ei);
+                    hi[row * m + p] = c * pi - s * (qi * er - qr * ei);
+                    hr[row * m + q] = s * pr + c * (qr * er + qi * ei);
+                    hi[row * m + q] = s * pi + c * (qi * er - qr * ei);
+                }
+                {
+                    const double2 qp = Q[row * m + p], qq = Q[row * m + q];
+                    Q[row * m + p] = make_double2(c * qp.x - s * (qq.x * er + qq.y * ei),
+                                                  c * qp.y - s * (qq.y * er - qq.x * ei));
+                    Q[row * m + q] = make_double2(s * qp.x + c * (qq.x * er + qq.y * ei),
+                                                  s * qp.y + c * (qq.y * er - qq.x * ei));
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // ascending order (ties by index), eigenvalues and the output matrix
+    for (int i = tid; i < m; i += kJB) order[i] = i;
+    __syncthreads();
+    for (int i = tid; i < m; i += kJB) {
+        const double wi = hr[i * m + i];
+        int rank = 0;
+        for (int j = 0; j < m; ++j) {
+            const double wj = hr[j * m + j];
+            rank += (wj < wi) || (wj == wi && j < i);
+        }
+        order[rank] = i;
+    }
+    __syncthreads();
+    double wmax = hr[0];
+    for (int i = 1; i < m; ++i) wmax = fmax(wmax, hr[i * m + i]);
+    const double shift = A.mode == 1 ? A.shift_rel * wmax : 0.0;
+    for (int e = tid; e < m * m; e += kJB) {
+        const int k = e / m, j = e - k * m;
+        const int src = min(max(order[j], 0), m - 1);
+        double2 v = Q[k * m + src];
+        if (A.mode == 1) {
+            const double lam = fmax(hr[src * m + src], 0.0) + shift;
+            const double sc = lam > 0 ? 1.0 / sqrt(lam) : 0.0;
+            v.x *= sc;
+            v.y *= sc;
+        }
+        A.Z[(size_t)t * m * m + e] = v;
+    }
+    for (int j = tid; j < m; j += kJB) {
+        const int src = min(max(order[j], 0), m - 1);
+        A.w[(size_t)t * m + j] = hr[src * m + src];
+    }
+}
+
+// ---- block rotation: out[t][j] = sum_k in[t][k] Z[t][k][j] (first nout columns) ---------
+struct RotArgs {
+    const double2 *in;
+    double2 *out;
+    const double2 *Z;       // [lt][m][m]
+    int m, ne, nout, mout;  // out block has mout vectors per timeslice
+};
+
+__global__ __launch_bounds__(kLB) void rotate_kernel(RotArgs A) {
+    __shared__ double zr[kEigMaxM][kRotNJ], zi[kEigMaxM][kRotNJ];
+    const int e = blockIdx.x * kLB + threadIdx.x;
+    const int j0 = blockIdx.y * kRotNJ;
+    const int t = blockIdx.z;
+    for (int q = threadIdx.x; q < A.m * kRotNJ; q += kLB) {
+        const int k = q / kRotNJ, jj = q - k * kRotNJ;
+        double2 v = make_double2(0, 0);
+        if (j0 + jj < A.nout) v = A.Z[((size_t)t * A.m + k) * A.m + j0 + jj];
+        zr[k][jj] = v.x;
+        zi[k][jj] = v.y;
+    }
+    __syncthreads();
+    if (e >= A.ne) return;
+    double ar[kRotNJ], ai[kRotNJ];
+#pragma unroll
+    for (int jj = 0; jj < kRotNJ; ++jj) ar[jj] = ai[jj] = 0.0;
+    for (int k = 0; k < A.m; ++k) {
+        const double2 x = A.in[((size_t)t * A.m + k) * A.ne + e];
+#pragma unroll
+        for (int jj = 0; jj < kRotNJ; ++jj) {
+            ar[jj] += x.x * zr[k][jj] - x.y * zi[k][jj];
+            ai[jj] += x.x * zi[k][jj] + x.y * zr[k][jj];
+        }
+    }
+#pragma unroll
+    for (int jj = 0; jj < kRotNJ; ++jj)
+        if (j0 + jj < A.nout) A.out[((size_t)t * A.mout + j0 + jj) * A.ne + e] = make_double2(ar[jj], ai[jj]);
+}
+
+// ---- residual norms: r2[t][j] = || W[t][j] - w[t][j] Y[t][j] ||^2 -----------------------
+__global__ __launch_bounds__(kLB) void residual_kernel(const double2 *Y, const double2 *W, const double *w, double *r2,
+                                                       int m, int ne, int nvec) {
+    __shared__ double red[kLB / 64];
+    const int j = blockIdx.x, t = blockIdx.y;
+    if (j >= nvec) return;
+    const double lam = w[(size_t)t * m + j];
+    const double2 *y = Y + ((size_t)t * m + j) * ne, *wv = W + ((size_t)t * m + j) * ne;
+    double s = 0;
+    for (int e = threadIdx.x; e < ne; e += kLB) {
+        const double dr = wv[e].x - lam * y[e].x, di = wv[e].y - lam * y[e].y;
+        s += dr * dr + di * di;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0;
+        for (int q = 0; q < kLB / 64; ++q) tot += red[q];
+        r2[(size_t)t * m + j] = tot;
+    }
+}
+
+// ---- start block: a counter-based pseudo-random complex field per (t, j, e) -------------
+__device__ __forceinline__ double hash_unit(unsigned long long k) {
+    // splitmix64 finaliser, mapped to (-1, 1)
+    k += 0x9E3779B97F4A7C15ull;
+    k = (k ^ (k >> 30)) * 0xBF58476D1CE4E5B9ull;
+    k = (k ^ (k >> 27)) * 0x94D049BB133111EBull;
+    k ^= k >> 31;
+    return (double)(k >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+__global__ __launch_bounds__(kLB) void start_kernel(double2 *X, int m, int ne, int lt) {
+    const long idx = (long)blockIdx.x * kLB + threadIdx.x;
+    const long total = (long)lt * m * ne;
+    if (idx >= total) return;
+    X[idx] = make_double2(hash_unit(2ull * (unsigned long long)idx), hash_unit(2ull * (unsigned long long)idx + 1));
+}
+
+// ---- phase convention and output -------------------------------------------------------
+// The largest-modulus component real positive (the lowest index among those within
+// 1e-12 of the largest), then the vector is written to V[t][l].
+__global__ __launch_bounds__(kLB) void phase_out_kernel(const double2 *Y, double2 *V, int m, int ne, int nev) {
+    __shared__ double redd[kLB / 64];
+    __shared__ int redi[kLB / 64];
+    __shared__ double2 ph;
+    const int l = blockIdx.x, t = blockIdx.y;
+    const double2 *y = Y + ((size_t)t * m + l) * ne;
+    double mx = 0;
+    for (int e = threadIdx.x; e < ne; e += kLB) mx = fmax(mx, sqrt(y[e].x * y[e].x + y[e].y * y[e].y));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if ((threadIdx.x & 63) == 0) redd[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    mx = redd[0];
+    for (int q = 1; q < kLB / 64; ++q) mx = fmax(mx, redd[q]);
+    int idx = ne;
+    for (int e = threadIdx.x; e < ne; e += kLB)
+        if (sqrt(y[e].x * y[e].x + y[e].y * y[e].y) >= mx - 1e-12 && e < idx) idx = e;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) idx = min(idx, __shfl_xor(idx, o, 64));
+    if ((threadIdx.x & 63) == 0) redi[threadIdx.x >> 6] = idx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int i = redi[0];
+        for (int q = 1; q < kLB / 64; ++q) i = min(i, redi[q]);
+        const double2 v = y[i];
+        const double a = sqrt(v.x * v.x + v.y * v.y);
+        ph = a > 0 ? make_double2(v.x / a, -v.y / a) : make_double2(1, 0);   // conj(v) / |v|
+    }
+    __syncthreads();
+    const double2 p = ph;
+    double2 *out = V + ((size_t)t * nev + l) * ne;
+    for (int e = threadIdx.x; e < ne; e += kLB) {
+        const double2 v = y[e];
+        out[e] = make_double2(v.x * p.x - v.y * p.y, v.x * p.y + v.y * p.x);
+    }
+}
+
+// ---- host side -----------------------------------------------------------------------------
+struct EigWS {
+    double2 *b[4];          // four blocks [lt][m][ne]
+    double2 *C, *Q, *Z;     // [lt][m][m]
+    double2 *gscratch;      // Gram partials
+    double *w, *r2, *coef;  // [lt][m], [lt][m], [2][lt][3]
+};
+
+int eig_block(int nev) {
+    int m = nev + (nev / 2 > 8 ? nev / 2 : 8);
+    m += m & 1;
+    return m > kEigMaxM ? kEigMaxM : m;
+}
+
+void gram_shape(int m, int ne, int lt, int &ntile, int &nsplit, int &nchunk) {
+    ntile = (m + kGT - 1) / kGT;
+    nchunk = (ne + kGKC - 1) / kGKC;
+    const int base = lt * ntile * ntile;
+    nsplit = (2048 + base - 1) / base;
+    if (nsplit > nchunk) nsplit = nchunk;
+    if (nsplit > 64) nsplit = 64;
+    if (nsplit < 1) nsplit = 1;
+}
+
+size_t eig_layout(const Ctx &c, int nev, char *base, EigWS *ws) {
+    const int m = eig_block(nev), lt = c.g.lt;
+    const int ne = 3 * c.g.lx * c.g.ly * c.g.lz;
+    int ntile, nsplit, nchunk;
+    gram_shape(m, ne, lt, ntile, nsplit, nchunk);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += round256(bytes);
+        return base ? base + o : nullptr;
+    };
+    EigWS w;
+    for (int k = 0; k < 4; ++k) w.b[k] = reinterpret_cast<double2 *>(take((size_t)lt * m * ne * 16));
+    w.C = reinterpret_cast<double2 *>(take((size_t)lt * m * m * 16));
+    w.Q = reinterpret_cast<double2 *>(take((size_t)lt * m * m * 16));
+    w.Z = reinterpret_cast<double2 *>(take((size_t)lt * m * m * 16));
+    w.gscratch = reinterpret_cast<double2 *>(take((size_t)nsplit * lt * m * m * 16));
+    w.w = reinterpret_cast<double *>(take((size_t)lt * m * 8));
+    w.r2 = reinterpret_cast<double *>(take((size_t)lt * m * 8));
+    w.coef = reinterpret_cast<double *>(take((size_t)lt * 6 * 8));
+    if (ws) *ws = w;
+    return off;
+}
+
+struct EigRun {
+    const Ctx &c;
+    EigWS ws;
+    int m, ne, lt, vs;
+
+    laph_status lap(const double2 *in, const double2 *z, double2 *out, const double *coef) const {
+        LapArgs a;
+        a.g = c.g;
+        a.gp = c.gp;
+        a.in = in;
+        a.z = z;
+        a.out = out;
+        a.m = m;
+        a.nvec = m;
+        a.coef = coef;
+        dim3 grid((vs + kLB - 1) / kLB, (m + kLapNV - 1) / kLapNV, lt);
+        hipLaunchKernelGGL(lap_kernel, grid, dim3(kLB), 0, c.stream, a);
+        return check_launch("lap_kernel");
+    }
+    laph_status gram(const double2 *P, const double2 *R) const {
+        GramArgs a;
+        a.P = P;
+        a.R = R;
+        a.m = m;
+        a.ne = ne;
+        a.lt = lt;
+        gram_shape(m, ne, lt, a.ntile, a.nsplit, a.nchunk);
+        a.scratch = ws.gscratch;
+        hipLaunchKernelGGL(gram_kernel, dim3(lt * a.ntile * a.ntile * a.nsplit), dim3(256), 0, c.stream, a);
+        LAPH_TRY(check_launch("gram_kernel"));
+        const long total = (long)lt * m * m;
+        hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c.stream, a,
+                           ws.C);
+        return check_launch("gram_reduce_kernel");
+    }
+    laph_status jacobi(int mode, double shift_rel) const {
+        JacArgs a;
+        a.C = ws.C;
+        a.Q = ws.Q;
+        a.Z = ws.Z;
+        a.w = ws.w;
+        a.m = m;
+        a.mode = mode;
+        a.shift_rel = shift_rel;
+        a.max_sweeps = 40;
+        hipLaunchKernelGGL(jacobi_kernel, dim3(lt), dim3(kJB), 0, c.stream, a);
+        return check_launch("jacobi_kernel");
+    }
+    laph_status rotate(const double2 *in, double2 *out) const {
+        RotArgs a;
+        a.in = in;
+        a.out = out;
+        a.Z = ws.Z;
+        a.m = m;
+        a.ne = ne;
+        a.nout = m;
+        a.mout = m;
+        dim3 grid((ne + kLB - 1) / kLB, (m + kRotNJ - 1) / kRotNJ, lt);
+        hipLaunchKernelGGL(rotate_kernel, grid, dim3(kLB), 0, c.stream, a);
+        return check_launch("rotate_kernel");
+    }
+};
+
+}  // namespace
+
+size_t laplacian_eig_workspace_bytes(const Ctx &c, int nev) { return eig_layout(c, nev, nullptr, nullptr); }
+
+laph_status apply_neg_laplacian(const Ctx &c, double *out, const double *in, int nvec) {
+    LapArgs a;
+    a.g = c.g;
+    a.gp = c.gp;
+    a.in = reinterpret_cast<const double2 *>(in);
+    a.z = nullptr;
+    a.out = reinterpret_cast<double2 *>(out);
+    a.m = nvec;
+    a.nvec = nvec;
+    a.coef = nullptr;
+    const int vs = c.g.lx * c.g.ly * c.g.lz;
+    dim3 grid((vs + kLB - 1) / kLB, (nvec + kLapNV - 1) / kLapNV, c.g.lt);
+    hipLaunchKernelGGL(lap_kernel, grid, dim3(kLB), 0, c.stream, a);
+    return check_launch("lap_kernel");
+}
+
+laph_status laplacian_eigvecs(Ctx &c, double *V, double *lam_host, int nev, double tol, int max_iter, int degree,
+                              char *work, size_t bytes, int *iters_out, double *res_host) {
+    const int m = eig_block(nev);
+    if (nev < 1 || nev > 64 || m <= nev) return set_error(LAPH_ERR_INVALID, "nev must be in 1..64");
+    if (!(tol > 0) || max_iter < 1) return set_error(LAPH_ERR_INVALID, "tol must be positive and max_iter >= 1");
+    const size_t need = eig_layout(c, nev, nullptr, nullptr);
+    if (!work || bytes < need) return set_error(LAPH_ERR_WORKSPACE, "workspace too small: %zu < %zu", bytes, need);
+    EigRun R{c, {}, m, 3 * c.g.lx * c.g.ly * c.g.lz, c.g.lt, c.g.lx * c.g.ly * c.g.lz};
+    eig_layout(c, nev, work, &R.ws);
+    const int lt = R.lt, ne = R.ne;
+    double2 *const *B = R.ws.b;
+    // buffer roles by index into B: x = current block; the others are scratch
+    int x = 0;
+    auto other = [&](std::initializer_list<int> used) {
+        for (int k = 0; k < 4; ++k) {
+            bool u = false;
+            for (int v : used) u |= v == k;
+            if (!u) return k;
+        }
+        return -1;
+    };
+    // Loewdin: three passes Y <- Y Q Lambda^{-1/2} of the Gram matrix (first pass shifted)
+    auto loewdin = [&](int &cur) -> laph_status {
+        for (int pass = 0; pass < 3; ++pass) {
+            const int sp = other({cur});
+            LAPH_TRY(R.gram(B[cur], B[cur]));
+            LAPH_TRY(R.jacobi(1, pass == 0 ? 1e-15 : 0.0));
+            LAPH_TRY(R.rotate(B[cur], B[sp]));
+            cur = sp;
+        }
+        return LAPH_OK;
+    };
+    {
+        const long total = (long)lt * m * ne;
+        hipLaunchKernelGGL(start_kernel, dim3((unsigned)((total + kLB - 1) / kLB)), dim3(kLB), 0, c.stream, B[x], m,
+                           ne, lt);
+        LAPH_TRY(check_launch("start_kernel"));
+    }
+    LAPH_TRY(loewdin(x));
+    std::vector<double> cut(lt, 0.5 * kLmax), coef(6 * (size_t)lt), w((size_t)lt * m), r2((size_t)lt * m);
+    const int deg = degree >= 2 ? degree : 16;
+    int it = 0;
+    bool done = false;
+    double worst = INFINITY;
+    while (it < max_iter && !done) {
+        ++it;
+        // Chebyshev filter on [cut_t, 12]: Y1 = (A - c) X / e;  Y_{k+1} = 2 (A - c) Y_k / e - Y_{k-1}
+        for (int t = 0; t < lt; ++t) {
+            const double cc = 0.5 * (cut[t] + kLmax), ee = 0.5 * (kLmax - cut[t]);
+            coef[3 * t] = 1.0 / ee;
+            coef[3 * t + 1] = -cc / ee;
+            coef[3 * t + 2] = 0.0;
+            coef[3 * (lt + t)] = 2.0 / ee;
+            coef[3 * (lt + t) + 1] = -2.0 * cc / ee;
+            coef[3 * (lt + t) + 2] = -1.0;
+        }
+        LAPH_HIP(hipMemcpyAsync(R.ws.coef, coef.data(), coef.size() * 8, hipMemcpyHostToDevice, c.stream));
+        // the copy reads the host vector asynchronously: wait before it can change
+        LAPH_HIP(hipStreamSynchronize(c.stream));
+        int prev = x, curr = other({x});
+        LAPH_TRY(R.lap(B[prev], nullptr, B[curr], R.ws.coef));
+        for (int k = 2; k <= deg; ++k) {
+            const int next = other({prev, curr});
+            LAPH_TRY(R.lap(B[curr], B[prev], B[next], R.ws.coef + 3 * lt));
+            prev = curr;
+            curr = next;
+        }
+        int blk = curr;
+        LAPH_TRY(loewdin(blk));
+        // Rayleigh-Ritz: H = Y^dagger (A Y); Ritz vectors Y Q and A Y Q; residual norms
+        const int wb = other({blk});
+        LAPH_TRY(R.lap(B[blk], nullptr, B[wb], nullptr));
+        LAPH_TRY(R.gram(B[blk], B[wb]));
+        LAPH_TRY(R.jacobi(0, 0.0));
+        const int ry = other({blk, wb}), rw = other({blk, wb, ry});
+        LAPH_TRY(R.rotate(B[blk], B[ry]));
+        LAPH_TRY(R.rotate(B[wb], B[rw]));
+        hipLaunchKernelGGL(residual_kernel, dim3(m, lt), dim3(kLB), 0, c.stream, B[ry], B[rw], R.ws.w, R.ws.r2, m, ne,
+                           m);
+        LAPH_TRY(check_launch("residual_kernel"));
+        LAPH_HIP(hipMemcpyAsync(w.data(), R.ws.w, w.size() * 8, hipMemcpyDeviceToHost, c.stream));
+        LAPH_HIP(hipMemcpyAsync(r2.data(), R.ws.r2, r2.size() * 8, hipMemcpyDeviceToHost, c.stream));
+        LAPH_HIP(hipStreamSynchronize(c.stream));
+        worst = 0;
+        for (int t = 0; t < lt; ++t) {
+            for (int j = 0; j < nev; ++j) worst = fmax(worst, sqrt(r2[(size_t)t * m + j]));
+            cut[t] = w[(size_t)t * m + m - 1];
+        }
+        if (!std::isfinite(worst)) return set_error(LAPH_ERR_NONFINITE, "non-finite residual in the eigensolver");
+        done = worst <= tol;
+        x = ry;   // the Ritz block starts the next iteration
+    }
+    if (iters_out) *iters_out = it;
+    if (res_host) *res_host = worst;
+    if (!done) return set_error(LAPH_ERR_NOCONV, "eigensolver did not reach tol in %d iterations", max_iter);
+    hipLaunchKernelGGL(phase_out_kernel, dim3(nev, lt), dim3(kLB), 0, c.stream, B[x], reinterpret_cast<double2 *>(V),
+                       m, ne, nev);
+    LAPH_TRY(check_launch("phase_out_kernel"));
+    for (int t = 0; t < lt; ++t)
+        for (int j = 0; j < nev; ++j) lam_host[(size_t)t * nev + j] = w[(size_t)t * m + j];
+    LAPH_HIP(hipStreamSynchronize(c.stream));
+    return LAPH_OK;
+}
+
+}  // namespace laph
