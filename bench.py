@@ -220,7 +220,13 @@ def extra_suite(laph, torch):
     del lat, Vd
     torch.cuda.empty_cache()
 
-    # 32^3 x 64: the 64 lowest eigenpairs of -Delta on all 64 timeslices (the LapH vectors)
+    out["32x32x32x64_laph_vectors_nev64"] = laph_vectors_run(laph, torch)
+    return out
+
+
+def laph_vectors_run(laph, torch):
+    """The 64 lowest eigenpairs of -Delta on all 64 timeslices of 32^3 x 64 (the LapH
+    vectors), and the Laplacian stencil's rate on 8 vectors per timeslice."""
     cfg = ls.CONFIGS["c4"]
     dims = cfg["dims"]
     lat = laph.Lattice(dims)
@@ -238,13 +244,13 @@ def extra_suite(laph, torch):
     vs = dims[0] * dims[1] * dims[2]
     # algorithmic bytes per vector and site: in + out (96 B) + 6 links (864 B) / 4 vectors per link load
     gb = (8 * 96 + 8 / 4 * 864) * vs * dims[3] / (ms * 1e-3) / 1e9
-    out["32x32x32x64_laph_vectors_nev64"] = {
-        "seconds": round(dt, 3), "iterations": info["iters"], "max_residual": info["residual"],
-        "lowest_eigenvalue": float(lam.min()), "largest_returned_eigenvalue": float(lam.max()),
-        "laplacian_8vec_ms": round(ms, 4), "laplacian_8vec_gbs": round(gb, 1)}
+    res = {"seconds": round(dt, 3), "iterations": info["iters"], "max_residual": info["residual"],
+           "lowest_eigenvalue": float(lam.min()), "largest_returned_eigenvalue": float(lam.max()),
+           "laplacian_8vec_ms": round(ms, 4), "laplacian_8vec_gbs": round(gb, 1),
+           "laplacian_8vec_hbm_frac": round(gb / HBM_PEAK_GBS, 4)}
     del lat, V, X
     torch.cuda.empty_cache()
-    return out
+    return res
 
 
 def stage_key(args, dims):
@@ -291,6 +297,9 @@ def main():
     ap.add_argument("--fp64-sample", type=int, default=4, help="RHS for the plain FP64 single-RHS comparison")
     ap.add_argument("--extra", action="store_true",
                     help="also measure the 16^3x32 single-RHS, 24^3x48 four-mass and gradient workloads")
+    ap.add_argument("--laph-vectors", action="store_true",
+                    help="only compute the LapH vectors of the 32^3x64 lattice (64 per timeslice) and print "
+                         "their timing as one JSON line")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch the dominant stage (and a 2 GiB copy for the counter scale), for "
                          "rocprofv3 --pmc runs; needs --stencil, --rhs-tile and --traversal")
@@ -307,6 +316,10 @@ def main():
     dims = cfg["dims"]
     if args.pmc_probe:
         pmc_probe(args, cfg, torch, laph)
+        return
+    if args.laph_vectors:
+        print(json.dumps({"workload": "LapH vectors 32x32x32x64, 64 lowest eigenpairs of -Delta per timeslice, "
+                                      "tol 1e-10", **laph_vectors_run(laph, torch)}), flush=True)
         return
     nev = cfg["nev"]
     m0 = cfg["masses"][0]
