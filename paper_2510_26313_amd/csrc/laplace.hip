@@ -9,12 +9,12 @@
 // Method: Chebyshev-filtered subspace iteration, all timeslices at once.  Per
 // iteration and timeslice, a block of m = nev + guard vectors is filtered by the
 // degree-d Chebyshev polynomial that damps [lambda_cut, 12] (lambda_cut = the
-// largest Ritz value of the block), made orthonormal by three Loewdin passes
+// largest Ritz value of the block), made orthonormal by two Loewdin passes
 // (Hermitian eigendecomposition of the Gram matrix, Y <- Y Q Lambda^{-1/2}; the
 // first pass shifted by 1e-15 of the largest Gram eigenvalue), and rotated to Ritz
 // vectors by a Rayleigh-Ritz step; it stops when every one of the nev lowest Ritz
 // pairs has ||(-Delta) y - lambda y|| <= tol.  Every vector operation runs here:
-// the stencil (register-tiled over vectors, FP64), the Gram matrices (FP64 matrix
+// the stencil (links staged in LDS once per block of sites for all vectors, FP64), the Gram matrices (FP64 matrix
 // cores), the small Hermitian eigenproblems (cyclic Jacobi in one workgroup per
 // timeslice, matrix in LDS), the block rotations and the residual norms.
 //
@@ -31,8 +31,7 @@ namespace laph {
 namespace {
 
 constexpr int kLB = 256;          // threads per block of the vector kernels
-constexpr int kLapNV = 4;         // vectors per thread in the stencil
-constexpr int kRotNJ = 16;        // output vectors per thread in the rotation
+constexpr int kRotNJ = 32;        // output vectors per thread in the rotation
 constexpr int kEigMaxM = 96;      // largest block (Jacobi matrix in LDS)
 constexpr int kJB = 256;          // threads of the Jacobi workgroup
 constexpr int kGT = 64;           // Gram tile (rows and columns)
@@ -57,71 +56,91 @@ __device__ __forceinline__ void site3(const Geom &g, int s, int &x, int &y, int 
     z = r / g.ly;
 }
 
+// A workgroup owns kLapSites sites of one timeslice: its threads first stage the 6
+// links of those sites in LDS (backward ones already as U^dagger) with the
+// neighbour indices, then each wave runs two vectors at a time (lanes 0-31 and
+// 32-63), so every link is read from HBM once for all vectors of the block.
+constexpr int kLapSites = 32;
+
 __global__ __launch_bounds__(kLB) void lap_kernel(LapArgs A) {
+    __shared__ double lnk[6][18][kLapSites];
+    __shared__ int nbr[6][kLapSites];
     const Geom &g = A.g;
     const int vs = g.lx * g.ly * g.lz;
-    const int s = blockIdx.x * kLB + threadIdx.x;
-    const int j0 = blockIdx.y * kLapNV;
-    const int t = blockIdx.z;
-    if (s >= vs) return;
-    int x, y, z;
-    site3(g, s, x, y, z);
-    const size_t tb = (size_t)t * A.m;
-    cplx<double> acc[kLapNV][3];
+    const int t = blockIdx.y;
+    const int s0 = blockIdx.x * kLapSites;
+    // ---- phase 1: links and neighbours (thread -> (hop, site))
+    for (int q = threadIdx.x; q < 6 * kLapSites; q += kLB) {
+        const int hop = q / kLapSites, site = q - hop * kLapSites;
+        const int s = s0 + site;
+        const int k = hop >> 1, fb = hop & 1;
+        cplx<double> L[9];
+        int sn = 0;
+        if (s < vs) {
+            int x, y, z;
+            site3(g, s, x, y, z);
+            int nx = x, ny = y, nz = z;
+            if (k == 0) nx = fb == 0 ? (x + 1 == g.lx ? 0 : x + 1) : (x == 0 ? g.lx - 1 : x - 1);
+            if (k == 1) ny = fb == 0 ? (y + 1 == g.ly ? 0 : y + 1) : (y == 0 ? g.ly - 1 : y - 1);
+            if (k == 2) nz = fb == 0 ? (z + 1 == g.lz ? 0 : z + 1) : (z == 0 ? g.lz - 1 : z - 1);
+            sn = nx + g.lx * (ny + g.ly * nz);
+            // forward: U_k(x); backward: U_k(x - k)^dagger
+            const int lx_ = fb == 0 ? x : nx, ly_ = fb == 0 ? y : ny, lz_ = fb == 0 ? z : nz;
+            GaugeIO<F64>::load(A.gp, (lx_ + ly_ + lz_ + t) & 1, k, g.vh, cb_index(g, lx_, ly_, lz_, t), L);
+        } else {
 #pragma unroll
-    for (int v = 0; v < kLapNV; ++v)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) acc[v][a] = {0.0, 0.0};
-    // fully unrolled: the direction indexes a local array (no scratch)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-#pragma unroll
-        for (int fb = 0; fb < 2; ++fb) {
-            int n[3] = {x, y, z};
-            const int ext = k == 0 ? g.lx : (k == 1 ? g.ly : g.lz);
-            n[k] = fb == 0 ? (n[k] + 1 == ext ? 0 : n[k] + 1) : (n[k] == 0 ? ext - 1 : n[k] - 1);
-            const int sn = n[0] + g.lx * (n[1] + g.ly * n[2]);
-            // forward: U_k(x) f(x+k); backward: U_k(x-k)^dagger f(x-k)
-            const int lx_ = fb == 0 ? x : n[0], ly_ = fb == 0 ? y : n[1], lz_ = fb == 0 ? z : n[2];
-            const int par = (lx_ + ly_ + lz_ + t) & 1;
-            const int h = cb_index(g, lx_, ly_, lz_, t);
-            cplx<double> L[9];
-            GaugeIO<F64>::load(A.gp, par, k, g.vh, h, L);
-#pragma unroll
-            for (int v = 0; v < kLapNV; ++v) {
-                if (j0 + v >= A.nvec) break;
-                const double2 *f = A.in + ((tb + j0 + v) * vs + sn) * 3;
-                cplx<double> fn[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) fn[a] = {f[a].x, f[a].y};
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-#pragma unroll
-                    for (int b = 0; b < 3; ++b) {
-                        if (fb == 0)
-                            cmac(acc[v][a], L[a * 3 + b], fn[b]);
-                        else
-                            cmac_conj(acc[v][a], L[b * 3 + a], fn[b]);
-                    }
-            }
+            for (int e = 0; e < 9; ++e) L[e] = {0.0, 0.0};
         }
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const cplx<double> e = fb == 0 ? L[a * 3 + b] : conj(L[b * 3 + a]);
+                lnk[hop][2 * (a * 3 + b)][site] = e.re;
+                lnk[hop][2 * (a * 3 + b) + 1][site] = e.im;
+            }
+        nbr[hop][site] = sn;
     }
+    __syncthreads();
+    // ---- phase 2: vectors, two per wave per round
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int site = lane & (kLapSites - 1), vsub = lane >> 5;
+    const int s = s0 + site;
+    if (s >= vs) return;
     double ca = 1.0, cb = 0.0, cc = 0.0;
     if (A.coef) {
         ca = A.coef[3 * t];
         cb = A.coef[3 * t + 1];
         cc = A.coef[3 * t + 2];
     }
+    const size_t tb = (size_t)t * A.m;
+#pragma unroll 1
+    for (int j = 2 * wave + vsub; j < A.nvec; j += 2 * (kLB / 64)) {
+        const double2 *vin = A.in + (tb + j) * vs * 3;
+        cplx<double> acc[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
 #pragma unroll
-    for (int v = 0; v < kLapNV; ++v) {
-        if (j0 + v >= A.nvec) break;
-        const size_t e = ((tb + j0 + v) * vs + s) * 3;
+        for (int hop = 0; hop < 6; ++hop) {
+            const double2 *f = vin + (size_t)nbr[hop][site] * 3;
+            cplx<double> fn[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) fn[a] = {f[a].x, f[a].y};
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    const cplx<double> l = {lnk[hop][2 * (a * 3 + b)][site], lnk[hop][2 * (a * 3 + b) + 1][site]};
+                    cmac(acc[a], l, fn[b]);
+                }
+            // one hop at a time: hoisting all six hops' loads costs occupancy
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        const size_t e = ((tb + j) * vs + s) * 3;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const double2 f = A.in[e + a];
             // (-Delta f) = 6 f - hops
-            double re = ca * (6.0 * f.x - acc[v][a].re) + cb * f.x;
-            double im = ca * (6.0 * f.y - acc[v][a].im) + cb * f.y;
+            double re = ca * (6.0 * f.x - acc[a].re) + cb * f.x;
+            double im = ca * (6.0 * f.y - acc[a].im) + cb * f.y;
             if (A.z) {
                 const double2 zz = A.z[e + a];
                 re += cc * zz.x;
@@ -565,7 +584,7 @@ struct EigRun {
         a.m = m;
         a.nvec = m;
         a.coef = coef;
-        dim3 grid((vs + kLB - 1) / kLB, (m + kLapNV - 1) / kLapNV, lt);
+        dim3 grid((vs + kLapSites - 1) / kLapSites, lt);
         hipLaunchKernelGGL(lap_kernel, grid, dim3(kLB), 0, c.stream, a);
         return check_launch("lap_kernel");
     }
@@ -628,7 +647,7 @@ laph_status apply_neg_laplacian(const Ctx &c, double *out, const double *in, int
     a.nvec = nvec;
     a.coef = nullptr;
     const int vs = c.g.lx * c.g.ly * c.g.lz;
-    dim3 grid((vs + kLB - 1) / kLB, (nvec + kLapNV - 1) / kLapNV, c.g.lt);
+    dim3 grid((vs + kLapSites - 1) / kLapSites, c.g.lt);
     hipLaunchKernelGGL(lap_kernel, grid, dim3(kLB), 0, c.stream, a);
     return check_launch("lap_kernel");
 }
@@ -654,9 +673,10 @@ laph_status laplacian_eigvecs(Ctx &c, double *V, double *lam_host, int nev, doub
         }
         return -1;
     };
-    // Loewdin: three passes Y <- Y Q Lambda^{-1/2} of the Gram matrix (first pass shifted)
+    // Loewdin: two passes Y <- Y Q Lambda^{-1/2} of the Gram matrix (the first shifted;
+    // the second restores orthonormality to rounding)
     auto loewdin = [&](int &cur) -> laph_status {
-        for (int pass = 0; pass < 3; ++pass) {
+        for (int pass = 0; pass < 2; ++pass) {
             const int sp = other({cur});
             LAPH_TRY(R.gram(B[cur], B[cur]));
             LAPH_TRY(R.jacobi(1, pass == 0 ? 1e-15 : 0.0));

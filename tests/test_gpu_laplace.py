@@ -99,3 +99,19 @@ def test_eigvecs_full_lattice_residuals():
         assert _residuals(U[t], Vt, lam[t]).max() <= 1e-9
         g = Vt.reshape(nev, -1).conj() @ Vt.reshape(nev, -1).T
         assert np.abs(g - np.eye(nev)).max() <= 1e-12
+
+
+def test_perambulator_from_gpu_laph_vectors():
+    """The whole pipeline on C0: LapH vectors from the GPU eigensolver, then the fused
+    perambulator, against the oracle's dense-inverse perambulator on the oracle's vectors."""
+    import paper_2510_26313_amd as pl
+    cfg = ls.CONFIGS["c0"]
+    dims = cfg["dims"]
+    U = ls.gauge_field(dims, cfg["seed_u"])
+    lat = make_lattice(dims, U, masses=cfg["masses"], csw=cfg["csw"])
+    log_case("pipeline", dims=dims, nev=cfg["nev"])
+    V, lam, info = lat.laplacian_eigvecs(cfg["nev"], tol=1e-12)
+    tau, st = lat.perambulator_raw(V, 0, 0, 1e-12, pl.default_params(inner_prec="f64"))
+    Vref, _, _ = olaph.laplacian_eigvecs(U, cfg["nev"])
+    ref, _ = olaph.perambulator(U, Vref, 0, cfg["masses"][0], method="dense")
+    assert np.linalg.norm(host(tau) - ref) <= 1e-9 * np.linalg.norm(ref)
