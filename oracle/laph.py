@@ -155,3 +155,43 @@ def fd_source(D, V, b, d, t_sink, h=1e-4, tol=1e-13):
     lp = loss_of_sources(D, V, b + h * d, t_sink, tol)[0]
     lm = loss_of_sources(D, V, b - h * d, t_sink, tol)[0]
     return (lp - lm) / (2 * h)
+
+
+# --- meson doublets and baryon triplets of the LapH vectors ----------------------
+#
+# The LapH vectors also build the quark-antiquark doublets and three-quark triplets
+# that enter the Wick contractions of meson and baryon correlators (Sec. "QUDA").
+# The paper names them only; the definitions below are the standard momentum-
+# projected, undisplaced forms, with p = 2 pi (nx / Lx, ny / Ly, nz / Lz):
+#
+#     Phi_p[t][l][m]     = sum_x exp(-i p.x) sum_a conj(V_l(x, t)_a) V_m(x, t)_a
+#     B_p[t][l][m][n]    = sum_x exp(-i p.x) sum_{a,b,c} eps_abc V_l(x, t)_a V_m(x, t)_b V_n(x, t)_c
+
+def levi_civita():
+    """eps_abc of three colours: +1 on even permutations of (0, 1, 2), -1 on odd ones."""
+    eps = np.zeros((3, 3, 3))
+    for a, b, c in ((0, 1, 2), (1, 2, 0), (2, 0, 1)):
+        eps[a, b, c] = 1.0
+        eps[a, c, b] = -1.0
+    return eps
+
+
+def momentum_phases(dims3, moms):
+    """exp(-i p.x) on one timeslice, [n_mom][z][y][x], for integer momenta (nx, ny, nz)."""
+    lx, ly, lz = dims3
+    z, y, x = np.meshgrid(np.arange(lz), np.arange(ly), np.arange(lx), indexing="ij")
+    return np.array([np.exp(-2j * np.pi * (nx * x / lx + ny * y / ly + nz * z / lz)) for nx, ny, nz in moms])
+
+
+def meson_doublets(V, moms):
+    """Phi[p][t][l][m] = sum_x exp(-i p.x) sum_a conj(V_l(x, t)_a) V_m(x, t)_a."""
+    lt, nev, lz, ly, lx, _ = V.shape
+    ph = momentum_phases((lx, ly, lz), moms)
+    return np.einsum("pzyx,tlzyxa,tmzyxa->ptlm", ph, np.conj(V), V, optimize=True)
+
+
+def baryon_triplets(V, moms):
+    """B[p][t][l][m][n] = sum_x exp(-i p.x) eps_abc V_l(x, t)_a V_m(x, t)_b V_n(x, t)_c."""
+    lt, nev, lz, ly, lx, _ = V.shape
+    ph = momentum_phases((lx, ly, lz), moms)
+    return np.einsum("pzyx,abc,tlzyxa,tmzyxb,tnzyxc->ptlmn", ph, levi_civita(), V, V, V, optimize=True)

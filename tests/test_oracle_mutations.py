@@ -4,7 +4,8 @@ Each case patches one oracle function with a wrong variant (wrong projector
 sign, missing boundary phase, wrong mass normalisation, no trace removal,
 flipped clover sign, a leaf built from the wrong links, a reversed leaf, a
 Laplacian sign slip, a conjugate on the wrong factor of the projection, a
-missing gamma5 in the adjoint) and asserts that the named pin now fails.
+missing gamma5 in the adjoint, the doublets' conjugate or phase sign, a triplet
+epsilon sign or a conjugated triplet factor) and asserts that the named pin now fails.
 Everything runs on the CPU; nothing here touches the GPU library.
 """
 import numpy as np
@@ -88,6 +89,32 @@ def _adjoint_no_g5(D, V, b, t_sink, tol=1e-13):
     return L, Z, -float(np.sum(np.real(np.conj(Z) * X))), X
 
 
+def _doublets_no_conj(V, moms):
+    lt, nev, lz, ly, lx, _ = V.shape
+    ph = laph.momentum_phases((lx, ly, lz), moms)
+    return np.einsum("pzyx,tlzyxa,tmzyxa->ptlm", ph, V, V)
+
+
+def _doublets_phase_sign(V, moms):
+    lt, nev, lz, ly, lx, _ = V.shape
+    ph = np.conj(laph.momentum_phases((lx, ly, lz), moms))
+    return np.einsum("pzyx,tlzyxa,tmzyxa->ptlm", ph, np.conj(V), V)
+
+
+def _triplets_one_eps_sign(V, moms):
+    lt, nev, lz, ly, lx, _ = V.shape
+    ph = laph.momentum_phases((lx, ly, lz), moms)
+    eps = laph.levi_civita()
+    eps[2, 0, 1] = -1.0
+    return np.einsum("pzyx,abc,tlzyxa,tmzyxb,tnzyxc->ptlmn", ph, eps, V, V, V)
+
+
+def _triplets_conj_first(V, moms):
+    lt, nev, lz, ly, lx, _ = V.shape
+    ph = laph.momentum_phases((lx, ly, lz), moms)
+    return np.einsum("pzyx,abc,tlzyxa,tmzyxb,tnzyxc->ptlmn", ph, laph.levi_civita(), np.conj(V), V, V)
+
+
 CASES = [
     ("hop projector sign", dirac, "hop", _hop_flipped, pins.test_free_field_plane_wave),
     ("no antiperiodic phase", dirac, "hop", _hop_periodic, pins.test_free_field_propagator_closed_form),
@@ -99,6 +126,12 @@ CASES = [
     ("laplacian sign", laph, "neg_laplacian_apply", _neg_lap_wrong_sign, pins.test_free_laplacian_spectrum),
     ("projection conjugate", laph, "project", _project_conj_x, pins.test_free_field_perambulator_and_mass_derivative),
     ("adjoint without gamma5", laph, "adjoint_gradients", _adjoint_no_g5, pins.test_adjoint_gradients_vs_fd),
+    ("doublet without conjugate", laph, "meson_doublets", _doublets_no_conj, pins.test_doublets_zero_momentum_identity),
+    ("doublet phase sign", laph, "meson_doublets", _doublets_phase_sign, pins.test_doublets_triplets_free_plane_waves),
+    ("triplet epsilon sign", laph, "baryon_triplets", _triplets_one_eps_sign,
+     pins.test_doublets_triplets_gauge_invariance),
+    ("triplet conjugated factor", laph, "baryon_triplets", _triplets_conj_first,
+     pins.test_doublets_triplets_gauge_invariance),
 ]
 
 

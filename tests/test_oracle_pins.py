@@ -443,6 +443,111 @@ def test_sources_layout():
 
 
 # ---------------------------------------------------------------------------
+# meson doublets and baryon triplets of the LapH vectors
+# ---------------------------------------------------------------------------
+
+# eps_abc written out: even permutations of (0, 1, 2) +1, odd ones -1
+EPS_LIT = {(0, 1, 2): 1, (1, 2, 0): 1, (2, 0, 1): 1, (0, 2, 1): -1, (2, 1, 0): -1, (1, 0, 2): -1}
+
+PW_MODES = [((0, 0, 0), 0), ((1, 0, 0), 1), ((0, 1, 0), 2), ((1, 1, 0), 0), ((3, 0, 0), 1), ((0, 0, 1), 2),
+            ((2, 3, 1), 1), ((0, 0, 0), 2), ((3, 3, 3), 0)]
+PW_MOMS = [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 3, 1), (-1, 0, 2), (3, 2, 1)]
+
+
+def _plane_wave_vectors(dims, modes):
+    """V_j(x, t) = exp(+2 pi i k_j . x / L) e_{c_j} / sqrt(Lx Ly Lz) on every timeslice."""
+    lx, ly, lz, lt = dims
+    z, y, x = np.meshgrid(np.arange(lz), np.arange(ly), np.arange(lx), indexing="ij")
+    V = np.zeros((lt, len(modes), lz, ly, lx, 3), dtype=np.complex128)
+    for j, ((kx, ky, kz), c) in enumerate(modes):
+        V[:, j, :, :, :, c] = np.exp(2j * np.pi * (kx * x / lx + ky * y / ly + kz * z / lz)) / np.sqrt(lx * ly * lz)
+    return V
+
+
+def test_doublets_triplets_free_plane_waves():
+    """Plane-wave colour vectors give closed forms (momenta mod L):
+    Phi_p[j][j'] = delta_{c c'} delta(k' - k = p),
+    B_p[j1][j2][j3] = eps_{c1 c2 c3} (L^3)^(-1/2) delta(k1 + k2 + k3 = p)."""
+    L = 4
+    dims = (L, L, L, 2)
+    V = _plane_wave_vectors(dims, PW_MODES)
+    phi = laph.meson_doublets(V, PW_MOMS)
+    B = laph.baryon_triplets(V, PW_MOMS)
+    assert phi.shape == (len(PW_MOMS), 2, len(PW_MODES), len(PW_MODES))
+    assert B.shape == (len(PW_MOMS), 2) + (len(PW_MODES),) * 3
+
+    def same(q, r):
+        return all((q[d] - r[d]) % L == 0 for d in range(3))
+
+    for ip, p in enumerate(PW_MOMS):
+        for j, (k, c) in enumerate(PW_MODES):
+            for jj, (kk, cc) in enumerate(PW_MODES):
+                want = float(c == cc and same([kk[d] - k[d] for d in range(3)], p))
+                assert np.abs(phi[ip, :, j, jj] - want).max() < 1e-13
+        for j1, (k1, c1) in enumerate(PW_MODES):
+            for j2, (k2, c2) in enumerate(PW_MODES):
+                for j3, (k3, c3) in enumerate(PW_MODES):
+                    ksum = [k1[d] + k2[d] + k3[d] for d in range(3)]
+                    want = EPS_LIT.get((c1, c2, c3), 0) / L ** 1.5 if same(ksum, p) else 0.0
+                    assert np.abs(B[ip, :, j1, j2, j3] - want).max() < 1e-13
+
+
+def test_doublets_zero_momentum_identity():
+    """Phi at p = 0 of orthonormal vectors is the identity on every timeslice."""
+    dims = (4, 4, 2, 3)
+    lx, ly, lz, lt = dims
+    rng = np.random.default_rng(52)
+    V = np.empty((lt, 6, lz, ly, lx, 3), dtype=np.complex128)
+    for t in range(lt):
+        q, _ = np.linalg.qr(rng.standard_normal((3 * lx * ly * lz, 6)) + 1j * rng.standard_normal((3 * lx * ly * lz, 6)))
+        V[t] = q.T.reshape(6, lz, ly, lx, 3)
+    phi = laph.meson_doublets(V, [(0, 0, 0)])
+    assert np.abs(phi[0] - np.eye(6)[None]).max() < 1e-13
+
+
+def test_doublets_triplets_gauge_invariance():
+    """V -> g V with g(x) in SU(3): doublets (g^dagger g = 1) and triplets (det g = 1) unchanged."""
+    dims = (4, 2, 2, 3)
+    lx, ly, lz, lt = dims
+    V = ls.random_spinor((lt, 5, lz, ly, lx, 3), 53)
+    g = ls.random_su3(lx * ly * lz * lt, 54).reshape(lt, lz, ly, lx, 3, 3)
+    Vg = np.matmul(g[:, None], V[..., None])[..., 0]
+    moms = [(0, 0, 0), (1, 0, 1), (0, -1, 0)]
+    assert _rel(laph.meson_doublets(Vg, moms), laph.meson_doublets(V, moms)) < 1e-13
+    assert _rel(laph.baryon_triplets(Vg, moms), laph.baryon_triplets(V, moms)) < 1e-13
+
+
+def test_triplet_integrand_is_determinant():
+    """eps_abc u_a v_b w_c = det[u v w]: the triplet against numpy's determinant per site."""
+    dims = (2, 4, 2, 2)
+    lx, ly, lz, lt = dims
+    V = ls.random_spinor((lt, 4, lz, ly, lx, 3), 55)
+    mom = (1, 1, 1)
+    B = laph.baryon_triplets(V, [mom])
+    for t in range(lt):
+        for l, m, n in ((0, 1, 2), (3, 1, 0), (2, 3, 1)):
+            acc = 0
+            for z in range(lz):
+                for y in range(ly):
+                    for x in range(lx):
+                        ph = np.exp(-2j * np.pi * (x / lx + y / ly + z / lz))
+                        acc += ph * np.linalg.det(np.stack([V[t, l, z, y, x], V[t, m, z, y, x], V[t, n, z, y, x]], 1))
+            assert abs(B[0, t, l, m, n] - acc) < 1e-13 * max(1.0, abs(acc))
+
+
+def test_doublets_momentum_reversal_and_triplet_antisymmetry():
+    """Phi_{-p}[m][l] = conj(Phi_p[l][m]); B changes sign under any swap of two indices."""
+    dims = (4, 2, 2, 2)
+    lx, ly, lz, lt = dims
+    V = ls.random_spinor((lt, 4, lz, ly, lx, 3), 56)
+    phi = laph.meson_doublets(V, [(1, 0, 1), (-1, 0, -1)])
+    assert _rel(phi[1], np.conj(phi[0]).transpose(0, 2, 1)) < 1e-14
+    B = laph.baryon_triplets(V, [(0, 1, 0)])
+    for perm in ((0, 1, 3, 2, 4), (0, 1, 2, 4, 3), (0, 1, 4, 3, 2)):
+        assert _rel(B.transpose(perm), -B) < 1e-14
+
+
+# ---------------------------------------------------------------------------
 # P13: FP16-with-norm codec
 # ---------------------------------------------------------------------------
 
