@@ -221,6 +221,7 @@ def extra_suite(laph, torch):
     torch.cuda.empty_cache()
 
     out["32x32x32x64_laph_vectors_nev64"] = laph_vectors_run(laph, torch)
+    out["32x32x32x64_contractions_nev64"] = contractions_run(laph, torch)
     return out
 
 
@@ -242,8 +243,9 @@ def laph_vectors_run(laph, torch):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / 5
     vs = dims[0] * dims[1] * dims[2]
-    # algorithmic bytes per vector and site: in + out (96 B) + 6 links (864 B) / 4 vectors per link load
-    gb = (8 * 96 + 8 / 4 * 864) * vs * dims[3] / (ms * 1e-3) / 1e9
+    # algorithmic bytes per site: in + out of every vector (96 B each) + the three
+    # links of the site (432 B, read once for all vectors)
+    gb = (8 * 96 + 432) * vs * dims[3] / (ms * 1e-3) / 1e9
     res = {"seconds": round(dt, 3), "iterations": info["iters"], "max_residual": info["residual"],
            "lowest_eigenvalue": float(lam.min()), "largest_returned_eigenvalue": float(lam.max()),
            "laplacian_8vec_ms": round(ms, 4), "laplacian_8vec_gbs": round(gb, 1),
@@ -251,6 +253,44 @@ def laph_vectors_run(laph, torch):
     del lat, V, X
     torch.cuda.empty_cache()
     return res
+
+
+def contractions_run(laph, torch, n_mom=4, reps=3):
+    """Meson doublets and baryon triplets of 64 LapH vectors on every timeslice of
+    32^3 x 64 for n_mom momenta: average time per call (HIP events over reps calls
+    after one warm call) and the rates against the FP64 matrix-core and HBM peaks."""
+    cfg = ls.CONFIGS["c4"]
+    dims, nev = cfg["dims"], cfg["nev"]
+    lat = laph.Lattice(dims)
+    Vd = torch.from_numpy(ls.orthonormal_laph_vectors(dims, nev, cfg["seed_v"])).cuda()
+    moms = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (1, 1, 0), (0, 0, 1), (1, 0, 1), (0, 1, 1), (1, 1, 1)][:n_mom]
+    vs = dims[0] * dims[1] * dims[2]
+    out = {"momenta": n_mom}
+    for name, fn in (("doublets", lat.meson_doublets), ("triplets", lat.baryon_triplets)):
+        r = fn(Vd, moms)
+        del r
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            r = fn(Vd, moms)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out_bytes = r.numel() * 16
+        del r
+        v_bytes = Vd.numel() * 16
+        if name == "doublets":
+            # complex multiply-adds: nev^2 entries x 3 vs terms per (t, p)
+            flops = 8.0 * nev * nev * 3 * vs * dims[3] * n_mom
+        else:
+            # the distinct triplets l < m < n, 3 vs terms each
+            flops = 8.0 * (nev * (nev - 1) * (nev - 2) // 6) * 3 * vs * dims[3] * n_mom
+        out[name] = {"ms": round(ms, 3), "tflops": round(flops / (ms * 1e-3) / 1e12, 3),
+                     "fp64_mfma_frac": round(flops / (ms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4),
+                     "gbs_v_once_plus_output": round((v_bytes + out_bytes) / (ms * 1e-3) / 1e9, 1)}
+    del lat, Vd
+    torch.cuda.empty_cache()
+    return out
 
 
 def stage_key(args, dims):
@@ -300,6 +340,9 @@ def main():
     ap.add_argument("--laph-vectors", action="store_true",
                     help="only compute the LapH vectors of the 32^3x64 lattice (64 per timeslice) and print "
                          "their timing as one JSON line")
+    ap.add_argument("--contractions", action="store_true",
+                    help="only compute meson doublets and baryon triplets of 64 vectors on 32^3x64 for 4 "
+                         "momenta and print their timing as one JSON line")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch the dominant stage (and a 2 GiB copy for the counter scale), for "
                          "rocprofv3 --pmc runs; needs --stencil, --rhs-tile and --traversal")
@@ -320,6 +363,10 @@ def main():
     if args.laph_vectors:
         print(json.dumps({"workload": "LapH vectors 32x32x32x64, 64 lowest eigenpairs of -Delta per timeslice, "
                                       "tol 1e-10", **laph_vectors_run(laph, torch)}), flush=True)
+        return
+    if args.contractions:
+        print(json.dumps({"workload": "meson doublets and baryon triplets, 32x32x32x64, nev 64",
+                          **contractions_run(laph, torch)}), flush=True)
         return
     nev = cfg["nev"]
     m0 = cfg["masses"][0]

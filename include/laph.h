@@ -208,7 +208,7 @@ laph_status laph_project_adjoint(laph_ctx ctx, double *GX, const double *Gtau, c
  *    lambda_host = [Lt][nev] ascending.  It stops when every returned pair has
  *    ||(-Delta) v - lambda v|| <= tol (absolute; the spectrum lies in [0, 12]) or
  *    after max_iter iterations (then LAPH_ERR_NOCONV; V is not written).  degree:
- *    Chebyshev filter degree per iteration (<= 1: 16).  iters_host and
+ *    Chebyshev filter degree per iteration (<= 1: 48).  iters_host and
  *    residual_host (may be null) receive the iterations used and the largest
  *    residual norm.  work: laph_laplacian_workspace_bytes(ctx, nev) bytes of device
  *    memory (about 4 Lt (nev + nev/2) 3 Lx Ly Lz complex doubles). */
@@ -217,6 +217,29 @@ laph_status laph_apply_laplacian(laph_ctx ctx, double *out, const double *in, in
 laph_status laph_laplacian_eigvecs(laph_ctx ctx, double *V, double *lambda_host, int nev, double tol, int max_iter,
                                    int degree, void *work, size_t work_bytes, int *iters_host,
                                    double *residual_host);
+
+/* Meson doublets and baryon triplets of the LapH vectors (Sec. "QUDA": the LapH
+ * vectors also form the quark-antiquark doublets and three-quark triplets used in
+ * the Wick contractions of meson and baryon correlators).  For each momentum
+ * p = 2 pi (nx / Lx, ny / Ly, nz / Lz) given as integers mom_host[3 q .. 3 q + 2]
+ * (any sign; host array of 3 n_mom ints) and every timeslice t:
+ *   Phi[q][t][l][m]    = sum_x e^{-i p.x} sum_a conj(V_l(x,t)_a) V_m(x,t)_a
+ *   B[q][t][l][m][n]   = sum_x e^{-i p.x} eps_abc V_l(x,t)_a V_m(x,t)_b V_n(x,t)_c
+ * x runs over the sites of the timeslice (x, y, z integer coordinates).
+ *  V:   c128 [Lt][nev][Lz][Ly][Lx][3] on the device (the laph_laplacian_eigvecs
+ *       layout), 1 <= nev <= 64 (triplets: nev >= 3); not modified.
+ *  phi: c128 [n_mom][Lt][nev][nev] on the device, every entry written.
+ *  B:   c128 [n_mom][Lt][nev][nev][nev] on the device, every entry written (the
+ *       tensor is antisymmetric: entries with a repeated index are exactly 0).
+ *  work: laph_contract_workspace_bytes(ctx, kind, nev, n_mom) bytes of device
+ *       memory (kind 0 doublets, 1 triplets); LAPH_ERR_WORKSPACE if smaller.
+ * Needs only the context's geometry (no gauge field, clover or state).  FP64
+ * throughout; asynchronous on the context stream. */
+size_t laph_contract_workspace_bytes(laph_ctx ctx, int kind, int nev, int n_mom);
+laph_status laph_meson_doublets(laph_ctx ctx, double *phi, const double *V, int nev, int n_mom,
+                                const int *mom_host, void *work, size_t work_bytes);
+laph_status laph_baryon_triplets(laph_ctx ctx, double *B, const double *V, int nev, int n_mom,
+                                 const int *mom_host, void *work, size_t work_bytes);
 
 /* Milliseconds of the last laph_solve / laph_perambulator split as
  * [0] total, [1] solve, [2] projection (HIP events on the context stream). */

@@ -62,6 +62,9 @@ _SIGS = [
     ("laph_apply_laplacian", c_int, [c_void_p, c_void_p, c_void_p, c_int]),
     ("laph_laplacian_eigvecs", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_double, c_int, c_int, c_void_p,
                                        c_size_t, P(c_int), P(c_double)]),
+    ("laph_contract_workspace_bytes", c_size_t, [c_void_p, c_int, c_int, c_int]),
+    ("laph_meson_doublets", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_size_t]),
+    ("laph_baryon_triplets", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_size_t]),
     ("laph_project_workspace_bytes", c_size_t, [c_void_p, c_int, c_int]),
     ("laph_project", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p, c_size_t]),
     ("laph_project_adjoint", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int]),

@@ -238,9 +238,10 @@ class Lattice:
         L.check(self._run(self.lib.laph_apply_laplacian, self.ctx, _ptr(out), _ptr(X), nvec))
         return out
 
-    def laplacian_eigvecs(self, nev, tol=1e-10, max_iter=200, degree=16):
+    def laplacian_eigvecs(self, nev, tol=1e-10, max_iter=200, degree=0):
         """Lowest nev eigenpairs of -Delta on every timeslice: (V [Lt][nev][Lz][Ly][Lx][3]
-        on the device, eigenvalues [Lt][nev] (numpy), dict(iters, residual))."""
+        on the device, eigenvalues [Lt][nev] (numpy), dict(iters, residual)).  degree: the
+        Chebyshev filter degree per iteration (0: the library's default)."""
         lt = self.dims[3]
         V = torch.empty(self.laph_shape(nev), dtype=torch.complex128, device=self.device)
         lam = np.zeros((lt, nev))
@@ -251,6 +252,27 @@ class Lattice:
                        _ptr(w), w.numel(), ctypes.byref(its), ctypes.byref(res))
         L.check(st)
         return V, lam, dict(iters=its.value, residual=res.value)
+
+    def _contract(self, kind, fn, V, moms):
+        nev = V.shape[1]
+        _check_tensor(V, self.laph_shape(nev), "V")
+        mom = np.ascontiguousarray(np.asarray(moms, dtype=np.int32).reshape(-1, 3))
+        nm = mom.shape[0]
+        shape = (nm, self.dims[3]) + (nev,) * (2 + kind)
+        out = torch.empty(shape, dtype=torch.complex128, device=self.device)
+        w = self._workspace(self.lib.laph_contract_workspace_bytes(self.ctx, kind, nev, nm))
+        L.check(self._run(fn, self.ctx, _ptr(out), _ptr(V), nev, nm, mom.ctypes.data_as(ctypes.c_void_p),
+                          _ptr(w), w.numel()))
+        return out
+
+    def meson_doublets(self, V, moms):
+        """Phi[q][t][l][m] = sum_x exp(-i p_q.x) conj(V_l(x,t)) . V_m(x,t) for integer
+        momenta moms[q] = (nx, ny, nz), p = 2 pi (nx/Lx, ny/Ly, nz/Lz); V [Lt][nev][Lz][Ly][Lx][3]."""
+        return self._contract(0, self.lib.laph_meson_doublets, V, moms)
+
+    def baryon_triplets(self, V, moms):
+        """B[q][t][l][m][n] = sum_x exp(-i p_q.x) eps_abc V_l(x,t)_a V_m(x,t)_b V_n(x,t)_c."""
+        return self._contract(1, self.lib.laph_baryon_triplets, V, moms)
 
     def make_sources(self, V, t0):
         nev = V.shape[1]

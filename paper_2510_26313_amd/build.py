@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblaph.so")
 SOURCES = ["dslash_f64.hip", "dslash_f32.hip", "dslash_f16.hip", "capi.hip", "setup.hip", "dslash.hip",
-           "blas.hip", "solver.hip", "project.hip", "tune.hip", "laplace.hip"]
+           "blas.hip", "solver.hip", "project.hip", "tune.hip", "laplace.hip", "contract.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

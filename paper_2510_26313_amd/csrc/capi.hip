@@ -484,6 +484,28 @@ laph_status laph_laplacian_eigvecs(laph_ctx h, double *V, double *lambda_host, i
                              work_bytes, iters_host, residual_host);
 }
 
+size_t laph_contract_workspace_bytes(laph_ctx h, int kind, int nev, int n_mom) {
+    if (!h) return 0;
+    return contract_workspace_bytes(C(h), kind, nev, n_mom);
+}
+
+static laph_status contract_entry(laph_ctx h, int kind, double *out, const double *V, int nev, int n_mom,
+                                  const int *mom_host, void *work, size_t work_bytes) {
+    if (!h) return set_error(LAPH_ERR_INVALID, "null context");
+    if (!out || !V) return set_error(LAPH_ERR_INVALID, "null output or V");
+    return contract(C(h), kind, out, V, nev, n_mom, mom_host, reinterpret_cast<char *>(work), work_bytes);
+}
+
+laph_status laph_meson_doublets(laph_ctx h, double *phi, const double *V, int nev, int n_mom, const int *mom_host,
+                                void *work, size_t work_bytes) {
+    return contract_entry(h, 0, phi, V, nev, n_mom, mom_host, work, work_bytes);
+}
+
+laph_status laph_baryon_triplets(laph_ctx h, double *B, const double *V, int nev, int n_mom, const int *mom_host,
+                                 void *work, size_t work_bytes) {
+    return contract_entry(h, 1, B, V, nev, n_mom, mom_host, work, work_bytes);
+}
+
 laph_status laph_make_sources(laph_ctx h, double *B, const double *V, int nev, int t0) {
     LAPH_TRY(check_ctx(h));
     Ctx &c = C(h);

@@ -1,0 +1,319 @@
+// Meson doublets and baryon triplets of the LapH vectors (Sec. "QUDA": besides
+// sourcing the solves and projecting the propagators, the LapH vectors form the
+// quark-antiquark doublets and three-quark triplets that enter the Wick
+// contractions of meson and baryon correlators).  Per timeslice t and momentum
+// p = 2 pi (nx / Lx, ny / Ly, nz / Lz):
+//
+//   Phi_p[t][l][m]   = sum_x e^{-i p.x} sum_a conj(V_l(x, t)_a) V_m(x, t)_a
+//   B_p[t][l][m][n]  = sum_x e^{-i p.x} eps_abc V_l(x, t)_a V_m(x, t)_b V_n(x, t)_c
+//
+// Both are complex FP64 GEMMs per (t, p) over K = (site, colour), 3 Lx Ly Lz long:
+//   doublets  A[l][(x, a)] = e^{-i p.x} conj(V_l(x)_a),  B[(x, a)][m]      = V_m(x)_a
+//   triplets  A[l][(x, a)] = e^{-i p.x} V_l(x)_a,        B[(x, a)][(m, n)] = (V_m(x) x V_n(x))_a
+// where the triplet's B column is the colour cross product of a pair m < n.  A
+// workgroup stages the V of a chunk of sites (all nev vectors) in LDS; each wave
+// forms its A and B fragments from there (the cross products are never stored)
+// and runs the FP64 matrix cores.  B_p is antisymmetric in every index pair, so
+// only l < m < n is accumulated (a wave skips row blocks with no l below the
+// pairs' m), and the reduction writes all six orderings with their signs and
+// zeros where an index repeats.  K is split over workgroups for occupancy; the
+// reduction sums the slices in a fixed order.
+#include <algorithm>
+#include <cmath>
+
+#include "laph_solver.h"
+
+namespace laph {
+
+namespace {
+
+constexpr int kCB = 256;          // threads per workgroup (4 waves)
+constexpr int kCS = 16;           // sites per K chunk
+constexpr int kCK = 3 * kCS;      // K (site, colour) per chunk
+constexpr int kCLd = kCK + 1;     // LDS row stride in doubles
+constexpr int kCRows = 64;        // l rows: nev <= 64
+constexpr int kCMaxMom = 16;      // momenta per launch
+constexpr int kCTarget = 2048;    // workgroups aimed for by the K split
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+struct ContractArgs {
+    int lx, ly, lz, lt, vs;
+    int nev;
+    int ncol;             // doublets: nev; triplets: nev (nev - 1) / 2 pairs (m < n, m-major)
+    int ntile;            // column tiles per (t, p)
+    int nsplit;           // K slices
+    int nchunk;           // K chunks of kCS sites
+    int nmom;
+    int mom[3 * kCMaxMom];
+    const double2 *V;     // [lt][nev][vs][3]
+    double2 *scratch;     // [nsplit][nmom][lt][nev][ncol]
+};
+
+// first column of pair row m in the m-major list of pairs m < n
+__host__ __device__ __forceinline__ int pair_base(int m, int nev) { return m * nev - m * (m + 1) / 2; }
+
+__device__ __forceinline__ void pair_of(int q, int nev, int &m, int &n) {
+    m = 0;
+    while (m + 1 < nev && pair_base(m + 1, nev) <= q) ++m;
+    n = q - pair_base(m, nev) + m + 1;
+}
+
+// NCB column blocks of 16 per wave: 4 NCB 16 columns per workgroup
+template <int MODE, int NCB>
+__global__ __launch_bounds__(kCB) void contract_kernel(ContractArgs A) {
+    __shared__ double Vr[kCRows][kCLd], Vi[kCRows][kCLd];
+    __shared__ double phr[kCS], phim[kCS];
+    // workgroups that share a K slice of one timeslice run on one XCD (consecutive
+    // workgroup ids go round-robin over the 8 XCDs)
+    const int nb = gridDim.x;
+    int bid = blockIdx.x;
+    if (nb % 8 == 0) bid = (bid % 8) * (nb / 8) + bid / 8;
+    const int inner = A.ntile * A.nmom;
+    const int tile = bid % A.ntile;
+    const int p = (bid / A.ntile) % A.nmom;
+    const int outer = bid / inner;
+    const int split = outer % A.nsplit;
+    const int t = outer / A.nsplit;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int kCols = 4 * NCB * 16;
+    const int nev = A.nev;
+
+    // this lane's column per block, the pair behind it, and the blocks' active rows
+    int col[NCB], cm[NCB], cn[NCB];
+    unsigned act = 0;   // bit 4 j + i: row block i, column block j
+#pragma unroll
+    for (int j = 0; j < NCB; ++j) {
+        const int c0 = tile * kCols + (wave * NCB + j) * 16;
+        col[j] = c0 + (lane & 15);
+        cm[j] = 0;
+        cn[j] = 0;
+        if (c0 >= A.ncol) continue;
+        int rows_hi = nev;   // rows below this bound take part
+        if (MODE == 1) {
+            const int cc = col[j] < A.ncol ? col[j] : A.ncol - 1;
+            pair_of(cc, nev, cm[j], cn[j]);
+            int mlast, nlast;
+            pair_of(min(c0 + 15, A.ncol - 1), nev, mlast, nlast);
+            rows_hi = mlast;   // l < m <= m of the block's last pair
+        } else {
+            cm[j] = col[j] < A.ncol ? col[j] : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (16 * i < rows_hi) act |= 1u << (4 * j + i);
+    }
+
+    d4 cre[4][NCB], cim[4][NCB];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < NCB; ++j) {
+            cre[i][j] = d4{0, 0, 0, 0};
+            cim[i][j] = d4{0, 0, 0, 0};
+        }
+    const int mx = A.mom[3 * p], my = A.mom[3 * p + 1], mz = A.mom[3 * p + 2];
+    const int ch0 = (int)((long)A.nchunk * split / A.nsplit), ch1 = (int)((long)A.nchunk * (split + 1) / A.nsplit);
+    const double2 *Vt = A.V + (size_t)t * nev * A.vs * 3;
+    const int n3 = 3 * A.vs;
+    for (int ch = ch0; ch < ch1; ++ch) {
+        const int s0 = ch * kCS;
+        // V of the chunk for every vector (rows beyond nev and sites beyond the
+        // timeslice are zero)
+        for (int q = tid; q < kCRows * kCK; q += kCB) {
+            const int l = q / kCK, kk = q - l * kCK;
+            double2 v = make_double2(0.0, 0.0);
+            if (l < nev && 3 * s0 + kk < n3) v = Vt[(size_t)l * n3 + 3 * s0 + kk];
+            Vr[l][kk] = v.x;
+            Vi[l][kk] = v.y;
+        }
+        if (tid < kCS) {
+            const int s = s0 + tid;
+            const int x = s % A.lx, y = (s / A.lx) % A.ly, z = s / (A.lx * A.ly);
+            // e^{-2 pi i (nx x / Lx + ny y / Ly + nz z / Lz)}, integer parts reduced first
+            const int qx = ((mx * x) % A.lx + A.lx) % A.lx;
+            const int qy = ((my * y) % A.ly + A.ly) % A.ly;
+            const int qz = ((mz * z) % A.lz + A.lz) % A.lz;
+            const double f = (double)qx / A.lx + (double)qy / A.ly + (double)qz / A.lz;
+            double sn, cs;
+            sincospi(-2.0 * f, &sn, &cs);
+            phr[tid] = cs;
+            phim[tid] = sn;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int k4 = 0; k4 < kCK; k4 += 4) {
+            const int kk = k4 + (lane >> 4);
+            const int sl = kk / 3, a = kk - 3 * sl;
+            const double pr = phr[sl], pi = phim[sl];
+            double ar[4], ai[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * i + (lane & 15);
+                const double vr = Vr[row][kk], vi = MODE == 0 ? -Vi[row][kk] : Vi[row][kk];
+                ar[i] = pr * vr - pi * vi;
+                ai[i] = pr * vi + pi * vr;
+            }
+#pragma unroll
+            for (int j = 0; j < NCB; ++j) {
+                if (!((act >> (4 * j)) & 15u)) continue;
+                double br, bi;
+                if (MODE == 0) {
+                    br = Vr[cm[j]][kk];
+                    bi = Vi[cm[j]][kk];
+                } else {
+                    // (V_m x V_n)_a = V_m,b V_n,c - V_m,c V_n,b with (a, b, c) cyclic
+                    const int kb = 3 * sl + (a == 2 ? 0 : a + 1), kc = 3 * sl + (a == 0 ? 2 : a - 1);
+                    const double ubr = Vr[cm[j]][kb], ubi = Vi[cm[j]][kb];
+                    const double ucr = Vr[cm[j]][kc], uci = Vi[cm[j]][kc];
+                    const double wbr = Vr[cn[j]][kb], wbi = Vi[cn[j]][kb];
+                    const double wcr = Vr[cn[j]][kc], wci = Vi[cn[j]][kc];
+                    br = (ubr * wcr - ubi * wci) - (ucr * wbr - uci * wbi);
+                    bi = (ubr * wci + ubi * wcr) - (ucr * wbi + uci * wbr);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (!((act >> (4 * j + i)) & 1u)) continue;
+                    cre[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br, cre[i][j], 0, 0, 0);
+                    cre[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], bi, cre[i][j], 0, 0, 0);
+                    cim[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi, cim[i][j], 0, 0, 0);
+                    cim[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br, cim[i][j], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // v_mfma_f64_16x16x4f64 leaves C[row][col] of a 16 x 16 block in lane col + 16 (row % 4),
+    // register row / 4 (a lane holds rows lane / 16 + 4 r of column lane % 16)
+    double2 *out = A.scratch + (((size_t)split * A.nmom + p) * A.lt + t) * (size_t)nev * A.ncol;
+#pragma unroll
+    for (int j = 0; j < NCB; ++j) {
+        if (col[j] >= A.ncol) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * i + (lane >> 4) + 4 * r;
+                if (row < nev) out[(size_t)row * A.ncol + col[j]] = make_double2(cre[i][j][r], cim[i][j][r]);
+            }
+    }
+}
+
+// Phi[p][t][l][m] = sum over K slices
+__global__ void doublet_reduce_kernel(ContractArgs A, double2 *phi, int p_begin, int nmom_total) {
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    const long per = (long)A.lt * A.nev * A.nev;
+    if (idx >= per * A.nmom) return;
+    const int p = (int)(idx / per);
+    const long r = idx - p * per;
+    double2 s = make_double2(0.0, 0.0);
+    for (int sp = 0; sp < A.nsplit; ++sp) {
+        const double2 v = A.scratch[((size_t)sp * A.nmom + p) * per + r];
+        s.x += v.x;
+        s.y += v.y;
+    }
+    (void)nmom_total;
+    phi[(size_t)(p_begin + p) * per + r] = s;
+}
+
+// B[p][t][l][m][n]: the sum over K slices of the sorted triple's entry, with the
+// sign of the permutation that sorts (l, m, n); zero when two indices coincide
+__global__ void triplet_reduce_kernel(ContractArgs A, double2 *B, int p_begin) {
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    const int nev = A.nev;
+    const long per = (long)A.lt * nev * nev * nev;
+    if (idx >= per * A.nmom) return;
+    const int p = (int)(idx / per);
+    long r = idx - p * per;
+    const int n = (int)(r % nev);
+    const int m = (int)((r / nev) % nev);
+    const int l = (int)((r / ((long)nev * nev)) % nev);
+    const int t = (int)(r / ((long)nev * nev * nev));
+    double2 s = make_double2(0.0, 0.0);
+    if (l != m && m != n && l != n) {
+        int a = l, b = m, c = n;
+        double sg = 1.0;
+        if (a > b) { int q = a; a = b; b = q; sg = -sg; }
+        if (b > c) { int q = b; b = c; c = q; sg = -sg; }
+        if (a > b) { int q = a; a = b; b = q; sg = -sg; }
+        const int q = pair_base(b, nev) + (c - b - 1);
+        for (int sp = 0; sp < A.nsplit; ++sp) {
+            const double2 v = A.scratch[((((size_t)sp * A.nmom + p) * A.lt + t) * nev + a) * A.ncol + q];
+            s.x += v.x;
+            s.y += v.y;
+        }
+        s.x *= sg;
+        s.y *= sg;
+    }
+    B[(size_t)(p_begin + p) * per + r] = s;
+}
+
+void contract_shape(const Ctx &c, int kind, int nev, int nmom, ContractArgs &a) {
+    a.lx = c.g.lx;
+    a.ly = c.g.ly;
+    a.lz = c.g.lz;
+    a.lt = c.g.lt;
+    a.vs = c.g.lx * c.g.ly * c.g.lz;
+    a.nev = nev;
+    a.ncol = kind == 0 ? nev : nev * (nev - 1) / 2;
+    const int cols = kind == 0 ? 64 : 128;
+    a.ntile = std::max(1, (a.ncol + cols - 1) / cols);
+    a.nmom = nmom;
+    a.nchunk = (a.vs + kCS - 1) / kCS;
+    const int base = a.lt * a.ntile * nmom;
+    a.nsplit = std::max(1, std::min({(kCTarget + base - 1) / base, a.nchunk, 64}));
+}
+
+}  // namespace
+
+// K-slice partials of one launch group of nmom momenta
+static size_t group_bytes(const Ctx &c, int kind, int nev, int nmom) {
+    ContractArgs a;
+    contract_shape(c, kind, nev, nmom, a);
+    return round256((size_t)a.nsplit * a.nmom * a.lt * nev * a.ncol * 16);
+}
+
+size_t contract_workspace_bytes(const Ctx &c, int kind, int nev, int n_mom) {
+    if (nev < 1 || nev > kCRows || n_mom < 1 || (kind != 0 && kind != 1)) return 0;
+    // the largest launch group: a full one, or the last (its K split may be finer)
+    size_t b = group_bytes(c, kind, nev, std::min(n_mom, kCMaxMom));
+    if (n_mom > kCMaxMom && n_mom % kCMaxMom) b = std::max(b, group_bytes(c, kind, nev, n_mom % kCMaxMom));
+    return b;
+}
+
+laph_status contract(const Ctx &c, int kind, double *out, const double *V, int nev, int n_mom, const int *mom_host,
+                     char *work, size_t bytes) {
+    if (nev < 1 || nev > kCRows) return set_error(LAPH_ERR_INVALID, "nev must be in 1..%d", kCRows);
+    if (kind == 1 && nev < 3) return set_error(LAPH_ERR_INVALID, "triplets need nev >= 3");
+    if (n_mom < 1 || !mom_host) return set_error(LAPH_ERR_INVALID, "need at least one momentum");
+    const size_t need = contract_workspace_bytes(c, kind, nev, n_mom);
+    if (!work || bytes < need) return set_error(LAPH_ERR_WORKSPACE, "workspace too small: %zu < %zu", bytes, need);
+    const size_t per = (size_t)c.g.lt * nev * nev * (kind == 0 ? 1 : nev);
+    for (int p0 = 0; p0 < n_mom; p0 += kCMaxMom) {
+        const int np = std::min(kCMaxMom, n_mom - p0);
+        ContractArgs a;
+        contract_shape(c, kind, nev, np, a);
+        if (group_bytes(c, kind, nev, np) > bytes) return set_error(LAPH_ERR_WORKSPACE, "workspace too small");
+        for (int q = 0; q < 3 * np; ++q) a.mom[q] = mom_host[3 * p0 + q];
+        a.V = reinterpret_cast<const double2 *>(V);
+        a.scratch = reinterpret_cast<double2 *>(work);
+        const unsigned nblk = (unsigned)(a.lt * a.nsplit * a.ntile * a.nmom);
+        if (kind == 0)
+            hipLaunchKernelGGL((contract_kernel<0, 1>), dim3(nblk), dim3(kCB), 0, c.stream, a);
+        else
+            hipLaunchKernelGGL((contract_kernel<1, 2>), dim3(nblk), dim3(kCB), 0, c.stream, a);
+        LAPH_TRY(check_launch("contract_kernel"));
+        const long total = (long)per * np;
+        const unsigned rb = (unsigned)((total + 255) / 256);
+        if (kind == 0)
+            hipLaunchKernelGGL(doublet_reduce_kernel, dim3(rb), dim3(256), 0, c.stream, a,
+                               reinterpret_cast<double2 *>(out), p0, n_mom);
+        else
+            hipLaunchKernelGGL(triplet_reduce_kernel, dim3(rb), dim3(256), 0, c.stream, a,
+                               reinterpret_cast<double2 *>(out), p0);
+        LAPH_TRY(check_launch("contract_reduce_kernel"));
+    }
+    return LAPH_OK;
+}
+
+}  // namespace laph

@@ -51,6 +51,12 @@ size_t laplacian_eig_workspace_bytes(const Ctx &c, int nev);
 laph_status laplacian_eigvecs(Ctx &c, double *V, double *lambda_host, int nev, double tol, int max_iter, int degree,
                               char *work, size_t bytes, int *iters_out, double *res_host);
 
+// Meson doublets (kind 0) and baryon triplets (kind 1) of the LapH vectors per
+// timeslice and momentum (contract.hip).
+size_t contract_workspace_bytes(const Ctx &c, int kind, int nev, int n_mom);
+laph_status contract(const Ctx &c, int kind, double *out, const double *V, int nev, int n_mom, const int *mom_host,
+                     char *work, size_t bytes);
+
 class Solver {
    public:
     struct WS {

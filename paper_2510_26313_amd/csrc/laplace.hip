@@ -9,7 +9,8 @@
 // Method: Chebyshev-filtered subspace iteration, all timeslices at once.  Per
 // iteration and timeslice, a block of m = nev + guard vectors is filtered by the
 // degree-d Chebyshev polynomial that damps [lambda_cut, 12] (lambda_cut = the
-// largest Ritz value of the block), made orthonormal by two Loewdin passes
+// largest Ritz value of the block; d as large as allowed while the growth of the
+// lowest Ritz direction over the cut stays below ~1e6), made orthonormal by two Loewdin passes
 // (Hermitian eigendecomposition of the Gram matrix, Y <- Y Q Lambda^{-1/2}; the
 // first pass shifted by 1e-15 of the largest Gram eigenvalue), and rotated to Ritz
 // vectors by a Rayleigh-Ritz step; it stops when every one of the nev lowest Ritz
@@ -18,8 +19,11 @@
 // cores), the small Hermitian eigenproblems (cyclic Jacobi in one workgroup per
 // timeslice, matrix in LDS), the block rotations and the residual norms.
 //
-// Layout of a block: [t][j][z][y][x][a] complex double (the canonical V layout),
-// vectors of one timeslice contiguous.
+// Layout of a block: [t][j][a][z][y][x] complex double (colour planes, so the
+// stencil's loads are contiguous across the lanes of a wave), vectors of one
+// timeslice contiguous; the result is written in the canonical V layout
+// [t][l][z][y][x][a].
+#include <algorithm>
 #include <cmath>
 #include <initializer_list>
 #include <vector>
@@ -37,6 +41,7 @@ constexpr int kJB = 256;          // threads of the Jacobi workgroup
 constexpr int kGT = 64;           // Gram tile (rows and columns)
 constexpr int kGKC = 16;          // Gram K chunk
 constexpr int kLmax = 12;         // upper bound of the spectrum
+constexpr int kDefaultDegree = 48; // Chebyshev degree per iteration when the caller passes <= 1
 
 // ---- stencil: out = ca[t] (-Delta) in + cb[t] in + cc[t] z ------------------------
 struct LapArgs {
@@ -62,6 +67,9 @@ __device__ __forceinline__ void site3(const Geom &g, int s, int &x, int &y, int 
 // 32-63), so every link is read from HBM once for all vectors of the block.
 constexpr int kLapSites = 32;
 
+// element (site, colour) of a vector: colour planes (Planar) or the canonical
+// site-major order
+template <bool HasZ, bool Planar>
 __global__ __launch_bounds__(kLB) void lap_kernel(LapArgs A) {
     __shared__ double lnk[6][18][kLapSites];
     __shared__ int nbr[6][kLapSites];
@@ -114,39 +122,52 @@ __global__ __launch_bounds__(kLB) void lap_kernel(LapArgs A) {
         cc = A.coef[3 * t + 2];
     }
     const size_t tb = (size_t)t * A.m;
+    const int ss = Planar ? 1 : 3, sa = Planar ? vs : 1;
+    int nb[6];
+#pragma unroll
+    for (int hop = 0; hop < 6; ++hop) nb[hop] = nbr[hop][site] * ss;
 #pragma unroll 1
     for (int j = 2 * wave + vsub; j < A.nvec; j += 2 * (kLB / 64)) {
-        const double2 *vin = A.in + (tb + j) * vs * 3;
+        const size_t vb = (tb + j) * vs * 3;
+        const double2 *__restrict__ vin = A.in + vb;
+        // every load of this vector first (six neighbours, the site itself, z), so a
+        // wave keeps up to 24 loads in flight; then the products with the staged links
+        double2 fn[6][3], fc[3], fz[3];
+#pragma unroll
+        for (int hop = 0; hop < 6; ++hop)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) fn[hop][a] = vin[nb[hop] + a * sa];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) fc[a] = vin[ss * s + a * sa];
+        if (HasZ) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) fz[a] = A.z[vb + ss * s + a * sa];
+        }
+        // the links are re-read from LDS per vector (an opaque index keeps the compiler
+        // from holding all 108 of them in registers across the loop)
+        int ls = site;
+        asm volatile("" : "+v"(ls));
         cplx<double> acc[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
 #pragma unroll
-        for (int hop = 0; hop < 6; ++hop) {
-            const double2 *f = vin + (size_t)nbr[hop][site] * 3;
-            cplx<double> fn[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) fn[a] = {f[a].x, f[a].y};
+        for (int hop = 0; hop < 6; ++hop)
 #pragma unroll
             for (int a = 0; a < 3; ++a)
 #pragma unroll
                 for (int b = 0; b < 3; ++b) {
-                    const cplx<double> l = {lnk[hop][2 * (a * 3 + b)][site], lnk[hop][2 * (a * 3 + b) + 1][site]};
-                    cmac(acc[a], l, fn[b]);
+                    const cplx<double> l = {lnk[hop][2 * (a * 3 + b)][ls], lnk[hop][2 * (a * 3 + b) + 1][ls]};
+                    cmac(acc[a], l, cplx<double>{fn[hop][b].x, fn[hop][b].y});
                 }
-            // one hop at a time: hoisting all six hops' loads costs occupancy
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        const size_t e = ((tb + j) * vs + s) * 3;
+        double2 *__restrict__ vout = A.out + vb;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const double2 f = A.in[e + a];
             // (-Delta f) = 6 f - hops
-            double re = ca * (6.0 * f.x - acc[a].re) + cb * f.x;
-            double im = ca * (6.0 * f.y - acc[a].im) + cb * f.y;
-            if (A.z) {
-                const double2 zz = A.z[e + a];
-                re += cc * zz.x;
-                im += cc * zz.y;
+            double re = ca * (6.0 * fc[a].x - acc[a].re) + cb * fc[a].x;
+            double im = ca * (6.0 * fc[a].y - acc[a].im) + cb * fc[a].y;
+            if (HasZ) {
+                re += cc * fz[a].x;
+                im += cc * fz[a].y;
             }
-            A.out[e + a] = make_double2(re, im);
+            vout[ss * s + a * sa] = make_double2(re, im);
         }
     }
 }
@@ -482,8 +503,9 @@ __global__ __launch_bounds__(kLB) void start_kernel(double2 *X, int m, int ne, i
 }
 
 // ---- phase convention and output -------------------------------------------------------
-// The largest-modulus component real positive (the lowest index among those within
-// 1e-12 of the largest), then the vector is written to V[t][l].
+// The largest-modulus component real positive (the lowest canonical index 3 s + a
+// among those within 1e-12 of the largest), then the vector is written to V[t][l]
+// in the canonical order (element a vs + s of the block goes to 3 s + a).
 __global__ __launch_bounds__(kLB) void phase_out_kernel(const double2 *Y, double2 *V, int m, int ne, int nev) {
     __shared__ double redd[kLB / 64];
     __shared__ int redi[kLB / 64];
@@ -498,9 +520,12 @@ __global__ __launch_bounds__(kLB) void phase_out_kernel(const double2 *Y, double
     __syncthreads();
     mx = redd[0];
     for (int q = 1; q < kLB / 64; ++q) mx = fmax(mx, redd[q]);
+    const int vs = ne / 3;
     int idx = ne;
-    for (int e = threadIdx.x; e < ne; e += kLB)
-        if (sqrt(y[e].x * y[e].x + y[e].y * y[e].y) >= mx - 1e-12 && e < idx) idx = e;
+    for (int e = threadIdx.x; e < ne; e += kLB) {
+        const int ec = 3 * (e % vs) + e / vs;
+        if (sqrt(y[e].x * y[e].x + y[e].y * y[e].y) >= mx - 1e-12 && ec < idx) idx = ec;
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) idx = min(idx, __shfl_xor(idx, o, 64));
     if ((threadIdx.x & 63) == 0) redi[threadIdx.x >> 6] = idx;
@@ -508,7 +533,7 @@ __global__ __launch_bounds__(kLB) void phase_out_kernel(const double2 *Y, double
     if (threadIdx.x == 0) {
         int i = redi[0];
         for (int q = 1; q < kLB / 64; ++q) i = min(i, redi[q]);
-        const double2 v = y[i];
+        const double2 v = y[(i % 3) * vs + i / 3];
         const double a = sqrt(v.x * v.x + v.y * v.y);
         ph = a > 0 ? make_double2(v.x / a, -v.y / a) : make_double2(1, 0);   // conj(v) / |v|
     }
@@ -516,7 +541,7 @@ __global__ __launch_bounds__(kLB) void phase_out_kernel(const double2 *Y, double
     const double2 p = ph;
     double2 *out = V + ((size_t)t * nev + l) * ne;
     for (int e = threadIdx.x; e < ne; e += kLB) {
-        const double2 v = y[e];
+        const double2 v = y[(e % 3) * vs + e / 3];
         out[e] = make_double2(v.x * p.x - v.y * p.y, v.x * p.y + v.y * p.x);
     }
 }
@@ -585,7 +610,8 @@ struct EigRun {
         a.nvec = m;
         a.coef = coef;
         dim3 grid((vs + kLapSites - 1) / kLapSites, lt);
-        hipLaunchKernelGGL(lap_kernel, grid, dim3(kLB), 0, c.stream, a);
+        if (a.z) hipLaunchKernelGGL((lap_kernel<true, true>), grid, dim3(kLB), 0, c.stream, a);
+        else hipLaunchKernelGGL((lap_kernel<false, true>), grid, dim3(kLB), 0, c.stream, a);
         return check_launch("lap_kernel");
     }
     laph_status gram(const double2 *P, const double2 *R) const {
@@ -648,7 +674,7 @@ laph_status apply_neg_laplacian(const Ctx &c, double *out, const double *in, int
     a.coef = nullptr;
     const int vs = c.g.lx * c.g.ly * c.g.lz;
     dim3 grid((vs + kLapSites - 1) / kLapSites, c.g.lt);
-    hipLaunchKernelGGL(lap_kernel, grid, dim3(kLB), 0, c.stream, a);
+    hipLaunchKernelGGL((lap_kernel<false, false>), grid, dim3(kLB), 0, c.stream, a);
     return check_launch("lap_kernel");
 }
 
@@ -693,13 +719,22 @@ laph_status laplacian_eigvecs(Ctx &c, double *V, double *lam_host, int nev, doub
     }
     LAPH_TRY(loewdin(x));
     std::vector<double> cut(lt, 0.5 * kLmax), coef(6 * (size_t)lt), w((size_t)lt * m), r2((size_t)lt * m);
-    const int deg = degree >= 2 ? degree : 16;
+    const int deg_max = degree >= 2 ? degree : kDefaultDegree;
+    std::vector<double> lo(lt, 0.0);   // lowest Ritz value per timeslice (-Delta >= 0 before the first)
     int it = 0;
     bool done = false;
     double worst = INFINITY;
     while (it < max_iter && !done) {
         ++it;
-        // Chebyshev filter on [cut_t, 12]: Y1 = (A - c) X / e;  Y_{k+1} = 2 (A - c) Y_k / e - Y_{k-1}
+        // Chebyshev filter on [cut_t, 12]: Y1 = (A - c) X / e;  Y_{k+1} = 2 (A - c) Y_k / e - Y_{k-1}.
+        // The degree is capped so that the filter grows the lowest Ritz direction by at
+        // most ~1e6 over the cut (T_d(g) ~ e^{d acosh g} / 2): a larger ratio leaves the
+        // block's other directions below rounding (the Gram matrix's condition is its square).
+        int deg = deg_max;
+        for (int t = 0; t < lt; ++t) {
+            const double g = (0.5 * (cut[t] + kLmax) - lo[t]) / (0.5 * (kLmax - cut[t]));
+            if (g > 1.0) deg = std::min(deg, std::max(2, (int)(std::log(2e6) / std::acosh(g))));
+        }
         for (int t = 0; t < lt; ++t) {
             const double cc = 0.5 * (cut[t] + kLmax), ee = 0.5 * (kLmax - cut[t]);
             coef[3 * t] = 1.0 / ee;
@@ -740,6 +775,7 @@ laph_status laplacian_eigvecs(Ctx &c, double *V, double *lam_host, int nev, doub
         for (int t = 0; t < lt; ++t) {
             for (int j = 0; j < nev; ++j) worst = fmax(worst, sqrt(r2[(size_t)t * m + j]));
             cut[t] = w[(size_t)t * m + m - 1];
+            lo[t] = w[(size_t)t * m];
         }
         if (!std::isfinite(worst)) return set_error(LAPH_ERR_NONFINITE, "non-finite residual in the eigensolver");
         done = worst <= tol;
