@@ -107,6 +107,42 @@ def perambulator(U, V, t0, m0, csw=1.0, tol=1e-13, method="bicgstab", antiperiod
     return project(V, X, V.shape[1]), X
 
 
+# --- stochastic LapH: noise-diluted sources ---------------------------------------
+#
+# The stochastic variant of LapH (Sec. "Current state-of-the-art": the earlier CPU
+# NN work used it) replaces the full set of 4 nev sources per source time by noise in the
+# LapH x spin space, diluted: the noise rho[alpha][k] of the source time is split
+# by spin (full spin dilution) and by LapH index into n_dil interlaced groups
+# {k : k mod n_dil = j}.  Source j, alpha carries the noise of its group and spin:
+#
+#     b^(4j+alpha)(x, t)_(beta, a) = delta_{t,t0} delta_{beta,alpha} sum_{k = j mod n_dil} rho[alpha][k] V_k(x, t0)_a
+#
+# and its solution is projected onto the LapH vectors of every sink time exactly
+# like the perambulator (phi[t][l][j][beta][alpha]).  With n_dil = nev and
+# rho = 1 the sources are the perambulator's.
+
+def noise_sources(V, t0, rho, n_dil):
+    """Diluted noise sources b[r][t][z][y][x][s][a], r = 4 j + alpha, j < n_dil."""
+    lt, nev, lz, ly, lx, _ = V.shape
+    b = np.zeros((4 * n_dil, lt, lz, ly, lx, 4, 3), dtype=np.complex128)
+    for j in range(n_dil):
+        for alpha in range(4):
+            for k in range(j, nev, n_dil):
+                b[4 * j + alpha, t0, :, :, :, alpha, :] += rho[alpha, k] * V[t0, k]
+    return b
+
+
+def stochastic_perambulator(U, V, t0, m0, rho, n_dil, csw=1.0, tol=1e-13, method="bicgstab", antiperiodic_t=True):
+    """phi[t][l][j][beta][alpha] = sum_{x,a} conj(V_l(x,t)_a) (D^-1 b^(4j+alpha))(x,t)_(beta,a); returns (phi, X)."""
+    D = WilsonClover(U, m0, csw, antiperiodic_t)
+    b = noise_sources(V, t0, rho, n_dil)
+    if method == "dense":
+        X = dense_solve(D, b)
+    else:
+        X, _ = bicgstab(D.apply, b, tol=tol)
+    return project(V, X, n_dil), X
+
+
 # --- loss and gradients -------------------------------------------------------------
 
 def loss_from_tau(tau, t_sink, nblk=None):

@@ -5,7 +5,8 @@ sign, missing boundary phase, wrong mass normalisation, no trace removal,
 flipped clover sign, a leaf built from the wrong links, a reversed leaf, a
 Laplacian sign slip, a conjugate on the wrong factor of the projection, a
 missing gamma5 in the adjoint, the doublets' conjugate or phase sign, a triplet
-epsilon sign or a conjugated triplet factor) and asserts that the named pin now fails.
+epsilon sign or a conjugated triplet factor, blocked instead of interlaced noise
+dilution, noise of the wrong spin) and asserts that the named pin now fails.
 Everything runs on the CPU; nothing here touches the GPU library.
 """
 import numpy as np
@@ -115,6 +116,26 @@ def _triplets_conj_first(V, moms):
     return np.einsum("pzyx,abc,tlzyxa,tmzyxb,tnzyxc->ptlmn", ph, laph.levi_civita(), np.conj(V), V, V)
 
 
+def _noise_sources_blocked(V, t0, rho, n_dil):
+    lt, nev, lz, ly, lx, _ = V.shape
+    b = np.zeros((4 * n_dil, lt, lz, ly, lx, 4, 3), dtype=np.complex128)
+    per = -(-nev // n_dil)
+    for k in range(nev):
+        for alpha in range(4):
+            b[4 * (k // per) + alpha, t0, :, :, :, alpha, :] += rho[alpha, k] * V[t0, k]
+    return b
+
+
+def _noise_sources_wrong_spin(V, t0, rho, n_dil):
+    lt, nev, lz, ly, lx, _ = V.shape
+    b = np.zeros((4 * n_dil, lt, lz, ly, lx, 4, 3), dtype=np.complex128)
+    for j in range(n_dil):
+        for alpha in range(4):
+            for k in range(j, nev, n_dil):
+                b[4 * j + alpha, t0, :, :, :, alpha, :] += rho[0, k] * V[t0, k]
+    return b
+
+
 CASES = [
     ("hop projector sign", dirac, "hop", _hop_flipped, pins.test_free_field_plane_wave),
     ("no antiperiodic phase", dirac, "hop", _hop_periodic, pins.test_free_field_propagator_closed_form),
@@ -132,6 +153,10 @@ CASES = [
      pins.test_doublets_triplets_gauge_invariance),
     ("triplet conjugated factor", laph, "baryon_triplets", _triplets_conj_first,
      pins.test_doublets_triplets_gauge_invariance),
+    ("blocked instead of interlaced dilution", laph, "noise_sources", _noise_sources_blocked,
+     pins.test_stochastic_perambulator_is_noise_weighted_perambulator),
+    ("noise of the wrong spin", laph, "noise_sources", _noise_sources_wrong_spin,
+     pins.test_stochastic_perambulator_is_noise_weighted_perambulator),
 ]
 
 

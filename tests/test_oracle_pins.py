@@ -548,6 +548,38 @@ def test_doublets_momentum_reversal_and_triplet_antisymmetry():
 
 
 # ---------------------------------------------------------------------------
+# stochastic LapH: noise-diluted sources
+# ---------------------------------------------------------------------------
+
+def test_noise_sources_full_dilution_are_laph_sources():
+    """n_dil = nev and rho = 1: the diluted noise sources are the perambulator's sources."""
+    dims = (2, 2, 2, 4)
+    V = ls.orthonormal_laph_vectors(dims, 3, 61)
+    b = laph.noise_sources(V, 2, np.ones((4, 3), dtype=np.complex128), 3)
+    assert np.array_equal(b, laph.laph_sources(V, 2))
+
+
+def test_stochastic_perambulator_is_noise_weighted_perambulator():
+    """D^-1 is linear: phi[t][l][j][beta][alpha] = sum_{k = j mod n_dil} tau[t][l][k][beta][alpha] rho[alpha][k]
+    (interlaced LapH dilution, full spin and time dilution; Z4 noise)."""
+    dims = (4, 4, 4, 4)
+    nev, n_dil, t0, m0 = 5, 2, 1, 0.1
+    U = ls.gauge_field(dims, 62)
+    V = ls.orthonormal_laph_vectors(dims, nev, 63)
+    rng = np.random.default_rng(64)
+    rho = np.exp(0.5j * np.pi * rng.integers(0, 4, size=(4, nev)))
+    tau, _ = laph.perambulator(U, V, t0, m0, method="dense")
+    phi, _ = laph.stochastic_perambulator(U, V, t0, m0, rho, n_dil, method="dense")
+    assert phi.shape == (dims[3], nev, n_dil, 4, 4)
+    want = np.zeros_like(phi)
+    for j in range(n_dil):
+        for k in range(nev):
+            if k % n_dil == j:
+                want[:, :, j] += tau[:, :, k] * rho[None, None, None, :, k]
+    assert _rel(phi, want) < 1e-12
+
+
+# ---------------------------------------------------------------------------
 # P13: FP16-with-norm codec
 # ---------------------------------------------------------------------------
 
