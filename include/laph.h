@@ -180,6 +180,25 @@ laph_status laph_perambulator(laph_ctx ctx, double *tau, const double *V, int ne
                               int mass_idx, double tol, const laph_solve_params *p,
                               laph_rhs_stats *stats_host, void *work, size_t work_bytes);
 
+/* Stochastic LapH (the noise-diluted variant of LapH the paper's earlier CPU work
+ * used, Sec. "Current state-of-the-art"): the caller's noise rho = c128 [4][nev] on
+ * the device (rho[alpha][k] for spin alpha and LapH index k of the source time t0;
+ * e.g. Z4 values) is diluted fully in time and spin and into n_dil interlaced LapH
+ * groups {k : k mod n_dil = j}, 1 <= n_dil <= nev.  Source r = 4j + alpha:
+ *   b^(4j+alpha)(x,t)_(s,a) = delta_{t,t0} delta_{s,alpha} sum_{k = j mod n_dil} rho[alpha][k] V_k(x,t0)_a
+ * laph_stochastic_perambulator solves the 4*n_dil sources like laph_perambulator and
+ * writes phi = c128 [Lt][nev][n_dil][4][4] = [t][l][j][beta][alpha] (the projection of
+ * the solutions onto the LapH vectors of every sink time); its workspace is
+ * laph_perambulator_workspace_bytes(ctx, nev, p); stats_host: 4*n_dil entries.
+ * With n_dil = nev and rho = 1, phi = tau.  laph_make_noise_sources writes the
+ * sources alone: B canonical, 4*n_dil RHS. */
+laph_status laph_stochastic_perambulator(laph_ctx ctx, double *phi, const double *V, int nev, int t0,
+                                         int mass_idx, const double *rho, int n_dil, double tol,
+                                         const laph_solve_params *p, laph_rhs_stats *stats_host,
+                                         void *work, size_t work_bytes);
+laph_status laph_make_noise_sources(laph_ctx ctx, double *B, const double *V, int nev, int t0,
+                                    const double *rho, int n_dil);
+
 /* Building blocks of the perambulator, exposed for the differentiable wrapper:
  *  laph_make_sources: B (canonical, 4*nev RHS) = spin-diluted sources at t0;
  *  laph_project:      tau (as above) from solutions X (canonical, 4*nev_src RHS);

@@ -58,6 +58,9 @@ _SIGS = [
     ("laph_perambulator", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_double,
                                   P(SolveParams), P(RhsStats), c_void_p, c_size_t]),
     ("laph_make_sources", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int]),
+    ("laph_stochastic_perambulator", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p, c_int,
+                                             c_double, P(SolveParams), P(RhsStats), c_void_p, c_size_t]),
+    ("laph_make_noise_sources", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p, c_int]),
     ("laph_laplacian_workspace_bytes", c_size_t, [c_void_p, c_int]),
     ("laph_apply_laplacian", c_int, [c_void_p, c_void_p, c_void_p, c_int]),
     ("laph_laplacian_eigvecs", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_double, c_int, c_int, c_void_p,

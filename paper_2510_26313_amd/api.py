@@ -274,6 +274,32 @@ class Lattice:
         """B[q][t][l][m][n] = sum_x exp(-i p_q.x) eps_abc V_l(x,t)_a V_m(x,t)_b V_n(x,t)_c."""
         return self._contract(1, self.lib.laph_baryon_triplets, V, moms)
 
+    def stochastic_perambulator_raw(self, V, t0, rho, n_dil, mass_idx=0, tol=1e-10, params=None):
+        """phi[t][l][j][beta][alpha] for the noise-diluted sources of rho [4][nev] (complex,
+        on the device) at t0 with n_dil interlaced LapH groups (fused solve + projection)."""
+        nev = V.shape[1]
+        _check_tensor(V, self.laph_shape(nev), "V")
+        _check_tensor(rho, (4, nev), "rho")
+        p = params if params is not None else default_params()
+        lt = self.dims[3]
+        phi = torch.zeros((lt, nev, int(n_dil), 4, 4), dtype=torch.complex128, device=self.device)
+        w = self._workspace(self.lib.laph_perambulator_workspace_bytes(self.ctx, nev, ctypes.byref(p)))
+        stats = (L.RhsStats * (4 * int(n_dil)))()
+        st = self._run(self.lib.laph_stochastic_perambulator, self.ctx, _ptr(phi), _ptr(V), nev, int(t0),
+                       int(mass_idx), _ptr(rho), int(n_dil), float(tol), ctypes.byref(p), stats, _ptr(w), w.numel())
+        sl = _stats_list(stats, 4 * int(n_dil))
+        L.check(st, sl)
+        return phi, sl
+
+    def make_noise_sources(self, V, t0, rho, n_dil):
+        nev = V.shape[1]
+        _check_tensor(V, self.laph_shape(nev), "V")
+        _check_tensor(rho, (4, nev), "rho")
+        B = torch.empty(self.spinor_shape(4 * int(n_dil)), dtype=torch.complex128, device=self.device)
+        L.check(self._run(self.lib.laph_make_noise_sources, self.ctx, _ptr(B), _ptr(V), nev, int(t0), _ptr(rho),
+                          int(n_dil)))
+        return B
+
     def make_sources(self, V, t0):
         nev = V.shape[1]
         _check_tensor(V, self.laph_shape(nev), "V")

@@ -397,8 +397,11 @@ size_t laph_perambulator_workspace_bytes(laph_ctx h, int nev, const laph_solve_p
     return packed_v_bytes(c, nev) + project_scratch_bytes(c, nev, chunk) + solver_workspace_bytes(c, chunk, *p);
 }
 
-laph_status laph_perambulator(laph_ctx h, double *tau, const double *V, int nev, int t0, int mass_idx, double tol,
-                              const laph_solve_params *p, laph_rhs_stats *stats_host, void *work, size_t work_bytes) {
+// sources -> batched solves -> projection, streamed in RHS chunks: the perambulator's
+// 4 nev sources (rho null) or 4 n_dil diluted noise sources
+static laph_status peramb_run(laph_ctx h, double *tau, const double *V, int nev, int t0, int mass_idx,
+                              const double *rho, int n_dil, double tol, const laph_solve_params *p,
+                              laph_rhs_stats *stats_host, void *work, size_t work_bytes) {
     LAPH_TRY(check_ctx(h, true, true));
     LAPH_TRY(check_params(p, tol));
     Ctx &c = C(h);
@@ -407,7 +410,8 @@ laph_status laph_perambulator(laph_ctx h, double *tau, const double *V, int nev,
     if (t0 < 0 || t0 >= c.g.lt) return set_error(LAPH_ERR_INVALID, "t0 out of range");
     if (mass_idx < 0 || mass_idx >= c.n_mass) return set_error(LAPH_ERR_INVALID, "mass index out of range");
     if (p->use_x0) return set_error(LAPH_ERR_INVALID, "use_x0 is not available for laph_perambulator");
-    const int chunk = peramb_chunk(nev, p);
+    const int nsrc = rho ? n_dil : nev;
+    const int chunk = peramb_chunk(nsrc, p);
     const size_t need = laph_perambulator_workspace_bytes(h, nev, p);
     if (!work || work_bytes < need) return set_error(LAPH_ERR_WORKSPACE, "perambulator workspace too small: %zu < %zu", work_bytes, need);
     char *w = reinterpret_cast<char *>(work);
@@ -416,7 +420,7 @@ laph_status laph_perambulator(laph_ctx h, double *tau, const double *V, int nev,
     char *swork = w + packed_v_bytes(c, nev) + project_scratch_bytes(c, nev, chunk);
     Solver solver;
     LAPH_TRY(solver.init(c, chunk, *p, swork, need - (swork - w), mass_idx));
-    const int nrhs = 4 * nev;
+    const int nrhs = 4 * nsrc;
     double ms_solve = 0, ms_proj = 0;
     LAPH_HIP(hipEventRecord(c.ev[0], c.stream));
     LAPH_TRY(pack_laph_vectors(c, Vp, V, nev));
@@ -429,6 +433,8 @@ laph_status laph_perambulator(laph_ctx h, double *tau, const double *V, int nev,
         src.t0 = t0;
         src.r_begin = r0;
         src.n = n;
+        src.rho = rho;
+        src.n_dil = n_dil;
         LAPH_HIP(hipEventRecord(c.ev[2], c.stream));
         LAPH_TRY(solver.solve(src, std::vector<int>(n, mass_idx), tol, nullptr, 0));
         LAPH_HIP(hipEventRecord(c.ev[3], c.stream));
@@ -439,7 +445,7 @@ laph_status laph_perambulator(laph_ctx h, double *tau, const double *V, int nev,
         ps.r_begin = r0;
         ps.Vp = Vp;
         ps.nev = nev;
-        ps.nev_src = nev;
+        ps.nev_src = nsrc;
         ps.tau = tau;
         ps.scratch = scratch;
         LAPH_TRY(project(c, ps));
@@ -462,6 +468,19 @@ laph_status laph_perambulator(laph_ctx h, double *tau, const double *V, int nev,
     c.last_ms[2] = ms_proj;
     if (worst != LAPH_OK) return set_error((laph_status)worst, "some right-hand sides did not converge (see stats)");
     return LAPH_OK;
+}
+
+laph_status laph_perambulator(laph_ctx h, double *tau, const double *V, int nev, int t0, int mass_idx, double tol,
+                              const laph_solve_params *p, laph_rhs_stats *stats_host, void *work, size_t work_bytes) {
+    return peramb_run(h, tau, V, nev, t0, mass_idx, nullptr, 0, tol, p, stats_host, work, work_bytes);
+}
+
+laph_status laph_stochastic_perambulator(laph_ctx h, double *phi, const double *V, int nev, int t0, int mass_idx,
+                                         const double *rho, int n_dil, double tol, const laph_solve_params *p,
+                                         laph_rhs_stats *stats_host, void *work, size_t work_bytes) {
+    if (!rho) return set_error(LAPH_ERR_INVALID, "null noise");
+    if (n_dil < 1 || n_dil > nev) return set_error(LAPH_ERR_INVALID, "n_dil must be in 1..nev");
+    return peramb_run(h, phi, V, nev, t0, mass_idx, rho, n_dil, tol, p, stats_host, work, work_bytes);
 }
 
 size_t laph_laplacian_workspace_bytes(laph_ctx h, int nev) {
@@ -511,6 +530,15 @@ laph_status laph_make_sources(laph_ctx h, double *B, const double *V, int nev, i
     Ctx &c = C(h);
     if (!B || !V || nev <= 0 || nev > 16383 || t0 < 0 || t0 >= c.g.lt) return set_error(LAPH_ERR_INVALID, "bad arguments");
     return make_sources_canonical(c, B, V, nev, t0);
+}
+
+laph_status laph_make_noise_sources(laph_ctx h, double *B, const double *V, int nev, int t0, const double *rho,
+                                    int n_dil) {
+    LAPH_TRY(check_ctx(h));
+    Ctx &c = C(h);
+    if (!B || !V || !rho || nev <= 0 || nev > 16383 || t0 < 0 || t0 >= c.g.lt || n_dil < 1 || n_dil > nev)
+        return set_error(LAPH_ERR_INVALID, "bad arguments");
+    return make_sources_canonical(c, B, V, nev, t0, rho, n_dil);
 }
 
 size_t laph_project_workspace_bytes(laph_ctx h, int nev, int nev_src) {

@@ -17,12 +17,15 @@ struct SourceSpec {
     const double *V = nullptr;
     int nev = 0, t0 = 0, r_begin = 0;
     int n = 0;
+    const double *rho = nullptr;   // noise [4][nev] complex (null: the perambulator's sources)
+    int n_dil = 0;
 };
 
 // b^(r)(x, t)_(s, a) = delta_{t,t0} delta_{s,alpha} V_k(x, t0)_a, r = 4k + alpha, for
-// r = r_begin .. r_begin + n - 1, into FP64 even (E) and odd (O) half-vectors.
+// r = r_begin .. r_begin + n - 1, into FP64 even (E) and odd (O) half-vectors; with
+// noise rho, r = 4j + alpha and V_k becomes sum_{k = j mod n_dil} rho[alpha][k] V_k.
 laph_status make_laph_sources(const Ctx &c, Operand E, Operand O, const double *V, int nev, int t0, int r_begin,
-                              int n);
+                              int n, const double *rho = nullptr, int n_dil = 0);
 
 // Projection of FP64 internal solutions onto the LapH vectors of every sink
 // timeslice, accumulated into tau[t][l][k][beta][alpha] for RHS r = r_begin + s.
@@ -41,7 +44,8 @@ laph_status pack_laph_vectors(const Ctx &c, double *Vp, const double *V, int nev
 size_t project_scratch_bytes(const Ctx &c, int nev, int n);
 laph_status project(const Ctx &c, const ProjectSpec &s);
 laph_status project_adjoint(const Ctx &c, double *GX, const double *Gtau, const double *V, int nev, int nev_src);
-laph_status make_sources_canonical(const Ctx &c, double *B, const double *V, int nev, int t0);
+laph_status make_sources_canonical(const Ctx &c, double *B, const double *V, int nev, int t0,
+                                   const double *rho = nullptr, int n_dil = 0);
 
 // LapH eigenvectors (laplace.hip): out[t][j] = (-Delta) in[t][j] per timeslice, and the
 // lowest nev eigenpairs of -Delta on every timeslice (Chebyshev-filtered subspace

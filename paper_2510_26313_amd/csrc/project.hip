@@ -23,7 +23,28 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------------------
 // sources
 // ---------------------------------------------------------------------------
-__global__ void laph_sources_kernel(Geom g, Operand E, Operand O, const double2 *V, int nev, int t0, int r_begin) {
+// Without noise (rho null) RHS r = 4k + alpha is V_k on spin alpha.  With noise, RHS
+// r = 4j + alpha is the diluted noise source sum_{k = j mod n_dil} rho[alpha][k] V_k on
+// spin alpha (interlaced LapH dilution, full spin and time dilution).
+__device__ __forceinline__ cplx<double> source_colour(const double2 *V, const double2 *rho, int nev, int n_dil,
+                                                      size_t v3, int t0, size_t site3, int r, int a) {
+    const int kj = r >> 2, alpha = r & 3;
+    if (!rho) {
+        const double2 v = V[(((size_t)t0 * nev + kj) * v3 + site3) * 3 + a];
+        return {v.x, v.y};
+    }
+    cplx<double> acc = {0.0, 0.0};
+    for (int k = kj; k < nev; k += n_dil) {
+        const double2 v = V[(((size_t)t0 * nev + k) * v3 + site3) * 3 + a];
+        const double2 q = rho[(size_t)alpha * nev + k];
+        acc.re += q.x * v.x - q.y * v.y;
+        acc.im += q.x * v.y + q.y * v.x;
+    }
+    return acc;
+}
+
+__global__ void laph_sources_kernel(Geom g, Operand E, Operand O, const double2 *V, int nev, int t0, int r_begin,
+                                    const double2 *rho, int n_dil) {
     const int h = blockIdx.x * 256 + threadIdx.x;
     const int s = blockIdx.y;
     const int p = blockIdx.z;
@@ -31,29 +52,31 @@ __global__ void laph_sources_kernel(Geom g, Operand E, Operand O, const double2 
     int x, y, z, t;
     site_coords(g, p, h, x, y, z, t);
     const int r = r_begin + s;
-    const int k = r >> 2, alpha = r & 3;
+    const int alpha = r & 3;
     cplx<double> out[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) out[c] = {0.0, 0.0};
     if (t == t0) {
         const size_t site3 = (size_t)x + (size_t)g.lx * (y + (size_t)g.ly * z);
-        const double2 *v = V + (((size_t)t0 * nev + k) * g.lx * g.ly * g.lz + site3) * 3;
+        const size_t v3 = (size_t)g.lx * g.ly * g.lz;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) out[3 * alpha + a] = {v[a].x, v[a].y};
+        for (int a = 0; a < 3; ++a) out[3 * alpha + a] = source_colour(V, rho, nev, n_dil, v3, t0, site3, r, a);
     }
     SpinorIO<F64>::store((p == 0 ? E : O).at(s), g.vh, h, out);
 }
 
 laph_status make_laph_sources(const Ctx &c, Operand E, Operand O, const double *V, int nev, int t0, int r_begin,
-                              int n) {
+                              int n, const double *rho, int n_dil) {
     if (n <= 0) return LAPH_OK;
     dim3 grid((c.g.vh + 255) / 256, n, 2);
     hipLaunchKernelGGL(laph_sources_kernel, grid, dim3(256), 0, c.stream, c.g, E, O,
-                       reinterpret_cast<const double2 *>(V), nev, t0, r_begin);
+                       reinterpret_cast<const double2 *>(V), nev, t0, r_begin, reinterpret_cast<const double2 *>(rho),
+                       n_dil);
     return check_launch("laph_sources_kernel");
 }
 
-__global__ void sources_canonical_kernel(Geom g, double2 *B, const double2 *V, int nev, int t0) {
+__global__ void sources_canonical_kernel(Geom g, double2 *B, const double2 *V, int nev, int t0, const double2 *rho,
+                                         int n_dil) {
     const long i = (long)blockIdx.x * 256 + threadIdx.x;
     const int r = blockIdx.y;
     const long vol = 2L * g.vh;
@@ -61,20 +84,23 @@ __global__ void sources_canonical_kernel(Geom g, double2 *B, const double2 *V, i
     const long v3 = (long)g.lx * g.ly * g.lz;
     const int t = (int)(i / v3);
     const long site3 = i % v3;
-    const int k = r >> 2, alpha = r & 3;
+    const int alpha = r & 3;
     double2 *dst = B + ((size_t)r * vol + i) * 12;
     for (int c = 0; c < 12; ++c) dst[c] = make_double2(0.0, 0.0);
     if (t == t0) {
-        const double2 *v = V + (((size_t)t0 * nev + k) * v3 + site3) * 3;
-        for (int a = 0; a < 3; ++a) dst[3 * alpha + a] = v[a];
+        for (int a = 0; a < 3; ++a) {
+            const cplx<double> v = source_colour(V, rho, nev, n_dil, (size_t)v3, t0, (size_t)site3, r, a);
+            dst[3 * alpha + a] = make_double2(v.re, v.im);
+        }
     }
 }
 
-laph_status make_sources_canonical(const Ctx &c, double *B, const double *V, int nev, int t0) {
+laph_status make_sources_canonical(const Ctx &c, double *B, const double *V, int nev, int t0, const double *rho,
+                                   int n_dil) {
     const long vol = 2L * c.g.vh;
-    dim3 grid((unsigned)((vol + 255) / 256), 4 * nev);
+    dim3 grid((unsigned)((vol + 255) / 256), 4 * (rho ? n_dil : nev));
     hipLaunchKernelGGL(sources_canonical_kernel, grid, dim3(256), 0, c.stream, c.g, reinterpret_cast<double2 *>(B),
-                       reinterpret_cast<const double2 *>(V), nev, t0);
+                       reinterpret_cast<const double2 *>(V), nev, t0, reinterpret_cast<const double2 *>(rho), n_dil);
     return check_launch("sources_canonical_kernel");
 }
 

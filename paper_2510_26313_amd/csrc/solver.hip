@@ -437,7 +437,7 @@ laph_status Solver::load_sources(const SourceSpec &src) {
         LAPH_TRY(pack_spinor(*c, o, src.B, LAPH_F64, src.n, 1, src.B_stride));
         return LAPH_OK;
     }
-    return make_laph_sources(*c, ws.E0, ws.O1, src.V, src.nev, src.t0, src.r_begin, src.n);
+    return make_laph_sources(*c, ws.E0, ws.O1, src.V, src.nev, src.t0, src.r_begin, src.n, src.rho, src.n_dil);
 }
 
 // ---- the full solve of n slots ----------------------------------------------------
