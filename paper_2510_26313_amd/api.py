@@ -71,6 +71,7 @@ class Lattice:
         L.check(self._run(self.lib.laph_attach_state, self.ctx, ctypes.c_void_p(self._state.data_ptr() + off), nbytes))
         self.masses = ()
         self.csw = None
+        self._scratch_buf = None
         lx, ly, lz, lt = self.dims
         self.volume = lx * ly * lz * lt
 
@@ -110,6 +111,20 @@ class Lattice:
 
     def _workspace(self, nbytes):
         return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
+
+    def _scratch(self, nbytes):
+        """Device workspace of one library call: one buffer per lattice, kept between calls
+        and grown on demand.  Calls run in order on the lattice's stream, so reuse is safe;
+        keeping it avoids re-allocating (and fragmenting) buffers of up to ~180 GB."""
+        n = max(int(nbytes), 256)
+        if self._scratch_buf is None or self._scratch_buf.numel() < n:
+            self._scratch_buf = None
+            self._scratch_buf = torch.empty(n, dtype=torch.uint8, device=self.device)
+        return self._scratch_buf
+
+    def release_scratch(self):
+        """Return the kept workspace to PyTorch's allocator."""
+        self._scratch_buf = None
 
     # -- setup ----------------------------------------------------------------------
     def load_gauge(self, U):
@@ -161,7 +176,7 @@ class Lattice:
         n = psi.shape[0]
         _check_tensor(psi, self.spinor_shape(n), "psi")
         out = torch.empty_like(psi)
-        w = self._workspace(self.field_bytes("f64", 2, False))
+        w = self._scratch(self.field_bytes("f64", 2, False))
         L.check(self._run(self.lib.laph_apply_D, self.ctx, _ptr(out), _ptr(psi), mass_idx, n, int(dagger), _ptr(w),
                                       w.numel()))
         return out
@@ -182,7 +197,7 @@ class Lattice:
         else:
             X = torch.empty_like(B)
             p.use_x0 = 0
-        w = self._workspace(self.lib.laph_solve_workspace_bytes(self.ctx, n, ctypes.byref(p)))
+        w = self._scratch(self.lib.laph_solve_workspace_bytes(self.ctx, n, ctypes.byref(p)))
         stats = (L.RhsStats * n)()
         st = self._run(self.lib.laph_solve, self.ctx, _ptr(X), _ptr(B), n, mi, float(tol), ctypes.byref(p), stats,
                                  _ptr(w), w.numel())
@@ -198,7 +213,7 @@ class Lattice:
         p = params if params is not None else default_params()
         lt = self.dims[3]
         tau = torch.zeros((lt, nev, nev, 4, 4), dtype=torch.complex128, device=self.device)
-        w = self._workspace(self.lib.laph_perambulator_workspace_bytes(self.ctx, nev, ctypes.byref(p)))
+        w = self._scratch(self.lib.laph_perambulator_workspace_bytes(self.ctx, nev, ctypes.byref(p)))
         stats = (L.RhsStats * (4 * nev))()
         st = self._run(self.lib.laph_perambulator, self.ctx, _ptr(tau), _ptr(V), nev, int(t0), int(mass_idx), float(tol),
                                         ctypes.byref(p), stats, _ptr(w), w.numel())
@@ -216,7 +231,7 @@ class Lattice:
 
     def time_stages(self, prec, nrhs, rhs_tile=4, mass_idx=0, reps=20, stencil=2, traversal=2):
         """Average ms per launch of the solver's two fused stencil stages (HIP events)."""
-        w = self._workspace(self.lib.laph_time_stages_workspace_bytes(self.ctx, L.PREC[prec], nrhs, rhs_tile))
+        w = self._scratch(self.lib.laph_time_stages_workspace_bytes(self.ctx, L.PREC[prec], nrhs, rhs_tile))
         ms = (ctypes.c_double * 2)()
         L.check(self._run(self.lib.laph_time_stages, self.ctx, L.PREC[prec], nrhs, stencil, rhs_tile, traversal,
                           mass_idx, reps, _ptr(w), w.numel(), ms))
@@ -224,7 +239,7 @@ class Lattice:
 
     def autotune(self, prec, nrhs, mass_idx=0):
         """Measure and keep the fastest stencil form / RHS per link load for this batch size."""
-        w = self._workspace(self.lib.laph_time_stages_workspace_bytes(self.ctx, L.PREC[prec], nrhs, 16))
+        w = self._scratch(self.lib.laph_time_stages_workspace_bytes(self.ctx, L.PREC[prec], nrhs, 16))
         st, tile, trav, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
         L.check(self._run(self.lib.laph_autotune, self.ctx, L.PREC[prec], nrhs, mass_idx, _ptr(w), w.numel(),
                           ctypes.byref(st), ctypes.byref(tile), ctypes.byref(trav), ctypes.byref(ms)))
@@ -245,7 +260,7 @@ class Lattice:
         lt = self.dims[3]
         V = torch.empty(self.laph_shape(nev), dtype=torch.complex128, device=self.device)
         lam = np.zeros((lt, nev))
-        w = self._workspace(self.lib.laph_laplacian_workspace_bytes(self.ctx, nev))
+        w = self._scratch(self.lib.laph_laplacian_workspace_bytes(self.ctx, nev))
         its, res = ctypes.c_int(0), ctypes.c_double(0)
         st = self._run(self.lib.laph_laplacian_eigvecs, self.ctx, _ptr(V),
                        lam.ctypes.data_as(ctypes.c_void_p), int(nev), float(tol), int(max_iter), int(degree),
@@ -260,7 +275,7 @@ class Lattice:
         nm = mom.shape[0]
         shape = (nm, self.dims[3]) + (nev,) * (2 + kind)
         out = torch.empty(shape, dtype=torch.complex128, device=self.device)
-        w = self._workspace(self.lib.laph_contract_workspace_bytes(self.ctx, kind, nev, nm))
+        w = self._scratch(self.lib.laph_contract_workspace_bytes(self.ctx, kind, nev, nm))
         L.check(self._run(fn, self.ctx, _ptr(out), _ptr(V), nev, nm, mom.ctypes.data_as(ctypes.c_void_p),
                           _ptr(w), w.numel()))
         return out
@@ -283,7 +298,7 @@ class Lattice:
         p = params if params is not None else default_params()
         lt = self.dims[3]
         phi = torch.zeros((lt, nev, int(n_dil), 4, 4), dtype=torch.complex128, device=self.device)
-        w = self._workspace(self.lib.laph_perambulator_workspace_bytes(self.ctx, nev, ctypes.byref(p)))
+        w = self._scratch(self.lib.laph_perambulator_workspace_bytes(self.ctx, nev, ctypes.byref(p)))
         stats = (L.RhsStats * (4 * int(n_dil)))()
         st = self._run(self.lib.laph_stochastic_perambulator, self.ctx, _ptr(phi), _ptr(V), nev, int(t0),
                        int(mass_idx), _ptr(rho), int(n_dil), float(tol), ctypes.byref(p), stats, _ptr(w), w.numel())
@@ -316,7 +331,7 @@ class Lattice:
         _check_tensor(X, self.spinor_shape(n), "X")
         lt = self.dims[3]
         tau = torch.zeros((lt, nev, n // 4, 4, 4), dtype=torch.complex128, device=self.device)
-        w = self._workspace(self.lib.laph_project_workspace_bytes(self.ctx, nev, n // 4))
+        w = self._scratch(self.lib.laph_project_workspace_bytes(self.ctx, nev, n // 4))
         L.check(self._run(self.lib.laph_project, self.ctx, _ptr(tau), _ptr(X), _ptr(V), nev, n // 4, _ptr(w), w.numel()))
         return tau
 

@@ -14,8 +14,8 @@
 // workgroup stages the V of a chunk of sites (all nev vectors) in LDS; each wave
 // forms its A and B fragments from there (the cross products are never stored)
 // and runs the FP64 matrix cores.  B_p is antisymmetric in every index pair, so
-// only l < m < n is accumulated (a wave skips row blocks with no l below the
-// pairs' m), and the reduction writes all six orderings with their signs and
+// only l < m < n is accumulated (a wave runs only the row blocks with some l below
+// its pairs' largest m), and the reduction writes all six orderings with their signs and
 // zeros where an index repeats.  K is split over workgroups for occupancy; the
 // reduction sums the slices in a fixed order.
 #include <algorithm>
@@ -59,6 +59,62 @@ __device__ __forceinline__ void pair_of(int q, int nev, int &m, int &n) {
     n = q - pair_base(m, nev) + m + 1;
 }
 
+// One staged chunk: the wave's A fragments (R row blocks) and B fragments (NCB column
+// blocks) per group of 4 K, then the R x NCB x 4 real products as straight-line code,
+// each product's accumulator written by the previous group's product of the same kind
+// only (independent accumulators back to back).
+template <int MODE, int NCB, int R>
+__device__ __forceinline__ void chunk_products(const double (*Vr)[kCLd], const double (*Vi)[kCLd],
+                                               const double *phr, const double *phim, int lane, const int *cm,
+                                               const int *cn, d4 (*cre)[NCB], d4 (*cim)[NCB]) {
+#pragma unroll 2
+    for (int k4 = 0; k4 < kCK; k4 += 4) {
+        const int kk = k4 + (lane >> 4);
+        const int sl = kk / 3, a = kk - 3 * sl;
+        const double pr = phr[sl], pi = phim[sl];
+        double ar[R], ai[R], nai[R], br[NCB], bi[NCB];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int row = 16 * i + (lane & 15);
+            const double vr = Vr[row][kk], vi = MODE == 0 ? -Vi[row][kk] : Vi[row][kk];
+            ar[i] = pr * vr - pi * vi;
+            ai[i] = pr * vi + pi * vr;
+            nai[i] = -ai[i];
+        }
+#pragma unroll
+        for (int j = 0; j < NCB; ++j) {
+            if (MODE == 0) {
+                br[j] = Vr[cm[j]][kk];
+                bi[j] = Vi[cm[j]][kk];
+            } else {
+                // (V_m x V_n)_a = V_m,b V_n,c - V_m,c V_n,b with (a, b, c) cyclic
+                const int kb = 3 * sl + (a == 2 ? 0 : a + 1), kc = 3 * sl + (a == 0 ? 2 : a - 1);
+                const double ubr = Vr[cm[j]][kb], ubi = Vi[cm[j]][kb];
+                const double ucr = Vr[cm[j]][kc], uci = Vi[cm[j]][kc];
+                const double wbr = Vr[cn[j]][kb], wbi = Vi[cn[j]][kb];
+                const double wcr = Vr[cn[j]][kc], wci = Vi[cn[j]][kc];
+                br[j] = (ubr * wcr - ubi * wci) - (ucr * wbr - uci * wbi);
+                bi[j] = (ubr * wci + ubi * wcr) - (ucr * wbi + uci * wbr);
+            }
+        }
+        // Re += Ar Br - Ai Bi;  Im += Ar Bi + Ai Br
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+            for (int j = 0; j < NCB; ++j) {
+                cre[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], cre[i][j], 0, 0, 0);
+                cim[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], cim[i][j], 0, 0, 0);
+            }
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+            for (int j = 0; j < NCB; ++j) {
+                cre[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[i], bi[j], cre[i][j], 0, 0, 0);
+                cim[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], cim[i][j], 0, 0, 0);
+            }
+    }
+}
+
 // NCB column blocks of 16 per wave: 4 NCB 16 columns per workgroup
 template <int MODE, int NCB>
 __global__ __launch_bounds__(kCB) void contract_kernel(ContractArgs A) {
@@ -79,30 +135,29 @@ __global__ __launch_bounds__(kCB) void contract_kernel(ContractArgs A) {
     constexpr int kCols = 4 * NCB * 16;
     const int nev = A.nev;
 
-    // this lane's column per block, the pair behind it, and the blocks' active rows
+    // this lane's column per block, the pair behind it, and the number of 16-row
+    // blocks the wave needs (wave-uniform: triplets need l < m, m at most the m of the
+    // wave's last pair)
     int col[NCB], cm[NCB], cn[NCB];
-    unsigned act = 0;   // bit 4 j + i: row block i, column block j
+    int rows_hi = 0;
 #pragma unroll
     for (int j = 0; j < NCB; ++j) {
         const int c0 = tile * kCols + (wave * NCB + j) * 16;
         col[j] = c0 + (lane & 15);
         cm[j] = 0;
         cn[j] = 0;
-        if (c0 >= A.ncol) continue;
-        int rows_hi = nev;   // rows below this bound take part
+        if (c0 >= A.ncol) continue;   // a block past the last column: zero B (V_0 x V_0, or column 0 unread)
         if (MODE == 1) {
-            const int cc = col[j] < A.ncol ? col[j] : A.ncol - 1;
-            pair_of(cc, nev, cm[j], cn[j]);
+            if (col[j] < A.ncol) pair_of(col[j], nev, cm[j], cn[j]);
             int mlast, nlast;
             pair_of(min(c0 + 15, A.ncol - 1), nev, mlast, nlast);
-            rows_hi = mlast;   // l < m <= m of the block's last pair
+            rows_hi = max(rows_hi, mlast);
         } else {
             cm[j] = col[j] < A.ncol ? col[j] : 0;
+            rows_hi = nev;
         }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (16 * i < rows_hi) act |= 1u << (4 * j + i);
     }
+    const int nact = min(4, (rows_hi + 15) / 16);
 
     d4 cre[4][NCB], cim[4][NCB];
 #pragma unroll
@@ -141,45 +196,12 @@ __global__ __launch_bounds__(kCB) void contract_kernel(ContractArgs A) {
             phim[tid] = sn;
         }
         __syncthreads();
-#pragma unroll 2
-        for (int k4 = 0; k4 < kCK; k4 += 4) {
-            const int kk = k4 + (lane >> 4);
-            const int sl = kk / 3, a = kk - 3 * sl;
-            const double pr = phr[sl], pi = phim[sl];
-            double ar[4], ai[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int row = 16 * i + (lane & 15);
-                const double vr = Vr[row][kk], vi = MODE == 0 ? -Vi[row][kk] : Vi[row][kk];
-                ar[i] = pr * vr - pi * vi;
-                ai[i] = pr * vi + pi * vr;
-            }
-#pragma unroll
-            for (int j = 0; j < NCB; ++j) {
-                if (!((act >> (4 * j)) & 15u)) continue;
-                double br, bi;
-                if (MODE == 0) {
-                    br = Vr[cm[j]][kk];
-                    bi = Vi[cm[j]][kk];
-                } else {
-                    // (V_m x V_n)_a = V_m,b V_n,c - V_m,c V_n,b with (a, b, c) cyclic
-                    const int kb = 3 * sl + (a == 2 ? 0 : a + 1), kc = 3 * sl + (a == 0 ? 2 : a - 1);
-                    const double ubr = Vr[cm[j]][kb], ubi = Vi[cm[j]][kb];
-                    const double ucr = Vr[cm[j]][kc], uci = Vi[cm[j]][kc];
-                    const double wbr = Vr[cn[j]][kb], wbi = Vi[cn[j]][kb];
-                    const double wcr = Vr[cn[j]][kc], wci = Vi[cn[j]][kc];
-                    br = (ubr * wcr - ubi * wci) - (ucr * wbr - uci * wbi);
-                    bi = (ubr * wci + ubi * wcr) - (ucr * wbi + uci * wbr);
-                }
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    if (!((act >> (4 * j + i)) & 1u)) continue;
-                    cre[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br, cre[i][j], 0, 0, 0);
-                    cre[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], bi, cre[i][j], 0, 0, 0);
-                    cim[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi, cim[i][j], 0, 0, 0);
-                    cim[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br, cim[i][j], 0, 0, 0);
-                }
-            }
+        switch (nact) {
+            case 4: chunk_products<MODE, NCB, 4>(Vr, Vi, phr, phim, lane, cm, cn, cre, cim); break;
+            case 3: chunk_products<MODE, NCB, 3>(Vr, Vi, phr, phim, lane, cm, cn, cre, cim); break;
+            case 2: chunk_products<MODE, NCB, 2>(Vr, Vi, phr, phim, lane, cm, cn, cre, cim); break;
+            case 1: chunk_products<MODE, NCB, 1>(Vr, Vi, phr, phim, lane, cm, cn, cre, cim); break;
+            default: break;
         }
         __syncthreads();
     }
