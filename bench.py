@@ -125,6 +125,11 @@ def stored_traffic(key):
     return None
 
 
+def progress(msg):
+    """A progress line on stderr (stdout carries only the result line)."""
+    print("[bench] %s" % msg, file=sys.stderr, flush=True)
+
+
 def _timed(torch, fn):
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -393,9 +398,11 @@ def main():
                                  stencil=args.stencil, traversal=args.traversal)
     setup_s = time.perf_counter() - t_setup
     t0s = cfg["t0s"]
+    progress("setup done in %.1f s (autotuned: %s)" % (setup_s, tuned))
 
     for i in range(args.warmup):
         lat.perambulator_raw(Vd, t0s[i % len(t0s)], 0, tol, params)
+        progress("warmup step %d done" % i)
     torch.cuda.synchronize()
     stats_all = []
     ms_solve = ms_proj = 0.0
@@ -406,6 +413,7 @@ def main():
         ms_solve += tm["solve_ms"]
         ms_proj += tm["project_ms"]
         stats_all += st
+        progress("timed step %d done" % i)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     n_rhs = args.steps * 4 * nev
@@ -429,6 +437,7 @@ def main():
                 "speedup_of_batched_mixed": round(value / (args.fp64_sample / dt), 2)}
         del B
 
+    progress("FP64 single-RHS comparison done")
     # projection: 8 flop per complex multiply-add, nev sinks x 4 spins x 3 colours x L^3 sites x T
     # timeslices per RHS
     proj_flops = 8.0 * nev * 4 * 3 * dims[0] * dims[1] * dims[2] * dims[3] * n_rhs
@@ -506,6 +515,7 @@ def main():
         torch.cuda.empty_cache()
         out["detail"]["extra"] = extra_suite(laph, torch)
     if not args.no_cpu_baseline:
+        progress("GPU measurements done; timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(cfg, dims, U, v_src, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

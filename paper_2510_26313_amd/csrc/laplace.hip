@@ -75,8 +75,16 @@ __global__ __launch_bounds__(kLB) void lap_kernel(LapArgs A) {
     __shared__ int nbr[6][kLapSites];
     const Geom &g = A.g;
     const int vs = g.lx * g.ly * g.lz;
-    const int t = blockIdx.y;
-    const int s0 = blockIdx.x * kLapSites;
+    // XCD-aware order: consecutive workgroup ids go round-robin over the 8 XCDs, so id
+    // b is remapped to give each XCD a contiguous range of (timeslice, row) blocks; the
+    // y and z neighbour rows of a block then run on the same XCD, close in time, and
+    // their vectors are shared in its L2
+    const int nrow = (vs + kLapSites - 1) / kLapSites;
+    const int nblk = gridDim.x;
+    int bid = blockIdx.x;
+    if (nblk % 8 == 0) bid = (bid % 8) * (nblk / 8) + bid / 8;
+    const int t = bid / nrow;
+    const int s0 = (bid - t * nrow) * kLapSites;
     // ---- phase 1: links and neighbours (thread -> (hop, site))
     for (int q = threadIdx.x; q < 6 * kLapSites; q += kLB) {
         const int hop = q / kLapSites, site = q - hop * kLapSites;
@@ -609,7 +617,7 @@ struct EigRun {
         a.m = m;
         a.nvec = m;
         a.coef = coef;
-        dim3 grid((vs + kLapSites - 1) / kLapSites, lt);
+        dim3 grid(((vs + kLapSites - 1) / kLapSites) * lt);
         if (a.z) hipLaunchKernelGGL((lap_kernel<true, true>), grid, dim3(kLB), 0, c.stream, a);
         else hipLaunchKernelGGL((lap_kernel<false, true>), grid, dim3(kLB), 0, c.stream, a);
         return check_launch("lap_kernel");
@@ -673,7 +681,7 @@ laph_status apply_neg_laplacian(const Ctx &c, double *out, const double *in, int
     a.nvec = nvec;
     a.coef = nullptr;
     const int vs = c.g.lx * c.g.ly * c.g.lz;
-    dim3 grid((vs + kLapSites - 1) / kLapSites, c.g.lt);
+    dim3 grid(((vs + kLapSites - 1) / kLapSites) * c.g.lt);
     hipLaunchKernelGGL((lap_kernel<false, false>), grid, dim3(kLB), 0, c.stream, a);
     return check_launch("lap_kernel");
 }
