@@ -11,9 +11,10 @@
 //   doublets  A[l][(x, a)] = e^{-i p.x} conj(V_l(x)_a),  B[(x, a)][m]      = V_m(x)_a
 //   triplets  A[l][(x, a)] = e^{-i p.x} V_l(x)_a,        B[(x, a)][(m, n)] = (V_m(x) x V_n(x))_a
 // where the triplet's B column is the colour cross product of a pair m < n.  A
-// workgroup stages the V of a chunk of sites (all nev vectors) in LDS; each wave
-// forms its A and B fragments from there (the cross products are never stored)
-// and runs the FP64 matrix cores.  B_p is antisymmetric in every index pair, so
+// workgroup stages the V of a chunk of sites (all nev vectors) in LDS with the
+// direct global-to-LDS loads, two chunks deep, so the next chunk arrives while the
+// matrix cores work on the current one; each wave forms its A and B fragments from
+// LDS (the cross products are never stored).  B_p is antisymmetric in every index pair, so
 // only l < m < n is accumulated (a wave runs only the row blocks with some l below
 // its pairs' largest m), and the reduction writes all six orderings with their signs and
 // zeros where an index repeats.  K is split over workgroups for occupancy; the
@@ -28,9 +29,10 @@ namespace laph {
 namespace {
 
 constexpr int kCB = 256;          // threads per workgroup (4 waves)
-constexpr int kCS = 16;           // sites per K chunk
+constexpr int kCS = 8;            // sites per K chunk
 constexpr int kCK = 3 * kCS;      // K (site, colour) per chunk
-constexpr int kCLd = kCK + 1;     // LDS row stride in doubles
+constexpr int kRS = kCK + 1;      // LDS row stride in complex (odd: conflict-free fragment reads)
+constexpr int kSlots = 64 * kRS;  // complex slots of one staged chunk (64 rows)
 constexpr int kCRows = 64;        // l rows: nev <= 64
 constexpr int kCMaxMom = 16;      // momenta per launch
 constexpr int kCTarget = 2048;    // workgroups aimed for by the K split
@@ -64,37 +66,35 @@ __device__ __forceinline__ void pair_of(int q, int nev, int &m, int &n) {
 // each product's accumulator written by the previous group's product of the same kind
 // only (independent accumulators back to back).
 template <int MODE, int NCB, int R>
-__device__ __forceinline__ void chunk_products(const double (*Vr)[kCLd], const double (*Vi)[kCLd],
-                                               const double *phr, const double *phim, int lane, const int *cm,
+__device__ __forceinline__ void chunk_products(const double2 *buf, const double2 *ph, int lane, const int *cm,
                                                const int *cn, d4 (*cre)[NCB], d4 (*cim)[NCB]) {
 #pragma unroll 2
     for (int k4 = 0; k4 < kCK; k4 += 4) {
         const int kk = k4 + (lane >> 4);
         const int sl = kk / 3, a = kk - 3 * sl;
-        const double pr = phr[sl], pi = phim[sl];
+        const double2 f = ph[sl];
         double ar[R], ai[R], nai[R], br[NCB], bi[NCB];
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-            const int row = 16 * i + (lane & 15);
-            const double vr = Vr[row][kk], vi = MODE == 0 ? -Vi[row][kk] : Vi[row][kk];
-            ar[i] = pr * vr - pi * vi;
-            ai[i] = pr * vi + pi * vr;
+            const double2 v = buf[(16 * i + (lane & 15)) * kRS + kk];
+            const double vi = MODE == 0 ? -v.y : v.y;
+            ar[i] = f.x * v.x - f.y * vi;
+            ai[i] = f.x * vi + f.y * v.x;
             nai[i] = -ai[i];
         }
 #pragma unroll
         for (int j = 0; j < NCB; ++j) {
             if (MODE == 0) {
-                br[j] = Vr[cm[j]][kk];
-                bi[j] = Vi[cm[j]][kk];
+                const double2 v = buf[cm[j] * kRS + kk];
+                br[j] = v.x;
+                bi[j] = v.y;
             } else {
                 // (V_m x V_n)_a = V_m,b V_n,c - V_m,c V_n,b with (a, b, c) cyclic
                 const int kb = 3 * sl + (a == 2 ? 0 : a + 1), kc = 3 * sl + (a == 0 ? 2 : a - 1);
-                const double ubr = Vr[cm[j]][kb], ubi = Vi[cm[j]][kb];
-                const double ucr = Vr[cm[j]][kc], uci = Vi[cm[j]][kc];
-                const double wbr = Vr[cn[j]][kb], wbi = Vi[cn[j]][kb];
-                const double wcr = Vr[cn[j]][kc], wci = Vi[cn[j]][kc];
-                br[j] = (ubr * wcr - ubi * wci) - (ucr * wbr - uci * wbi);
-                bi[j] = (ubr * wci + ubi * wcr) - (ucr * wbi + uci * wbr);
+                const double2 ub = buf[cm[j] * kRS + kb], uc = buf[cm[j] * kRS + kc];
+                const double2 wb = buf[cn[j] * kRS + kb], wc = buf[cn[j] * kRS + kc];
+                br[j] = (ub.x * wc.x - ub.y * wc.y) - (uc.x * wb.x - uc.y * wb.y);
+                bi[j] = (ub.x * wc.y + ub.y * wc.x) - (uc.x * wb.y + uc.y * wb.x);
             }
         }
         // Re += Ar Br - Ai Bi;  Im += Ar Bi + Ai Br
@@ -115,11 +115,41 @@ __device__ __forceinline__ void chunk_products(const double (*Vr)[kCLd], const d
     }
 }
 
+template <int MODE, int NCB>
+__device__ __forceinline__ void chunk_dispatch(int nact, const double2 *buf, const double2 *ph, int lane,
+                                               const int *cm, const int *cn, d4 (*cre)[NCB], d4 (*cim)[NCB]) {
+    switch (nact) {
+        case 4: chunk_products<MODE, NCB, 4>(buf, ph, lane, cm, cn, cre, cim); break;
+        case 3: chunk_products<MODE, NCB, 3>(buf, ph, lane, cm, cn, cre, cim); break;
+        case 2: chunk_products<MODE, NCB, 2>(buf, ph, lane, cm, cn, cre, cim); break;
+        case 1: chunk_products<MODE, NCB, 1>(buf, ph, lane, cm, cn, cre, cim); break;
+        default: break;
+    }
+}
+
+// Copy chunk s0 of every vector (64 rows, nev real) into LDS with the direct
+// global-to-LDS loads: lane i of load q fills slot 64 q + i of the buffer, so each
+// lane fetches the element that lands in its slot.  Pad slots and rows or sites
+// outside the data load the timeslice's first element (finite; the zero phase of a
+// site outside the lattice cancels it, and pad slots and rows past nev are not read
+// into any kept product).
+__device__ __forceinline__ void stage_chunk(double2 *buf, const double2 *Vt, int nev, int n3, int s0, int wave,
+                                            int lane) {
+    for (int q = wave; q < kSlots / 64; q += 4) {
+        const int e = 64 * q + lane;
+        const int row = e / kRS, col = e - row * kRS;
+        const double2 *src = Vt;
+        if (col < kCK && row < nev && 3 * s0 + col < n3) src = Vt + (size_t)row * n3 + 3 * s0 + col;
+        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(buf + 64 * q), 16, 0, 0);
+    }
+}
+
 // NCB column blocks of 16 per wave: 4 NCB 16 columns per workgroup
 template <int MODE, int NCB>
 __global__ __launch_bounds__(kCB) void contract_kernel(ContractArgs A) {
-    __shared__ double Vr[kCRows][kCLd], Vi[kCRows][kCLd];
-    __shared__ double phr[kCS], phim[kCS];
+    // two staged chunks: the next one is in flight while the products run on the other
+    __shared__ double2 bufA[kSlots], bufB[kSlots];
+    __shared__ double2 phA[kCS], phB[kCS];
     // workgroups that share a K slice of one timeslice run on one XCD (consecutive
     // workgroup ids go round-robin over the 8 XCDs)
     const int nb = gridDim.x;
@@ -171,38 +201,44 @@ __global__ __launch_bounds__(kCB) void contract_kernel(ContractArgs A) {
     const int ch0 = (int)((long)A.nchunk * split / A.nsplit), ch1 = (int)((long)A.nchunk * (split + 1) / A.nsplit);
     const double2 *Vt = A.V + (size_t)t * nev * A.vs * 3;
     const int n3 = 3 * A.vs;
-    for (int ch = ch0; ch < ch1; ++ch) {
-        const int s0 = ch * kCS;
-        // V of the chunk for every vector (rows beyond nev and sites beyond the
-        // timeslice are zero)
-        for (int q = tid; q < kCRows * kCK; q += kCB) {
-            const int l = q / kCK, kk = q - l * kCK;
-            double2 v = make_double2(0.0, 0.0);
-            if (l < nev && 3 * s0 + kk < n3) v = Vt[(size_t)l * n3 + 3 * s0 + kk];
-            Vr[l][kk] = v.x;
-            Vi[l][kk] = v.y;
-        }
+    // e^{-2 pi i (nx x / Lx + ny y / Ly + nz z / Lz)} of the chunk's sites, integer parts
+    // reduced first; zero for sites past the timeslice
+    auto phases = [&](double2 *ph, int s0) {
         if (tid < kCS) {
             const int s = s0 + tid;
-            const int x = s % A.lx, y = (s / A.lx) % A.ly, z = s / (A.lx * A.ly);
-            // e^{-2 pi i (nx x / Lx + ny y / Ly + nz z / Lz)}, integer parts reduced first
-            const int qx = ((mx * x) % A.lx + A.lx) % A.lx;
-            const int qy = ((my * y) % A.ly + A.ly) % A.ly;
-            const int qz = ((mz * z) % A.lz + A.lz) % A.lz;
-            const double f = (double)qx / A.lx + (double)qy / A.ly + (double)qz / A.lz;
-            double sn, cs;
-            sincospi(-2.0 * f, &sn, &cs);
-            phr[tid] = cs;
-            phim[tid] = sn;
+            double2 v = make_double2(0.0, 0.0);
+            if (s < A.vs) {
+                const int x = s % A.lx, y = (s / A.lx) % A.ly, z = s / (A.lx * A.ly);
+                const int qx = ((mx * x) % A.lx + A.lx) % A.lx;
+                const int qy = ((my * y) % A.ly + A.ly) % A.ly;
+                const int qz = ((mz * z) % A.lz + A.lz) % A.lz;
+                const double f = (double)qx / A.lx + (double)qy / A.ly + (double)qz / A.lz;
+                sincospi(-2.0 * f, &v.y, &v.x);
+            }
+            ph[tid] = v;
         }
+    };
+    if (ch0 < ch1) {
+        stage_chunk(bufA, Vt, nev, n3, ch0 * kCS, wave, lane);
+        phases(phA, ch0 * kCS);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int ch = ch0; ch < ch1; ch += 2) {
+        if (ch + 1 < ch1) {
+            stage_chunk(bufB, Vt, nev, n3, (ch + 1) * kCS, wave, lane);
+            phases(phB, (ch + 1) * kCS);
+        }
+        chunk_dispatch<MODE, NCB>(nact, bufA, phA, lane, cm, cn, cre, cim);
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        switch (nact) {
-            case 4: chunk_products<MODE, NCB, 4>(Vr, Vi, phr, phim, lane, cm, cn, cre, cim); break;
-            case 3: chunk_products<MODE, NCB, 3>(Vr, Vi, phr, phim, lane, cm, cn, cre, cim); break;
-            case 2: chunk_products<MODE, NCB, 2>(Vr, Vi, phr, phim, lane, cm, cn, cre, cim); break;
-            case 1: chunk_products<MODE, NCB, 1>(Vr, Vi, phr, phim, lane, cm, cn, cre, cim); break;
-            default: break;
+        if (ch + 1 >= ch1) break;
+        if (ch + 2 < ch1) {
+            stage_chunk(bufA, Vt, nev, n3, (ch + 2) * kCS, wave, lane);
+            phases(phA, (ch + 2) * kCS);
         }
+        chunk_dispatch<MODE, NCB>(nact, bufB, phB, lane, cm, cn, cre, cim);
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
     }
     // v_mfma_f64_16x16x4f64 leaves C[row][col] of a 16 x 16 block in lane col + 16 (row % 4),
