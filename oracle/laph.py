@@ -143,6 +143,18 @@ def stochastic_perambulator(U, V, t0, m0, rho, n_dil, csw=1.0, tol=1e-13, method
     return project(V, X, n_dil), X
 
 
+# --- spin basis of the perambulator ---------------------------------------------------
+#
+# The driver side of the paper's workflow introduces a further Dirac spin basis
+# (Sec. "Quda_laph"), without saying which.  A change of basis psi' = S psi (S unitary)
+# turns the propagator's spin matrix M into S M S^dagger, so for the perambulator
+#     tau'[t][l][k][beta'][alpha'] = sum_{beta, alpha} S[beta'][beta] tau[t][l][k][beta][alpha] conj(S[alpha'][alpha])
+
+def spin_rotate(tau, S):
+    """tau' = S tau S^dagger on the last two (sink spin, source spin) indices."""
+    return np.einsum("ab,...bc,dc->...ad", S, tau, np.conj(S))
+
+
 # --- loss and gradients -------------------------------------------------------------
 
 def loss_from_tau(tau, t_sink, nblk=None):

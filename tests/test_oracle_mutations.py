@@ -6,7 +6,7 @@ flipped clover sign, a leaf built from the wrong links, a reversed leaf, a
 Laplacian sign slip, a conjugate on the wrong factor of the projection, a
 missing gamma5 in the adjoint, the doublets' conjugate or phase sign, a triplet
 epsilon sign or a conjugated triplet factor, blocked instead of interlaced noise
-dilution, noise of the wrong spin) and asserts that the named pin now fails.
+dilution, noise of the wrong spin, a spin rotation by S^T instead of S^dagger) and asserts that the named pin now fails.
 Everything runs on the CPU; nothing here touches the GPU library.
 """
 import numpy as np
@@ -136,6 +136,10 @@ def _noise_sources_wrong_spin(V, t0, rho, n_dil):
     return b
 
 
+def _spin_rotate_transpose(tau, S):
+    return np.einsum("ab,...bc,cd->...ad", S, tau, S.T)
+
+
 CASES = [
     ("hop projector sign", dirac, "hop", _hop_flipped, pins.test_free_field_plane_wave),
     ("no antiperiodic phase", dirac, "hop", _hop_periodic, pins.test_free_field_propagator_closed_form),
@@ -157,6 +161,8 @@ CASES = [
      pins.test_stochastic_perambulator_is_noise_weighted_perambulator),
     ("noise of the wrong spin", laph, "noise_sources", _noise_sources_wrong_spin,
      pins.test_stochastic_perambulator_is_noise_weighted_perambulator),
+    ("spin rotation by S^T instead of S^dagger", laph, "spin_rotate", _spin_rotate_transpose,
+     pins.test_spin_rotate_equals_rotating_sources_and_solutions),
 ]
 
 

@@ -580,6 +580,33 @@ def test_stochastic_perambulator_is_noise_weighted_perambulator():
 
 
 # ---------------------------------------------------------------------------
+# spin basis of the perambulator
+# ---------------------------------------------------------------------------
+
+def test_spin_rotate_equals_rotating_sources_and_solutions():
+    """tau in the basis psi' = S psi, two routes: S tau S^dagger, against sources built from
+    the new basis vectors (old components conj(S[alpha'][alpha])), solved, their solutions
+    rotated by S and projected."""
+    dims = (4, 4, 4, 4)
+    nev, t0, m0 = 2, 1, 0.1
+    U = ls.gauge_field(dims, 81)
+    V = ls.orthonormal_laph_vectors(dims, nev, 82)
+    rng = np.random.default_rng(83)
+    S, _ = np.linalg.qr(rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4)))
+    tau, _ = laph.perambulator(U, V, t0, m0, method="dense")
+    D = dirac.WilsonClover(U, m0, 1.0)
+    b = np.zeros((4 * nev, dims[3], dims[2], dims[1], dims[0], 4, 3), dtype=np.complex128)
+    for k in range(nev):
+        for ap in range(4):
+            for al in range(4):
+                b[4 * k + ap, t0, :, :, :, al, :] = np.conj(S[ap, al]) * V[t0, k]
+    X = solvers.dense_solve(D, b)
+    Xs = np.einsum("ab,r...bc->r...ac", S, X)
+    assert _rel(laph.spin_rotate(tau, S), laph.project(V, Xs, nev)) < 1e-12
+    assert _rel(laph.spin_rotate(laph.spin_rotate(tau, S), np.conj(S.T)), tau) < 1e-14
+
+
+# ---------------------------------------------------------------------------
 # P13: FP16-with-norm codec
 # ---------------------------------------------------------------------------
 
