@@ -479,14 +479,18 @@ def main():
     torch.cuda.synchronize()
     copy_gbs = 2 * xa.numel() * 4 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del xa, xb
-    # the stencil at small batches, where it is bound by HBM (algorithmic bytes / time)
+    # the stencil at small batches: HBM-bound at one RHS, at the FP32 ridge by eight
+    # (algorithmic bytes and flops / time; register tiles up to 4 RHS, LDS links at 8)
     dslash = {"copy_gbs": round(copy_gbs, 1)}
-    for prec, nrhs, st, tile in (("f32", 1, 1, 1), ("f16n", 1, 1, 1), ("f32", 8, 2, 8), ("f16n", 8, 2, 8)):
+    for prec, nrhs, st, tile in (("f32", 1, 1, 1), ("f16n", 1, 1, 1), ("f16n", 2, 1, 2), ("f16n", 4, 1, 4),
+                                 ("f32", 8, 2, 8), ("f16n", 8, 2, 8)):
         m1, _ = lat.time_stages(prec, nrhs, tile, 0, reps=10, stencil=st, traversal=1)
         gb = stage_bytes_per_site(prec, nrhs, 1) * vh / (m1 * 1e-3) / 1e9
+        tf = STAGE_FLOPS_PER_SITE_RHS * nrhs * vh / (m1 * 1e-3) / 1e12
         dslash["%s_nrhs%d" % (prec, nrhs)] = {"ms": round(m1, 4), "gbs": round(gb, 1),
                                               "hbm_frac": round(gb / HBM_PEAK_GBS, 4),
-                                              "of_copy": round(gb / copy_gbs, 4)}
+                                              "of_copy": round(gb / copy_gbs, 4), "tflops": round(tf, 2),
+                                              "alu_frac": round(tf / ALU_PEAK_TFLOPS, 4)}
 
     out = {
         "metric": "perambulator RHS solved/s at rel. residual 1e-10; Dslash HBM GB/s vs peak",

@@ -199,6 +199,16 @@ laph_status laph_stochastic_perambulator(laph_ctx ctx, double *phi, const double
 laph_status laph_make_noise_sources(laph_ctx ctx, double *B, const double *V, int nev, int t0,
                                     const double *rho, int n_dil);
 
+/* Spin basis of tau (the paper's driver adds a Dirac spin basis of its own, Sec.
+ * "Quda_laph", without defining it): for a change of basis psi' = S psi with S a
+ * unitary 4 x 4 matrix (S_host: c128 [4][4] row-major, host), every trailing 4 x 4
+ * block of tau (sink spin beta, source spin alpha) becomes S tau S^dagger:
+ *   out[b][beta'][alpha'] = sum S[beta'][beta] tau[b][beta][alpha] conj(S[alpha'][alpha])
+ * tau, out: c128 [n_blocks][4][4] on the device (out may be tau).  For a
+ * perambulator n_blocks = Lt * nev * nev (or Lt * nev * n_dil for phi).
+ * Asynchronous on the context stream. */
+laph_status laph_spin_rotate(laph_ctx ctx, double *out, const double *tau, long n_blocks, const double *S_host);
+
 /* Building blocks of the perambulator, exposed for the differentiable wrapper:
  *  laph_make_sources: B (canonical, 4*nev RHS) = spin-diluted sources at t0;
  *  laph_project:      tau (as above) from solutions X (canonical, 4*nev_src RHS);

@@ -9,4 +9,4 @@ All arithmetic runs in the HIP library; importing this package does not load
 it (``Lattice`` does, and raises if it has not been built).
 """
 from ._lib import EXPORTED, LaphError, LaphNoConvergence, LIB_PATH, load  # noqa: F401
-from .api import Lattice, default_params, perambulator, project, solve  # noqa: F401
+from .api import DIRAC_PAULI, Lattice, default_params, perambulator, project, solve  # noqa: F401

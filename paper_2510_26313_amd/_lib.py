@@ -71,6 +71,7 @@ _SIGS = [
     ("laph_project_workspace_bytes", c_size_t, [c_void_p, c_int, c_int]),
     ("laph_project", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p, c_size_t]),
     ("laph_project_adjoint", c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int]),
+    ("laph_spin_rotate", c_int, [c_void_p, c_void_p, c_void_p, ctypes.c_long, c_void_p]),
     ("laph_last_timings", c_int, [c_void_p, P(c_double)]),
     ("laph_time_stages_workspace_bytes", c_size_t, [c_void_p, c_int, c_int, c_int]),
     ("laph_time_stages", c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_void_p, c_size_t,

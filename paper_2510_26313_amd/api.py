@@ -17,6 +17,15 @@ from . import _lib as L
 # here: the adjoint solve is the library's dagger solve (D^dagger = gamma5 D gamma5)
 
 
+# A Dirac-Pauli type basis, reached from the library's DeGrand-Rossi (chiral) basis by
+# psi' = DIRAC_PAULI psi: gamma_t becomes diag(1, 1, -1, -1) (upper components: positive
+# energy at rest) and gamma_5 becomes the off-diagonal block swap.  For laph.spin_rotate.
+DIRAC_PAULI = np.array([[1, 0, 1, 0],
+                        [0, 1, 0, 1],
+                        [1, 0, -1, 0],
+                        [0, 1, 0, -1]], dtype=np.complex128) / np.sqrt(2.0)
+
+
 def default_params(**kw):
     lib = L.load()
     p = L.SolveParams()
@@ -314,6 +323,24 @@ class Lattice:
         L.check(self._run(self.lib.laph_make_noise_sources, self.ctx, _ptr(B), _ptr(V), nev, int(t0), _ptr(rho),
                           int(n_dil)))
         return B
+
+    def spin_rotate(self, tau, S, out=None):
+        """tau' = S tau S^dagger on the trailing (sink spin, source spin) 4 x 4 blocks of a
+        perambulator-shaped tensor, for a change of Dirac basis psi' = S psi (S: 4 x 4
+        unitary, numpy).  out=tau rotates in place."""
+        if not isinstance(tau, torch.Tensor) or tau.dtype != torch.complex128 or not tau.is_cuda:
+            raise TypeError("tau must be a complex128 CUDA tensor")
+        if tuple(tau.shape[-2:]) != (4, 4) or not tau.is_contiguous():
+            raise ValueError("tau must be contiguous with trailing 4 x 4 spin blocks")
+        S = np.ascontiguousarray(np.asarray(S, dtype=np.complex128))
+        if S.shape != (4, 4):
+            raise ValueError("S must be 4 x 4")
+        out = torch.empty_like(tau) if out is None else out
+        if out.shape != tau.shape or out.dtype != tau.dtype or not out.is_contiguous():
+            raise ValueError("out must match tau")
+        L.check(self._run(self.lib.laph_spin_rotate, self.ctx, _ptr(out), _ptr(tau), tau.numel() // 16,
+                          S.ctypes.data_as(ctypes.c_void_p)))
+        return out
 
     def make_sources(self, V, t0):
         nev = V.shape[1]

@@ -583,6 +583,12 @@ laph_status laph_project(laph_ctx h, double *tau, const double *X, const double 
     return LAPH_OK;
 }
 
+laph_status laph_spin_rotate(laph_ctx h, double *out, const double *tau, long n_blocks, const double *S_host) {
+    if (!h) return set_error(LAPH_ERR_INVALID, "null context");
+    if (!out || !tau || !S_host || n_blocks < 0) return set_error(LAPH_ERR_INVALID, "bad arguments");
+    return spin_rotate(C(h), out, tau, n_blocks, S_host);
+}
+
 laph_status laph_project_adjoint(laph_ctx h, double *GX, const double *Gtau, const double *V, int nev, int nev_src) {
     LAPH_TRY(check_ctx(h));
     if (!GX || !Gtau || !V || nev <= 0 || nev_src <= 0 || nev_src > 16383) return set_error(LAPH_ERR_INVALID, "bad arguments");

@@ -44,6 +44,8 @@ laph_status pack_laph_vectors(const Ctx &c, double *Vp, const double *V, int nev
 size_t project_scratch_bytes(const Ctx &c, int nev, int n);
 laph_status project(const Ctx &c, const ProjectSpec &s);
 laph_status project_adjoint(const Ctx &c, double *GX, const double *Gtau, const double *V, int nev, int nev_src);
+// tau' = S tau S^dagger on nblk consecutive 4 x 4 complex blocks (S: host, row-major)
+laph_status spin_rotate(const Ctx &c, double *out, const double *tau, long nblk, const double *S_host);
 laph_status make_sources_canonical(const Ctx &c, double *B, const double *V, int nev, int t0,
                                    const double *rho = nullptr, int n_dil = 0);
 

@@ -291,6 +291,51 @@ laph_status project(const Ctx &c, const ProjectSpec &s) {
 }
 
 // ---------------------------------------------------------------------------
+// spin basis: tau' = S tau S^dagger on every 4 x 4 (sink spin, source spin) block
+// (a change of Dirac basis psi' = S psi; the paper's driver adds such a basis)
+// ---------------------------------------------------------------------------
+struct SpinMat {
+    double2 s[16];   // S[row][col], row-major
+};
+
+__global__ void spin_rotate_kernel(double2 *out, const double2 *tau, long nblk, SpinMat S) {
+    const long b = (long)blockIdx.x * 256 + threadIdx.x;
+    if (b >= nblk) return;
+    cplx<double> m[16], sm[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) m[i] = {tau[b * 16 + i].x, tau[b * 16 + i].y};
+    // sm = S m
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            cplx<double> acc = {0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) cmac(acc, cplx<double>{S.s[4 * r + k].x, S.s[4 * r + k].y}, m[4 * k + c]);
+            sm[4 * r + c] = acc;
+        }
+    // out = sm S^dagger: out[r][c] = sum_k sm[r][k] conj(S[c][k])
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            cplx<double> acc = {0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) cmac_conj(acc, cplx<double>{S.s[4 * c + k].x, S.s[4 * c + k].y}, sm[4 * r + k]);
+            out[b * 16 + 4 * r + c] = make_double2(acc.re, acc.im);
+        }
+}
+
+laph_status spin_rotate(const Ctx &c, double *out, const double *tau, long nblk, const double *S_host) {
+    if (nblk <= 0) return LAPH_OK;
+    SpinMat S;
+    for (int i = 0; i < 16; ++i) S.s[i] = make_double2(S_host[2 * i], S_host[2 * i + 1]);
+    hipLaunchKernelGGL(spin_rotate_kernel, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, c.stream,
+                       reinterpret_cast<double2 *>(out), reinterpret_cast<const double2 *>(tau), nblk, S);
+    return check_launch("spin_rotate_kernel");
+}
+
+// ---------------------------------------------------------------------------
 // adjoint of the projection: GX^(4k+alpha)(x, t)_(beta, a) = sum_l V_l(x, t)_a Gtau[t][l][k][beta][alpha]
 // ---------------------------------------------------------------------------
 __global__ void project_adjoint_kernel(Geom g, double2 *GX, const double2 *Gtau, const double2 *V, int nev,

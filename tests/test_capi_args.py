@@ -45,6 +45,7 @@ def test_null_context_is_rejected(lib):
         lambda: lib.laph_perambulator(None, buf, buf, 4, 0, 0, 1e-10, ctypes.byref(p), None, buf, 1 << 20),
         lambda: lib.laph_laplacian_eigvecs(None, buf, buf, 4, 1e-10, 10, 0, buf, 1 << 20, None, None),
         lambda: lib.laph_make_sources(None, buf, buf, 4, 0),
+        lambda: lib.laph_spin_rotate(None, buf, buf, 1, buf),
     ]
     for call in calls:
         assert call() == L.LAPH_ERR_INVALID
