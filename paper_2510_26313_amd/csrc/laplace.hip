@@ -66,6 +66,13 @@ __device__ __forceinline__ void site3(const Geom &g, int s, int &x, int &y, int 
 // neighbour indices, then each wave runs two vectors at a time (lanes 0-31 and
 // 32-63), so every link is read from HBM once for all vectors of the block.
 constexpr int kLapSites = 32;
+// vectors per group (grid dimension, outermost): 32 measured best at 32^3 x 64 with 96
+// vectors (4.03 s for the eigensolver, against 4.24 s with one group of all vectors,
+// 4.19 s with 16 and 4.46 s with 8: groups re-stage the links, all-vector blocks lose
+// the L2 reuse of their neighbour rows)
+#ifndef LAPH_LAP_VG
+#define LAPH_LAP_VG 32
+#endif
 
 // element (site, colour) of a vector: colour planes (Planar) or the canonical
 // site-major order
@@ -83,8 +90,13 @@ __global__ __launch_bounds__(kLB) void lap_kernel(LapArgs A) {
     const int nblk = gridDim.x;
     int bid = blockIdx.x;
     if (nblk % 8 == 0) bid = (bid % 8) * (nblk / 8) + bid / 8;
+    // vector groups outermost: the blocks in flight work on the same few vectors, so
+    // the y and z neighbour rows a block reads were loaded by its neighbours moments ago
+    const int grp = bid / (nrow * g.lt);
+    bid -= grp * nrow * g.lt;
     const int t = bid / nrow;
     const int s0 = (bid - t * nrow) * kLapSites;
+    const int j_lo = grp * LAPH_LAP_VG, j_hi = min(A.nvec, j_lo + LAPH_LAP_VG);
     // ---- phase 1: links and neighbours (thread -> (hop, site))
     for (int q = threadIdx.x; q < 6 * kLapSites; q += kLB) {
         const int hop = q / kLapSites, site = q - hop * kLapSites;
@@ -135,7 +147,7 @@ __global__ __launch_bounds__(kLB) void lap_kernel(LapArgs A) {
 #pragma unroll
     for (int hop = 0; hop < 6; ++hop) nb[hop] = nbr[hop][site] * ss;
 #pragma unroll 1
-    for (int j = 2 * wave + vsub; j < A.nvec; j += 2 * (kLB / 64)) {
+    for (int j = j_lo + 2 * wave + vsub; j < j_hi; j += 2 * (kLB / 64)) {
         const size_t vb = (tb + j) * vs * 3;
         const double2 *__restrict__ vin = A.in + vb;
         // every load of this vector first (six neighbours, the site itself, z), so a
@@ -617,7 +629,7 @@ struct EigRun {
         a.m = m;
         a.nvec = m;
         a.coef = coef;
-        dim3 grid(((vs + kLapSites - 1) / kLapSites) * lt);
+        dim3 grid(((vs + kLapSites - 1) / kLapSites) * lt * ((m + LAPH_LAP_VG - 1) / LAPH_LAP_VG));
         if (a.z) hipLaunchKernelGGL((lap_kernel<true, true>), grid, dim3(kLB), 0, c.stream, a);
         else hipLaunchKernelGGL((lap_kernel<false, true>), grid, dim3(kLB), 0, c.stream, a);
         return check_launch("lap_kernel");
@@ -681,7 +693,7 @@ laph_status apply_neg_laplacian(const Ctx &c, double *out, const double *in, int
     a.nvec = nvec;
     a.coef = nullptr;
     const int vs = c.g.lx * c.g.ly * c.g.lz;
-    dim3 grid(((vs + kLapSites - 1) / kLapSites) * c.g.lt);
+    dim3 grid(((vs + kLapSites - 1) / kLapSites) * c.g.lt * ((nvec + LAPH_LAP_VG - 1) / LAPH_LAP_VG));
     hipLaunchKernelGGL((lap_kernel<false, false>), grid, dim3(kLB), 0, c.stream, a);
     return check_launch("lap_kernel");
 }
