@@ -64,19 +64,30 @@ __device__ __forceinline__ void pair_of(int q, int nev, int &m, int &n) {
 // One staged chunk: the wave's A fragments (R row blocks) and B fragments (NCB column
 // blocks) per group of 4 K, then the R x NCB x 4 real products as straight-line code,
 // each product's accumulator written by the previous group's product of the same kind
-// only (independent accumulators back to back).
+// only (independent accumulators back to back).  A row of the chunk holds K colour-major
+// (colour a of site s at a kCS + s), so with the 6 groups unrolled each group's colour
+// and its cross-product partners are compile-time offsets from one per-lane address.
 template <int MODE, int NCB, int R>
 __device__ __forceinline__ void chunk_products(const double2 *buf, const double2 *ph, int lane, const int *cm,
                                                const int *cn, d4 (*cre)[NCB], d4 (*cim)[NCB]) {
-#pragma unroll 2
+    const int q = lane >> 4;   // K within a group of 4
+    const double2 *arow = buf + (lane & 15) * kRS + q;
+    const double2 *bm[NCB], *bn[NCB];
+#pragma unroll
+    for (int j = 0; j < NCB; ++j) {
+        bm[j] = buf + cm[j] * kRS + q;
+        bn[j] = buf + cn[j] * kRS + q;
+    }
+    // the phases of the two sites this lane meets (groups start at site 0 or 4)
+    const double2 f0 = ph[q], f1 = ph[q + 4];
+#pragma unroll
     for (int k4 = 0; k4 < kCK; k4 += 4) {
-        const int kk = k4 + (lane >> 4);
-        const int sl = kk / 3, a = kk - 3 * sl;
-        const double2 f = ph[sl];
+        const int a = k4 / kCS, so = k4 % kCS;   // colour and site offset of the group
+        const double2 f = so ? f1 : f0;
         double ar[R], ai[R], nai[R], br[NCB], bi[NCB];
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-            const double2 v = buf[(16 * i + (lane & 15)) * kRS + kk];
+            const double2 v = arow[16 * i * kRS + k4];
             const double vi = MODE == 0 ? -v.y : v.y;
             ar[i] = f.x * v.x - f.y * vi;
             ai[i] = f.x * vi + f.y * v.x;
@@ -85,14 +96,14 @@ __device__ __forceinline__ void chunk_products(const double2 *buf, const double2
 #pragma unroll
         for (int j = 0; j < NCB; ++j) {
             if (MODE == 0) {
-                const double2 v = buf[cm[j] * kRS + kk];
+                const double2 v = bm[j][k4];
                 br[j] = v.x;
                 bi[j] = v.y;
             } else {
                 // (V_m x V_n)_a = V_m,b V_n,c - V_m,c V_n,b with (a, b, c) cyclic
-                const int kb = 3 * sl + (a == 2 ? 0 : a + 1), kc = 3 * sl + (a == 0 ? 2 : a - 1);
-                const double2 ub = buf[cm[j] * kRS + kb], uc = buf[cm[j] * kRS + kc];
-                const double2 wb = buf[cn[j] * kRS + kb], wc = buf[cn[j] * kRS + kc];
+                const int ob = (a == 2 ? 0 : a + 1) * kCS + so, oc = (a == 0 ? 2 : a - 1) * kCS + so;
+                const double2 ub = bm[j][ob], uc = bm[j][oc];
+                const double2 wb = bn[j][ob], wc = bn[j][oc];
                 br[j] = (ub.x * wc.x - ub.y * wc.y) - (uc.x * wb.x - uc.y * wb.y);
                 bi[j] = (ub.x * wc.y + ub.y * wc.x) - (uc.x * wb.y + uc.y * wb.x);
             }
@@ -112,6 +123,8 @@ __device__ __forceinline__ void chunk_products(const double2 *buf, const double2
                 cre[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[i], bi[j], cre[i][j], 0, 0, 0);
                 cim[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], cim[i][j], 0, 0, 0);
             }
+        // keep each group's LDS reads with its products (hoisting them all costs occupancy)
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -129,7 +142,8 @@ __device__ __forceinline__ void chunk_dispatch(int nact, const double2 *buf, con
 
 // Copy chunk s0 of every vector (64 rows, nev real) into LDS with the direct
 // global-to-LDS loads: lane i of load q fills slot 64 q + i of the buffer, so each
-// lane fetches the element that lands in its slot.  Pad slots and rows or sites
+// lane fetches the element that lands in its slot (which also reorders a row's K to
+// colour-major).  Pad slots and rows or sites
 // outside the data load the timeslice's first element (finite; the zero phase of a
 // site outside the lattice cancels it, and pad slots and rows past nev are not read
 // into any kept product).
@@ -138,8 +152,9 @@ __device__ __forceinline__ void stage_chunk(double2 *buf, const double2 *Vt, int
     for (int q = wave; q < kSlots / 64; q += 4) {
         const int e = 64 * q + lane;
         const int row = e / kRS, col = e - row * kRS;
+        const int a = col / kCS, sl = col - a * kCS;   // colour-major within the row
         const double2 *src = Vt;
-        if (col < kCK && row < nev && 3 * s0 + col < n3) src = Vt + (size_t)row * n3 + 3 * s0 + col;
+        if (col < kCK && row < nev && 3 * (s0 + sl) < n3) src = Vt + (size_t)row * n3 + 3 * (s0 + sl) + a;
         __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(buf + 64 * q), 16, 0, 0);
     }
 }
