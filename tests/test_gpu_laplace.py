@@ -2,7 +2,8 @@
 
 * (-Delta) X against the oracle's stencil on a ragged lattice (1e-13);
 * the nev lowest eigenpairs against the oracle's dense eigendecomposition per
-  timeslice (C0 4^4 with nev 8, and 8^3 x 4 with nev 16): eigenvalues within 1e-10,
+  timeslice (C0 4^4 with nev 8, 8^3 x 4 with nev 16, a non-cubic 6x4x4x6 with an odd
+  nev 5 and 4^4 with a single vector): eigenvalues within 1e-10,
   eigenvectors (both sides in the same phase convention) within 1e-8;
 * 16^3 x 4, nev 32: eigenvalues of timeslice 0 against ARPACK (scipy eigsh on the
   oracle's stencil), residuals of every pair with the oracle's stencil;
@@ -53,7 +54,8 @@ def test_apply_laplacian_vs_oracle():
         assert np.abs(got[t] - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("dims,nev,seed", [((4, 4, 4, 4), 8, 1000), ((8, 8, 8, 4), 16, 1001)])
+@pytest.mark.parametrize("dims,nev,seed", [((4, 4, 4, 4), 8, 1000), ((8, 8, 8, 4), 16, 1001),
+                                            ((6, 4, 4, 6), 5, 1002), ((4, 4, 4, 4), 1, 1003)])
 def test_eigvecs_vs_dense_oracle(dims, nev, seed):
     U, lat = _lattice(dims, seed)
     Vref, lamref, gap = olaph.laplacian_eigvecs(U, nev)
