@@ -15,9 +15,10 @@
 // first pass shifted by 1e-15 of the largest Gram eigenvalue), and rotated to Ritz
 // vectors by a Rayleigh-Ritz step; it stops when every one of the nev lowest Ritz
 // pairs has ||(-Delta) y - lambda y|| <= tol.  Every vector operation runs here:
-// the stencil (links staged in LDS once per block of sites for all vectors, FP64), the Gram matrices (FP64 matrix
-// cores), the small Hermitian eigenproblems (cyclic Jacobi in one workgroup per
-// timeslice, matrix in LDS), the block rotations and the residual norms.
+// the stencil (links staged in LDS once per block of sites for a group of vectors,
+// FP64), the Gram matrices and the block rotations (FP64 matrix cores), the small
+// Hermitian eigenproblems (cyclic Jacobi in one workgroup per timeslice, matrix in
+// LDS) and the residual norms.
 //
 // Layout of a block: [t][j][a][z][y][x] complex double (colour planes, so the
 // stencil's loads are contiguous across the lanes of a wave), vectors of one
@@ -35,9 +36,8 @@ namespace laph {
 namespace {
 
 constexpr int kLB = 256;          // threads per block of the vector kernels
-constexpr int kRotNJ = 32;        // output vectors per thread in the rotation
 constexpr int kEigMaxM = 96;      // largest block (Jacobi matrix in LDS)
-constexpr int kJB = 256;          // threads of the Jacobi workgroup
+constexpr int kJB = 1024;         // threads of the Jacobi workgroup
 constexpr int kGT = 64;           // Gram tile (rows and columns)
 constexpr int kGKC = 16;          // Gram K chunk
 constexpr int kLmax = 12;         // upper bound of the spectrum
@@ -451,34 +451,85 @@ struct RotArgs {
     int m, ne, nout, mout;  // out block has mout vectors per timeslice
 };
 
-__global__ __launch_bounds__(kLB) void rotate_kernel(RotArgs A) {
-    __shared__ double zr[kEigMaxM][kRotNJ], zi[kEigMaxM][kRotNJ];
-    const int e = blockIdx.x * kLB + threadIdx.x;
-    const int j0 = blockIdx.y * kRotNJ;
-    const int t = blockIdx.z;
-    for (int q = threadIdx.x; q < A.m * kRotNJ; q += kLB) {
-        const int k = q / kRotNJ, jj = q - k * kRotNJ;
-        double2 v = make_double2(0, 0);
-        if (j0 + jj < A.nout) v = A.Z[((size_t)t * A.m + k) * A.m + j0 + jj];
-        zr[k][jj] = v.x;
-        zi[k][jj] = v.y;
+// Computed on the FP64 matrix cores as
+// out^T[j][e] = sum_k Z^T[j][k] in[k][e] per timeslice: A = Z^T (rows j, staged in LDS
+// 16 k at a time and shared by the four waves), B = the input block (16 consecutive e
+// per k row: 256-byte loads), complex as four real products per 16 x 16 block.  A wave
+// owns 32 e (two column blocks) and every j (up to six row blocks), so a lane's results
+// for one j are 16 consecutive e: the stores are 256-byte segments too.
+constexpr int kRE = 32;                 // e per wave
+constexpr int kRK = 16;                 // k per staged chunk
+constexpr int kRJB = kEigMaxM / 16;     // row blocks (j)
+
+__global__ __launch_bounds__(256) void rotate_mfma_kernel(RotArgs A) {
+    __shared__ double zr[kRK][kEigMaxM + 1], zi[kRK][kEigMaxM + 1];
+    const int t = blockIdx.y;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int e0 = (blockIdx.x * 4 + wave) * kRE;
+    const int njb = (A.nout + 15) / 16;
+    d4 cr[kRJB][2], ci[kRJB][2];
+#pragma unroll
+    for (int jb = 0; jb < kRJB; ++jb)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            cr[jb][c] = d4{0, 0, 0, 0};
+            ci[jb][c] = d4{0, 0, 0, 0};
+        }
+    const double2 *in = A.in + (size_t)t * A.m * A.ne;
+    const double2 *Zt = A.Z + (size_t)t * A.m * A.m;
+    for (int k0 = 0; k0 < A.m; k0 += kRK) {
+        // Z rows k0 .. k0 + 15, the first nout columns (zero elsewhere)
+        for (int q = threadIdx.x; q < kRK * kEigMaxM; q += 256) {
+            const int kk = q / kEigMaxM, j = q - kk * kEigMaxM;
+            double2 v = make_double2(0.0, 0.0);
+            if (k0 + kk < A.m && j < A.nout) v = Zt[(size_t)(k0 + kk) * A.m + j];
+            zr[kk][j] = v.x;
+            zi[kk][j] = v.y;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k4 = 0; k4 < kRK; k4 += 4) {
+            const int kk = k4 + (lane >> 4), k = k0 + kk;
+            double br[2], bi[2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int e = e0 + 16 * c + (lane & 15);
+                double2 v = make_double2(0.0, 0.0);
+                if (k < A.m && e < A.ne) v = in[(size_t)k * A.ne + e];
+                br[c] = v.x;
+                bi[c] = v.y;
+            }
+#pragma unroll
+            for (int jb = 0; jb < kRJB; ++jb) {
+                if (jb >= njb) break;   // wave-uniform
+                const int j = 16 * jb + (lane & 15);
+                const double ar = zr[kk][j], ai = zi[kk][j], nai = -ai;
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    cr[jb][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br[c], cr[jb][c], 0, 0, 0);
+                    cr[jb][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, bi[c], cr[jb][c], 0, 0, 0);
+                    ci[jb][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi[c], ci[jb][c], 0, 0, 0);
+                    ci[jb][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br[c], ci[jb][c], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    if (e >= A.ne) return;
-    double ar[kRotNJ], ai[kRotNJ];
+    // lane holds rows (lane >> 4) + 4 i of column lane & 15 of each 16 x 16 block
 #pragma unroll
-    for (int jj = 0; jj < kRotNJ; ++jj) ar[jj] = ai[jj] = 0.0;
-    for (int k = 0; k < A.m; ++k) {
-        const double2 x = A.in[((size_t)t * A.m + k) * A.ne + e];
+    for (int jb = 0; jb < kRJB; ++jb) {
+        if (jb >= njb) break;
 #pragma unroll
-        for (int jj = 0; jj < kRotNJ; ++jj) {
-            ar[jj] += x.x * zr[k][jj] - x.y * zi[k][jj];
-            ai[jj] += x.x * zi[k][jj] + x.y * zr[k][jj];
+        for (int c = 0; c < 2; ++c) {
+            const int e = e0 + 16 * c + (lane & 15);
+            if (e >= A.ne) continue;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int j = 16 * jb + (lane >> 4) + 4 * i;
+                if (j < A.nout) A.out[((size_t)t * A.mout + j) * A.ne + e] = make_double2(cr[jb][c][i], ci[jb][c][i]);
+            }
         }
     }
-#pragma unroll
-    for (int jj = 0; jj < kRotNJ; ++jj)
-        if (j0 + jj < A.nout) A.out[((size_t)t * A.mout + j0 + jj) * A.ne + e] = make_double2(ar[jj], ai[jj]);
 }
 
 // ---- residual norms: r2[t][j] = || W[t][j] - w[t][j] Y[t][j] ||^2 -----------------------
@@ -672,9 +723,9 @@ struct EigRun {
         a.ne = ne;
         a.nout = m;
         a.mout = m;
-        dim3 grid((ne + kLB - 1) / kLB, (m + kRotNJ - 1) / kRotNJ, lt);
-        hipLaunchKernelGGL(rotate_kernel, grid, dim3(kLB), 0, c.stream, a);
-        return check_launch("rotate_kernel");
+        dim3 grid((ne + 4 * kRE - 1) / (4 * kRE), lt);
+        hipLaunchKernelGGL(rotate_mfma_kernel, grid, dim3(256), 0, c.stream, a);
+        return check_launch("rotate_mfma_kernel");
     }
 };
 
