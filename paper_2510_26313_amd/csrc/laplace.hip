@@ -38,7 +38,6 @@ namespace {
 constexpr int kLB = 256;          // threads per block of the vector kernels
 constexpr int kEigMaxM = 96;      // largest block (Jacobi matrix in LDS)
 constexpr int kJB = 1024;         // threads of the Jacobi workgroup
-constexpr int kGT = 64;           // Gram tile (rows and columns)
 constexpr int kGKC = 16;          // Gram K chunk
 constexpr int kLmax = 12;         // upper bound of the spectrum
 constexpr int kDefaultDegree = 48; // Chebyshev degree per iteration when the caller passes <= 1
@@ -203,70 +202,87 @@ struct GramArgs {
     double2 *scratch;       // [split][lt][m][m]
 };
 
+// One workgroup per (timeslice, K slice) computes the whole m x m block (m <= 96: 6 x 6
+// blocks of 16), each wave a 3 x 3 quadrant of blocks, so no tile padding is computed
+// at m = 96 (tiles of 64 did 1.78x the work).
 __global__ __launch_bounds__(256) void gram_kernel(GramArgs A) {
-    __shared__ double Pr[kGT][kGKC + 1], Pi[kGT][kGKC + 1], Rr[kGT][kGKC + 1], Ri[kGT][kGKC + 1];
-    int bid = blockIdx.x;
-    const int split = bid % A.nsplit;
-    bid /= A.nsplit;
-    const int tj = bid % A.ntile;
-    bid /= A.ntile;
-    const int ti = bid % A.ntile;
-    const int t = bid / A.ntile;
+    __shared__ double Pr[kEigMaxM][kGKC + 1], Pi[kEigMaxM][kGKC + 1], Rr[kEigMaxM][kGKC + 1], Ri[kEigMaxM][kGKC + 1];
+    const int split = blockIdx.x % A.nsplit;
+    const int t = blockIdx.x / A.nsplit;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    d4 cre[4], cim[4];
+    const int rb0 = 3 * (wave >> 1), cb0 = 3 * (wave & 1);   // the wave's quadrant
+    d4 cre[3][3], cim[3][3];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        cre[j] = d4{0, 0, 0, 0};
-        cim[j] = d4{0, 0, 0, 0};
-    }
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            cre[a][b] = d4{0, 0, 0, 0};
+            cim[a][b] = d4{0, 0, 0, 0};
+        }
     const int c0 = (int)((long)A.nchunk * split / A.nsplit), c1 = (int)((long)A.nchunk * (split + 1) / A.nsplit);
-    const int krow = tid & 15, rsub = tid >> 4;
+    const double2 *P = A.P + (size_t)t * A.m * A.ne, *R = A.R + (size_t)t * A.m * A.ne;
     for (int ch = c0; ch < c1; ++ch) {
-        const int e = ch * kGKC + krow;
-        const bool kin = e < A.ne;
-#pragma unroll
-        for (int q = 0; q < kGT / 16; ++q) {
-            const int r = rsub + 16 * q;
-            const int i = ti * kGT + r, jj = tj * kGT + r;
+        // rows of P and R (zero past m), K = this chunk's 16 elements (zero past ne)
+        for (int q = tid; q < kEigMaxM * kGKC; q += 256) {
+            const int r = q / kGKC, kk = q - r * kGKC;
+            const int e = ch * kGKC + kk;
             double2 pv = make_double2(0, 0), rv = make_double2(0, 0);
-            if (kin && i < A.m) pv = A.P[((size_t)t * A.m + i) * A.ne + e];
-            if (kin && jj < A.m) rv = A.R[((size_t)t * A.m + jj) * A.ne + e];
-            Pr[r][krow] = pv.x;
-            Pi[r][krow] = pv.y;
-            Rr[r][krow] = rv.x;
-            Ri[r][krow] = rv.y;
+            if (e < A.ne && r < A.m) {
+                pv = P[(size_t)r * A.ne + e];
+                rv = R[(size_t)r * A.ne + e];
+            }
+            Pr[r][kk] = pv.x;
+            Pi[r][kk] = pv.y;
+            Rr[r][kk] = rv.x;
+            Ri[r][kk] = rv.y;
         }
         __syncthreads();
 #pragma unroll
         for (int k4 = 0; k4 < kGKC; k4 += 4) {
-            const int arow = wave * 16 + (lane & 15);
             const int kk = k4 + (lane >> 4);
-            const double ar = Pr[arow][kk], ai = Pi[arow][kk], nai = -ai;
+            double ar[3], ai[3], nai[3], br[3], bi[3];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int bcol = q * 16 + (lane & 15);
-                const double br = Rr[bcol][kk], bi = Ri[bcol][kk];
-                // conj(P) R = (Pr Rr + Pi Ri) + i (Pr Ri - Pi Rr)
-                cre[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, cre[q], 0, 0, 0);
-                cre[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, cre[q], 0, 0, 0);
-                cim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, cim[q], 0, 0, 0);
-                cim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, br, cim[q], 0, 0, 0);
+            for (int a = 0; a < 3; ++a) {
+                const int row = 16 * (rb0 + a) + (lane & 15);
+                ar[a] = Pr[row][kk];
+                ai[a] = Pi[row][kk];
+                nai[a] = -ai[a];
+                const int col = 16 * (cb0 + a) + (lane & 15);
+                br[a] = Rr[col][kk];
+                bi[a] = Ri[col][kk];
             }
+            // conj(P) R = (Pr Rr + Pi Ri) + i (Pr Ri - Pi Rr)
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], cre[a][b], 0, 0, 0);
+                    cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], bi[b], cim[a][b], 0, 0, 0);
+                }
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], bi[b], cre[a][b], 0, 0, 0);
+                    cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[a], br[b], cim[a][b], 0, 0, 0);
+                }
         }
         __syncthreads();
     }
     // the 16x16x4 FP64 MFMA leaves C[row][col] in lane col + 16 (row % 4), register row / 4
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int j = tj * kGT + q * 16 + (lane & 15);
-        if (j >= A.m) continue;
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = ti * kGT + wave * 16 + (lane >> 4) + 4 * r;
-            if (i >= A.m) continue;
-            A.scratch[(((size_t)split * A.lt + t) * A.m + i) * A.m + j] = make_double2(cre[q][r], cim[q][r]);
+        for (int b = 0; b < 3; ++b) {
+            const int j = 16 * (cb0 + b) + (lane & 15);
+            if (j >= A.m) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = 16 * (rb0 + a) + (lane >> 4) + 4 * r;
+                if (i >= A.m) continue;
+                A.scratch[(((size_t)split * A.lt + t) * A.m + i) * A.m + j] = make_double2(cre[a][b][r], cim[a][b][r]);
+            }
         }
-    }
 }
 
 __global__ void gram_reduce_kernel(GramArgs A, double2 *C) {
@@ -632,9 +648,10 @@ int eig_block(int nev) {
 }
 
 void gram_shape(int m, int ne, int lt, int &ntile, int &nsplit, int &nchunk) {
-    ntile = (m + kGT - 1) / kGT;
+    (void)m;
+    ntile = 1;   // one workgroup covers the whole block
     nchunk = (ne + kGKC - 1) / kGKC;
-    const int base = lt * ntile * ntile;
+    const int base = lt;
     nsplit = (2048 + base - 1) / base;
     if (nsplit > nchunk) nsplit = nchunk;
     if (nsplit > 64) nsplit = 64;
@@ -694,7 +711,7 @@ struct EigRun {
         a.lt = lt;
         gram_shape(m, ne, lt, a.ntile, a.nsplit, a.nchunk);
         a.scratch = ws.gscratch;
-        hipLaunchKernelGGL(gram_kernel, dim3(lt * a.ntile * a.ntile * a.nsplit), dim3(256), 0, c.stream, a);
+        hipLaunchKernelGGL(gram_kernel, dim3(lt * a.nsplit), dim3(256), 0, c.stream, a);
         LAPH_TRY(check_launch("gram_kernel"));
         const long total = (long)lt * m * m;
         hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c.stream, a,
