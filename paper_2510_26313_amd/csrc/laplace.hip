@@ -10,15 +10,16 @@
 // iteration and timeslice, a block of m = nev + guard vectors is filtered by the
 // degree-d Chebyshev polynomial that damps [lambda_cut, 12] (lambda_cut = the
 // largest Ritz value of the block; d as large as allowed while the growth of the
-// lowest Ritz direction over the cut stays below ~1e6), made orthonormal by two Loewdin passes
-// (Hermitian eigendecomposition of the Gram matrix, Y <- Y Q Lambda^{-1/2}; the
-// first pass shifted by 1e-15 of the largest Gram eigenvalue), and rotated to Ritz
-// vectors by a Rayleigh-Ritz step; it stops when every one of the nev lowest Ritz
+// lowest Ritz direction over the cut stays below ~1e6), made orthonormal by two
+// Cholesky passes (Gram matrix C = R^dagger R, Y <- Y R^{-1}; the first pass shifted by
+// 1e-15 of the largest Gram diagonal entry; a timeslice whose factorisation breaks
+// down takes Y <- Y Q Lambda^{-1/2} from the Gram matrix's eigendecomposition
+// instead), and rotated to Ritz vectors by a Rayleigh-Ritz step; it stops when every one of the nev lowest Ritz
 // pairs has ||(-Delta) y - lambda y|| <= tol.  Every vector operation runs here:
 // the stencil (links staged in LDS once per block of sites for a group of vectors,
 // FP64), the Gram matrices and the block rotations (FP64 matrix cores), the small
-// Hermitian eigenproblems (cyclic Jacobi in one workgroup per timeslice, matrix in
-// LDS) and the residual norms.
+// Hermitian eigenproblems and Cholesky factors (one workgroup per timeslice, matrix
+// in LDS) and the residual norms.
 //
 // Layout of a block: [t][j][a][z][y][x] complex double (colour planes, so the
 // stencil's loads are contiguous across the lanes of a wave), vectors of one
@@ -311,6 +312,8 @@ struct JacArgs {
     int mode;
     double shift_rel;     // mode 1: shift = shift_rel * largest eigenvalue
     int max_sweeps;
+    int *flag;            // [lt]: Cholesky writes 1 where it broke down; Jacobi, given
+                          // the array, works only on those timeslices
 };
 
 __global__ __launch_bounds__(kJB) void jacobi_kernel(JacArgs A) {
@@ -320,6 +323,7 @@ __global__ __launch_bounds__(kJB) void jacobi_kernel(JacArgs A) {
     __shared__ double red[kJB / 64][2];
     __shared__ int order[kEigMaxM];
     const int m = A.m, t = blockIdx.x, tid = threadIdx.x;
+    if (A.flag && A.flag[t] == 0) return;
     const double2 *C = A.C + (size_t)t * m * m;
     double2 *Q = A.Q + (size_t)t * m * m;
     for (int e = tid; e < m * m; e += kJB) {
@@ -456,6 +460,84 @@ __global__ __launch_bounds__(kJB) void jacobi_kernel(JacArgs A) {
     for (int j = tid; j < m; j += kJB) {
         const int src = min(max(order[j], 0), m - 1);
         A.w[(size_t)t * m + j] = hr[src * m + src];
+    }
+}
+
+// ---- orthonormalising factor: Z[t] = R^{-1} for C[t] + shift = R^dagger R ---------------
+// One workgroup per timeslice, the Gram matrix in LDS: a right-looking Cholesky
+// factorisation C + s I = L L^dagger (s = shift_rel times the largest diagonal entry),
+// then X = L^{-1} by forward substitution (one column per thread) and Z = X^dagger, so
+// the columns of Y Z are orthonormal: (Y Z)^dagger (Y Z) = X C X^dagger = I.  A pivot
+// below kCholTiny of the largest diagonal entry (a block too close to rank deficiency
+// for two Cholesky passes to reach FP64 orthonormality) flags the timeslice, which the
+// eigendecomposition then handles instead.
+constexpr double kCholTiny = 1e-12;
+
+__global__ __launch_bounds__(256) void chol_kernel(JacArgs A) {
+    __shared__ double gr[kEigMaxM * kEigMaxM], gi[kEigMaxM * kEigMaxM];
+    __shared__ double dmax;
+    const int m = A.m, t = blockIdx.x, tid = threadIdx.x;
+    const double2 *C = A.C + (size_t)t * m * m;
+    for (int e = tid; e < m * m; e += 256) {
+        const int i = e / m, j = e - i * m;
+        const double2 a = C[i * m + j], b = C[j * m + i];
+        gr[e] = 0.5 * (a.x + b.x);   // (C + C^dagger) / 2
+        gi[e] = 0.5 * (a.y - b.y);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double d = 0.0;
+        for (int i = 0; i < m; ++i) d = fmax(d, gr[i * m + i]);
+        dmax = d;
+    }
+    __syncthreads();
+    for (int i = tid; i < m; i += 256) gr[i * m + i] += A.shift_rel * dmax;
+    __syncthreads();
+    bool ok = true;
+    for (int k = 0; k < m; ++k) {
+        const double p = gr[k * m + k];
+        ok = ok && p >= kCholTiny * dmax;   // false for NaN too
+        const double d = sqrt(fmax(p, 1e-300));
+        __syncthreads();
+        // column k below the diagonal: L[i][k] = G[i][k] / d
+        for (int i = k + 1 + tid; i < m; i += 256) {
+            gr[i * m + k] /= d;
+            gi[i * m + k] /= d;
+        }
+        if (tid == 0) {
+            gr[k * m + k] = d;
+            gi[k * m + k] = 0.0;
+        }
+        __syncthreads();
+        // trailing lower triangle: G[i][j] -= L[i][k] conj(L[j][k]), k < j <= i
+        const int n = m - k - 1;
+        for (int q = tid; q < n * n; q += 256) {
+            const int i = k + 1 + q / n, j = k + 1 + q % n;
+            if (j > i) continue;
+            const double lr = gr[i * m + k], li = gi[i * m + k], rr = gr[j * m + k], ri = gi[j * m + k];
+            gr[i * m + j] -= lr * rr + li * ri;
+            gi[i * m + j] -= li * rr - lr * ri;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) A.flag[t] = ok ? 0 : 1;
+    // X = L^{-1}: column c solves L x = e_c (x[i] = 0 for i < c); Z[c][i] = conj(X[i][c]),
+    // so row c of Z holds conj(x) and the substitution reads its own earlier entries back
+    double2 *Z = A.Z + (size_t)t * m * m;
+    for (int c = tid; c < m; c += 256) {
+        double2 *zc = Z + (size_t)c * m;
+        for (int i = 0; i < c; ++i) zc[i] = make_double2(0.0, 0.0);
+        for (int i = c; i < m; ++i) {
+            double sr = i == c ? 1.0 : 0.0, si = 0.0;
+            for (int j = c; j < i; ++j) {
+                const double lr = gr[i * m + j], li = gi[i * m + j];
+                const double xr = zc[j].x, xi = -zc[j].y;
+                sr -= lr * xr - li * xi;
+                si -= lr * xi + li * xr;
+            }
+            const double dd = gr[i * m + i];
+            zc[i] = make_double2(sr / dd, -si / dd);
+        }
     }
 }
 
@@ -639,6 +721,7 @@ struct EigWS {
     double2 *C, *Q, *Z;     // [lt][m][m]
     double2 *gscratch;      // Gram partials
     double *w, *r2, *coef;  // [lt][m], [lt][m], [2][lt][3]
+    int *flag;              // [lt] Cholesky breakdown flags
 };
 
 int eig_block(int nev) {
@@ -678,6 +761,7 @@ size_t eig_layout(const Ctx &c, int nev, char *base, EigWS *ws) {
     w.w = reinterpret_cast<double *>(take((size_t)lt * m * 8));
     w.r2 = reinterpret_cast<double *>(take((size_t)lt * m * 8));
     w.coef = reinterpret_cast<double *>(take((size_t)lt * 6 * 8));
+    w.flag = reinterpret_cast<int *>(take((size_t)lt * 4));
     if (ws) *ws = w;
     return off;
 }
@@ -718,7 +802,7 @@ struct EigRun {
                            ws.C);
         return check_launch("gram_reduce_kernel");
     }
-    laph_status jacobi(int mode, double shift_rel) const {
+    laph_status jacobi(int mode, double shift_rel, int *only = nullptr) const {
         JacArgs a;
         a.C = ws.C;
         a.Q = ws.Q;
@@ -728,8 +812,23 @@ struct EigRun {
         a.mode = mode;
         a.shift_rel = shift_rel;
         a.max_sweeps = 40;
+        a.flag = only;
         hipLaunchKernelGGL(jacobi_kernel, dim3(lt), dim3(kJB), 0, c.stream, a);
         return check_launch("jacobi_kernel");
+    }
+    laph_status chol(double shift_rel) const {
+        JacArgs a;
+        a.C = ws.C;
+        a.Q = ws.Q;
+        a.Z = ws.Z;
+        a.w = ws.w;
+        a.m = m;
+        a.mode = 1;
+        a.shift_rel = shift_rel;
+        a.max_sweeps = 0;
+        a.flag = ws.flag;
+        hipLaunchKernelGGL(chol_kernel, dim3(lt), dim3(256), 0, c.stream, a);
+        return check_launch("chol_kernel");
     }
     laph_status rotate(const double2 *in, double2 *out) const {
         RotArgs a;
@@ -787,13 +886,15 @@ laph_status laplacian_eigvecs(Ctx &c, double *V, double *lam_host, int nev, doub
         }
         return -1;
     };
-    // Loewdin: two passes Y <- Y Q Lambda^{-1/2} of the Gram matrix (the first shifted;
-    // the second restores orthonormality to rounding)
+    // two orthonormalising passes Y <- Y R^{-1} (the first shifted; the second restores
+    // orthonormality to rounding)
     auto loewdin = [&](int &cur) -> laph_status {
         for (int pass = 0; pass < 2; ++pass) {
             const int sp = other({cur});
             LAPH_TRY(R.gram(B[cur], B[cur]));
-            LAPH_TRY(R.jacobi(1, pass == 0 ? 1e-15 : 0.0));
+            const double shift = pass == 0 ? 1e-15 : 0.0;
+            LAPH_TRY(R.chol(shift));
+            LAPH_TRY(R.jacobi(1, shift, R.ws.flag));   // timeslices where Cholesky broke down
             LAPH_TRY(R.rotate(B[cur], B[sp]));
             cur = sp;
         }
