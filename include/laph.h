@@ -240,7 +240,12 @@ laph_status laph_project_adjoint(laph_ctx ctx, double *GX, const double *Gtau, c
  *    Chebyshev filter degree per iteration (<= 1: 48).  iters_host and
  *    residual_host (may be null) receive the iterations used and the largest
  *    residual norm.  work: laph_laplacian_workspace_bytes(ctx, nev) bytes of device
- *    memory (about 4 Lt (nev + nev/2) 3 Lx Ly Lz complex doubles). */
+ *    memory (about 4 Lt (nev + nev/2) 3 Lx Ly Lz complex doubles).  The block is
+ *    orthonormalised by Cholesky factors of its Gram matrix; a timeslice with a
+ *    pivot below 1e-12 of the largest diagonal entry uses the Gram matrix's
+ *    eigendecomposition instead.  The environment variable LAPH_EIG_CHOL_TINY, read
+ *    at each call, replaces that threshold (a value >= 1 takes the eigendecomposition
+ *    on every timeslice). */
 size_t laph_laplacian_workspace_bytes(laph_ctx ctx, int nev);
 laph_status laph_apply_laplacian(laph_ctx ctx, double *out, const double *in, int nvec);
 laph_status laph_laplacian_eigvecs(laph_ctx ctx, double *V, double *lambda_host, int nev, double tol, int max_iter,

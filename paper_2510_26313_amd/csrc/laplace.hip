@@ -27,6 +27,7 @@
 // [t][l][z][y][x][a].
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <initializer_list>
 #include <vector>
 
@@ -314,6 +315,7 @@ struct JacArgs {
     int max_sweeps;
     int *flag;            // [lt]: Cholesky writes 1 where it broke down; Jacobi, given
                           // the array, works only on those timeslices
+    double tiny;          // Cholesky: smallest pivot accepted, relative to the largest diagonal
 };
 
 __global__ __launch_bounds__(kJB) void jacobi_kernel(JacArgs A) {
@@ -468,9 +470,9 @@ __global__ __launch_bounds__(kJB) void jacobi_kernel(JacArgs A) {
 // factorisation C + s I = L L^dagger (s = shift_rel times the largest diagonal entry),
 // then X = L^{-1} by forward substitution (one column per thread) and Z = X^dagger, so
 // the columns of Y Z are orthonormal: (Y Z)^dagger (Y Z) = X C X^dagger = I.  A pivot
-// below kCholTiny of the largest diagonal entry (a block too close to rank deficiency
-// for two Cholesky passes to reach FP64 orthonormality) flags the timeslice, which the
-// eigendecomposition then handles instead.
+// below `tiny` (1e-12) of the largest diagonal entry (a block too close to rank
+// deficiency for two Cholesky passes to reach FP64 orthonormality) flags the
+// timeslice, which the eigendecomposition then handles instead.
 constexpr double kCholTiny = 1e-12;
 
 __global__ __launch_bounds__(256) void chol_kernel(JacArgs A) {
@@ -496,7 +498,7 @@ __global__ __launch_bounds__(256) void chol_kernel(JacArgs A) {
     bool ok = true;
     for (int k = 0; k < m; ++k) {
         const double p = gr[k * m + k];
-        ok = ok && p >= kCholTiny * dmax;   // false for NaN too
+        ok = ok && p >= A.tiny * dmax;   // false for NaN too
         const double d = sqrt(fmax(p, 1e-300));
         __syncthreads();
         // column k below the diagonal: L[i][k] = G[i][k] / d
@@ -770,6 +772,7 @@ struct EigRun {
     const Ctx &c;
     EigWS ws;
     int m, ne, lt, vs;
+    double chol_tiny;
 
     laph_status lap(const double2 *in, const double2 *z, double2 *out, const double *coef) const {
         LapArgs a;
@@ -813,6 +816,7 @@ struct EigRun {
         a.shift_rel = shift_rel;
         a.max_sweeps = 40;
         a.flag = only;
+        a.tiny = 0.0;
         hipLaunchKernelGGL(jacobi_kernel, dim3(lt), dim3(kJB), 0, c.stream, a);
         return check_launch("jacobi_kernel");
     }
@@ -827,6 +831,7 @@ struct EigRun {
         a.shift_rel = shift_rel;
         a.max_sweeps = 0;
         a.flag = ws.flag;
+        a.tiny = chol_tiny;
         hipLaunchKernelGGL(chol_kernel, dim3(lt), dim3(256), 0, c.stream, a);
         return check_launch("chol_kernel");
     }
@@ -872,7 +877,11 @@ laph_status laplacian_eigvecs(Ctx &c, double *V, double *lam_host, int nev, doub
     if (!(tol > 0) || max_iter < 1) return set_error(LAPH_ERR_INVALID, "tol must be positive and max_iter >= 1");
     const size_t need = eig_layout(c, nev, nullptr, nullptr);
     if (!work || bytes < need) return set_error(LAPH_ERR_WORKSPACE, "workspace too small: %zu < %zu", bytes, need);
-    EigRun R{c, {}, m, 3 * c.g.lx * c.g.ly * c.g.lz, c.g.lt, c.g.lx * c.g.ly * c.g.lz};
+    // LAPH_EIG_CHOL_TINY overrides the Cholesky breakdown threshold (a value >= 1 sends
+    // every timeslice through the eigendecomposition path)
+    const char *tiny_env = std::getenv("LAPH_EIG_CHOL_TINY");
+    const double tiny = tiny_env ? std::atof(tiny_env) : kCholTiny;
+    EigRun R{c, {}, m, 3 * c.g.lx * c.g.ly * c.g.lz, c.g.lt, c.g.lx * c.g.ly * c.g.lz, tiny};
     eig_layout(c, nev, work, &R.ws);
     const int lt = R.lt, ne = R.ne;
     double2 *const *B = R.ws.b;

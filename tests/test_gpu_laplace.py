@@ -4,7 +4,8 @@
 * the nev lowest eigenpairs against the oracle's dense eigendecomposition per
   timeslice (C0 4^4 with nev 8, 8^3 x 4 with nev 16, a non-cubic 6x4x4x6 with an odd
   nev 5 and 4^4 with a single vector): eigenvalues within 1e-10,
-  eigenvectors (both sides in the same phase convention) within 1e-8;
+  eigenvectors (both sides in the same phase convention) within 1e-8; the same at
+  8^3 x 4 with the orthonormalisation forced through either of its two paths;
 * 16^3 x 4, nev 32: eigenvalues of timeslice 0 against ARPACK (scipy eigsh on the
   oracle's stencil), residuals of every pair with the oracle's stencil;
 * 32^3 x 64, nev 64 (the perambulator lattice): residuals with the oracle's stencil
@@ -67,6 +68,23 @@ def test_eigvecs_vs_dense_oracle(dims, nev, seed):
     # eigenvector error <~ residual / gap to the rest of the spectrum
     err = np.linalg.norm((V - Vref).reshape(dims[3], nev, -1), axis=2)
     assert err.max() <= 1e-8, (err.max(), gap.min())
+
+
+@pytest.mark.parametrize("tiny", ["2", "1e-300"])
+def test_eigvecs_orthonormalisation_paths(monkeypatch, tiny):
+    """The Cholesky breakdown threshold forced both ways: every timeslice through the
+    Gram eigendecomposition (2), or none however close to breakdown (1e-300)."""
+    dims, nev, seed = (8, 8, 8, 4), 16, 1001
+    U, lat = _lattice(dims, seed)
+    Vref, lamref, _ = olaph.laplacian_eigvecs(U, nev)
+    monkeypatch.setenv("LAPH_EIG_CHOL_TINY", tiny)
+    log_case("laplacian_eigvecs orthonormalisation", dims=dims, nev=nev, chol_tiny=tiny)
+    V, lam, info = lat.laplacian_eigvecs(nev, tol=1e-12)
+    V = host(V)
+    assert info["residual"] <= 1e-12
+    assert np.abs(lam - lamref).max() <= 1e-10
+    err = np.linalg.norm((V - Vref).reshape(dims[3], nev, -1), axis=2)
+    assert err.max() <= 1e-8
 
 
 def test_eigvecs_16cubed_vs_arpack():
