@@ -549,6 +549,7 @@ struct RotArgs {
     double2 *out;
     const double2 *Z;       // [lt][m][m]
     int m, ne, nout, mout;  // out block has mout vectors per timeslice
+    const int *tri;         // [lt] or null: where tri[t] == 0, Z[t][k][j] = 0 for k > j
 };
 
 // Computed on the FP64 matrix cores as
@@ -556,7 +557,9 @@ struct RotArgs {
 // 16 k at a time and shared by the four waves), B = the input block (16 consecutive e
 // per k row: 256-byte loads), complex as four real products per 16 x 16 block.  A wave
 // owns 32 e (two column blocks) and every j (up to six row blocks), so a lane's results
-// for one j are 16 consecutive e: the stores are 256-byte segments too.
+// for one j are 16 consecutive e: the stores are 256-byte segments too.  An upper
+// triangular Z (a Cholesky factor's inverse) skips the row blocks wholly below the
+// diagonal: 21 of the 36 block products at m = 96.
 constexpr int kRE = 32;                 // e per wave
 constexpr int kRK = 16;                 // k per staged chunk
 constexpr int kRJB = kEigMaxM / 16;     // row blocks (j)
@@ -567,6 +570,7 @@ __global__ __launch_bounds__(256) void rotate_mfma_kernel(RotArgs A) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int e0 = (blockIdx.x * 4 + wave) * kRE;
     const int njb = (A.nout + 15) / 16;
+    const bool upper = A.tri && A.tri[t] == 0;
     d4 cr[kRJB][2], ci[kRJB][2];
 #pragma unroll
     for (int jb = 0; jb < kRJB; ++jb)
@@ -602,6 +606,7 @@ __global__ __launch_bounds__(256) void rotate_mfma_kernel(RotArgs A) {
 #pragma unroll
             for (int jb = 0; jb < kRJB; ++jb) {
                 if (jb >= njb) break;   // wave-uniform
+                if (upper && 16 * jb + 15 < k0) continue;
                 const int j = 16 * jb + (lane & 15);
                 const double ar = zr[kk][j], ai = zi[kk][j], nai = -ai;
 #pragma unroll
@@ -835,7 +840,7 @@ struct EigRun {
         hipLaunchKernelGGL(chol_kernel, dim3(lt), dim3(256), 0, c.stream, a);
         return check_launch("chol_kernel");
     }
-    laph_status rotate(const double2 *in, double2 *out) const {
+    laph_status rotate(const double2 *in, double2 *out, bool tri = false) const {
         RotArgs a;
         a.in = in;
         a.out = out;
@@ -844,6 +849,7 @@ struct EigRun {
         a.ne = ne;
         a.nout = m;
         a.mout = m;
+        a.tri = tri ? ws.flag : nullptr;   // Cholesky's breakdown flags: 0 = triangular Z
         dim3 grid((ne + 4 * kRE - 1) / (4 * kRE), lt);
         hipLaunchKernelGGL(rotate_mfma_kernel, grid, dim3(256), 0, c.stream, a);
         return check_launch("rotate_mfma_kernel");
@@ -904,7 +910,7 @@ laph_status laplacian_eigvecs(Ctx &c, double *V, double *lam_host, int nev, doub
             const double shift = pass == 0 ? 1e-15 : 0.0;
             LAPH_TRY(R.chol(shift));
             LAPH_TRY(R.jacobi(1, shift, R.ws.flag));   // timeslices where Cholesky broke down
-            LAPH_TRY(R.rotate(B[cur], B[sp]));
+            LAPH_TRY(R.rotate(B[cur], B[sp], true));
             cur = sp;
         }
         return LAPH_OK;
