@@ -237,7 +237,9 @@ laph_status laph_project_adjoint(laph_ctx ctx, double *GX, const double *Gtau, c
  *    lambda_host = [Lt][nev] ascending.  It stops when every returned pair has
  *    ||(-Delta) v - lambda v|| <= tol (absolute; the spectrum lies in [0, 12]) or
  *    after max_iter iterations (then LAPH_ERR_NOCONV; V is not written).  degree:
- *    Chebyshev filter degree per iteration (<= 1: 48).  iters_host and
+ *    largest Chebyshev filter degree per iteration (<= 1: 96); the degree is also
+ *    kept low enough that the filter grows the lowest Ritz direction by at most
+ *    about 1e6 over the damped interval.  iters_host and
  *    residual_host (may be null) receive the iterations used and the largest
  *    residual norm.  work: laph_laplacian_workspace_bytes(ctx, nev) bytes of device
  *    memory (about 4 Lt (nev + nev/2) 3 Lx Ly Lz complex doubles).  The block is

@@ -42,7 +42,8 @@ constexpr int kEigMaxM = 96;      // largest block (Jacobi matrix in LDS)
 constexpr int kJB = 1024;         // threads of the Jacobi workgroup
 constexpr int kGKC = 16;          // Gram K chunk
 constexpr int kLmax = 12;         // upper bound of the spectrum
-constexpr int kDefaultDegree = 48; // Chebyshev degree per iteration when the caller passes <= 1
+constexpr int kDefaultDegree = 96; // Chebyshev degree cap when the caller passes <= 1 (the growth
+                                   // bound below is what limits it: about 65 at 32^3)
 
 // ---- stencil: out = ca[t] (-Delta) in + cb[t] in + cc[t] z ------------------------
 struct LapArgs {
@@ -204,23 +205,34 @@ struct GramArgs {
     double2 *scratch;       // [split][lt][m][m]
 };
 
-// One workgroup per (timeslice, K slice) computes the whole m x m block (m <= 96: 6 x 6
-// blocks of 16), each wave a 3 x 3 quadrant of blocks, so no tile padding is computed
-// at m = 96 (tiles of 64 did 1.78x the work).
+// One workgroup per (timeslice, K slice) computes the m x m block (m <= 96: 6 x 6
+// blocks of 16), so no tile padding is computed at m = 96 (tiles of 64 did 1.78x the
+// work).  Both uses of C here are Hermitian (a Gram matrix Y^dagger Y, and
+// H = Y^dagger (-Delta) Y), so only the 21 blocks on and above the diagonal are
+// computed, at most 6 per wave (rows 0 | 1 | 2 and 5 | 3 and 4), and the second pass
+// mirrors them.
+__device__ __forceinline__ void gram_slot(int wave, int s, int &a, int &b) {
+    if (wave == 0) { a = 0; b = s; }
+    else if (wave == 1) { a = 1; b = 1 + s; }
+    else if (wave == 2) { a = s < 4 ? 2 : 5; b = s < 4 ? 2 + s : 5; }
+    else { a = s < 3 ? 3 : 4; b = s < 3 ? 3 + s : s + 1; }
+}
+
 __global__ __launch_bounds__(256) void gram_kernel(GramArgs A) {
     __shared__ double Pr[kEigMaxM][kGKC + 1], Pi[kEigMaxM][kGKC + 1], Rr[kEigMaxM][kGKC + 1], Ri[kEigMaxM][kGKC + 1];
     const int split = blockIdx.x % A.nsplit;
     const int t = blockIdx.x / A.nsplit;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int rb0 = 3 * (wave >> 1), cb0 = 3 * (wave & 1);   // the wave's quadrant
-    d4 cre[3][3], cim[3][3];
+    const int nslot = wave == 0 ? 6 : 5;   // wave-uniform
+    int sa[6], sb[6];
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+    for (int s = 0; s < 6; ++s) gram_slot(wave, s, sa[s], sb[s]);
+    d4 cre[6], cim[6];
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            cre[a][b] = d4{0, 0, 0, 0};
-            cim[a][b] = d4{0, 0, 0, 0};
-        }
+    for (int s = 0; s < 6; ++s) {
+        cre[s] = d4{0, 0, 0, 0};
+        cim[s] = d4{0, 0, 0, 0};
+    }
     const int c0 = (int)((long)A.nchunk * split / A.nsplit), c1 = (int)((long)A.nchunk * (split + 1) / A.nsplit);
     const double2 *P = A.P + (size_t)t * A.m * A.ne, *R = A.R + (size_t)t * A.m * A.ne;
     for (int ch = c0; ch < c1; ++ch) {
@@ -242,62 +254,51 @@ __global__ __launch_bounds__(256) void gram_kernel(GramArgs A) {
 #pragma unroll
         for (int k4 = 0; k4 < kGKC; k4 += 4) {
             const int kk = k4 + (lane >> 4);
-            double ar[3], ai[3], nai[3], br[3], bi[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const int row = 16 * (rb0 + a) + (lane & 15);
-                ar[a] = Pr[row][kk];
-                ai[a] = Pi[row][kk];
-                nai[a] = -ai[a];
-                const int col = 16 * (cb0 + a) + (lane & 15);
-                br[a] = Rr[col][kk];
-                bi[a] = Ri[col][kk];
-            }
             // conj(P) R = (Pr Rr + Pi Ri) + i (Pr Ri - Pi Rr)
 #pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], cre[a][b], 0, 0, 0);
-                    cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], bi[b], cim[a][b], 0, 0, 0);
-                }
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], bi[b], cre[a][b], 0, 0, 0);
-                    cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[a], br[b], cim[a][b], 0, 0, 0);
-                }
+            for (int s = 0; s < 6; ++s) {
+                if (s >= nslot) break;
+                const int row = 16 * sa[s] + (lane & 15), col = 16 * sb[s] + (lane & 15);
+                const double ar = Pr[row][kk], ai = Pi[row][kk], br = Rr[col][kk], bi = Ri[col][kk];
+                cre[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, cre[s], 0, 0, 0);
+                cim[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, cim[s], 0, 0, 0);
+                cre[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, cre[s], 0, 0, 0);
+                cim[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, br, cim[s], 0, 0, 0);
+            }
         }
         __syncthreads();
     }
     // the 16x16x4 FP64 MFMA leaves C[row][col] in lane col + 16 (row % 4), register row / 4
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+    for (int s = 0; s < 6; ++s) {
+        if (s >= nslot) break;
+        const int j = 16 * sb[s] + (lane & 15);
+        if (j >= A.m) continue;
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const int j = 16 * (cb0 + b) + (lane & 15);
-            if (j >= A.m) continue;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = 16 * (rb0 + a) + (lane >> 4) + 4 * r;
-                if (i >= A.m) continue;
-                A.scratch[(((size_t)split * A.lt + t) * A.m + i) * A.m + j] = make_double2(cre[a][b][r], cim[a][b][r]);
-            }
+        for (int r = 0; r < 4; ++r) {
+            const int i = 16 * sa[s] + (lane >> 4) + 4 * r;
+            if (i >= A.m) continue;
+            A.scratch[(((size_t)split * A.lt + t) * A.m + i) * A.m + j] = make_double2(cre[s][r], cim[s][r]);
         }
+    }
 }
 
 __global__ void gram_reduce_kernel(GramArgs A, double2 *C) {
     const long idx = (long)blockIdx.x * 256 + threadIdx.x;
     const long total = (long)A.lt * A.m * A.m;
     if (idx >= total) return;
+    // entries of blocks below the diagonal are the conjugates of their mirror images
+    const long mm = (long)A.m * A.m, t = idx / mm;
+    const int i = (int)((idx - t * mm) / A.m), j = (int)(idx - t * mm - (long)i * A.m);
+    const bool mirror = i / 16 > j / 16;
+    const long src = mirror ? t * mm + (long)j * A.m + i : idx;
     double2 s = make_double2(0, 0);
     for (int sp = 0; sp < A.nsplit; ++sp) {
-        const double2 v = A.scratch[(size_t)sp * total + idx];
+        const double2 v = A.scratch[(size_t)sp * total + src];
         s.x += v.x;
         s.y += v.y;
     }
-    C[idx] = s;
+    C[idx] = mirror ? make_double2(s.x, -s.y) : s;
 }
 
 // ---- Hermitian eigensolver: cyclic Jacobi, round-robin parallel ordering ---------------
