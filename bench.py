@@ -153,31 +153,31 @@ def extra_suite(laph, torch):
     out = {}
     tol = 1e-10
     # 16^3 x 32: 128 RHS at t0 = 0, one RHS after another
-    cfg = ls.CONFIGS["c1"]
+    cfg = ls.CONFIGS["single_rhs_16x16x16x32"]
     dims = cfg["dims"]
     lat = laph.Lattice(dims)
     lat.load_gauge(torch.from_numpy(ls.gauge_field(dims, cfg["seed_u"])).cuda())
     lat.set_masses([cfg["masses"][0]], cfg["csw"])
     Vd = torch.from_numpy(ls.orthonormal_laph_vectors(dims, cfg["nev"], cfg["seed_v"])).cuda()
     B = lat.make_sources(Vd, 0)
-    c1 = {}
+    single = {}
     for prec in ("f64", "f32", "f16n"):
         p = laph.default_params(inner_prec=prec, batched=0, rhs_tile=1, stencil=1, traversal=1)
         lat.solve_raw(B[:2].contiguous(), 0, tol, p)
         (_, st), dt = _timed(torch, lambda: lat.solve_raw(B, 0, tol, p))
-        c1["single_rhs_" + prec] = _solve_summary(st, B.shape[0], dt)
+        single["single_rhs_" + prec] = _solve_summary(st, B.shape[0], dt)
     tuned = lat.autotune("f16n", B.shape[0], 0)
     lat.autotune("f64", B.shape[0], 0)   # the reliable-update stages' shape, outside the timing
     p = laph.default_params(inner_prec="f16n", stencil=tuned["stencil"], rhs_tile=tuned["rhs_tile"],
                             traversal=tuned["traversal"])
     (_, st), dt = _timed(torch, lambda: lat.solve_raw(B, 0, tol, p))
-    c1["batched_f16n"] = _solve_summary(st, B.shape[0], dt)
-    out["16x16x16x32_128rhs_m0.05"] = c1
+    single["batched_f16n"] = _solve_summary(st, B.shape[0], dt)
+    out["16x16x16x32_128rhs_m0.05"] = single
     del lat, Vd, B
     torch.cuda.empty_cache()
 
     # 24^3 x 48: 256 RHS over four masses in one batched solve
-    cfg = ls.CONFIGS["c2"]
+    cfg = ls.CONFIGS["multimass_24x24x24x48"]
     dims = cfg["dims"]
     lat = laph.Lattice(dims)
     lat.load_gauge(torch.from_numpy(ls.gauge_field(dims, cfg["seed_u"])).cuda())
@@ -191,37 +191,37 @@ def extra_suite(laph, torch):
                             traversal=tuned["traversal"])
     (X, st), dt = _timed(torch, lambda: lat.solve_raw(B, mi, tol, p))
     del X
-    c2 = {"batched_f16n": _solve_summary(st, B.shape[0], dt), "tuned": tuned, "per_mass": {}}
+    multi = {"batched_f16n": _solve_summary(st, B.shape[0], dt), "tuned": tuned, "per_mass": {}}
     for m, m0 in enumerate(cfg["masses"]):
         it = [s["iters"] for s, mm in zip(st, mi) if mm == m]
-        c2["per_mass"]["%g" % m0] = {"rhs": len(it), "iters_min": min(it), "iters_max": max(it)}
+        multi["per_mass"]["%g" % m0] = {"rhs": len(it), "iters_min": min(it), "iters_max": max(it)}
     pick = [0, 39, 40, 111, 112, 175, 176, 255]   # two per mass
     Bs = B[pick].contiguous()
     p64 = laph.default_params(inner_prec="f64", batched=0, rhs_tile=1, stencil=1, traversal=1)
     (_, st64), dt64 = _timed(torch, lambda: lat.solve_raw(Bs, [mi[r] for r in pick], tol, p64))
-    c2["single_rhs_f64_sample"] = _solve_summary(st64, len(pick), dt64)
-    c2["speedup_of_batched_mixed"] = round(c2["batched_f16n"]["rhs_per_s"] / c2["single_rhs_f64_sample"]["rhs_per_s"], 2)
-    out["24x24x24x48_256rhs_4masses"] = c2
+    multi["single_rhs_f64_sample"] = _solve_summary(st64, len(pick), dt64)
+    multi["speedup_of_batched_mixed"] = round(multi["batched_f16n"]["rhs_per_s"] / multi["single_rhs_f64_sample"]["rhs_per_s"], 2)
+    out["24x24x24x48_256rhs_4masses"] = multi
     del lat, Vd, B, Bs
     torch.cuda.empty_cache()
 
     # 16^3 x 32: differentiable perambulator, L = sum |tau[t = 8]|^2, FP32 inner
-    cfg = ls.CONFIGS["c3"]
+    cfg = ls.CONFIGS["gradients_8x8x8x8"]
     dims = cfg["dims_timing"]
     lat = laph.Lattice(dims)
     lat.load_gauge(torch.from_numpy(ls.gauge_field(dims, cfg["seed_u"])).cuda())
     lat.csw = cfg["csw"]
     Vd = torch.from_numpy(ls.orthonormal_laph_vectors(dims, cfg["nev"], cfg["seed_v"])).cuda()
-    c3 = {}
+    grad = {}
     for rep in range(2):   # the first pass warms up
         B = lat.make_sources(Vd, 0).requires_grad_(True)
         m0 = torch.tensor(cfg["masses"][0], dtype=torch.float64, requires_grad=True)
         tau, tf = _timed(torch, lambda: laph.project(lat, laph.solve(lat, B, m0, tol, inner_prec="f32"), Vd))
         L = (tau[cfg["t_sink_timing"]].abs() ** 2).sum()
         _, tb = _timed(torch, lambda: L.backward())
-        c3 = {"rhs": int(B.shape[0]), "forward_s": round(tf, 4), "backward_s": round(tb, 4),
-              "backward_over_forward": round(tb / tf, 3), "grad_m0": float(m0.grad)}
-    out["16x16x16x32_gradients"] = c3
+        grad = {"rhs": int(B.shape[0]), "forward_s": round(tf, 4), "backward_s": round(tb, 4),
+                "backward_over_forward": round(tb / tf, 3), "grad_m0": float(m0.grad)}
+    out["16x16x16x32_gradients"] = grad
     del lat, Vd
     torch.cuda.empty_cache()
 
@@ -233,7 +233,7 @@ def extra_suite(laph, torch):
 def laph_vectors_run(laph, torch):
     """The 64 lowest eigenpairs of -Delta on all 64 timeslices of 32^3 x 64 (the LapH
     vectors), and the Laplacian stencil's rate on 8 vectors per timeslice."""
-    cfg = ls.CONFIGS["c4"]
+    cfg = ls.CONFIGS["perambulator_32x32x32x64"]
     dims = cfg["dims"]
     lat = laph.Lattice(dims)
     lat.load_gauge(torch.from_numpy(ls.gauge_field(dims, cfg["seed_u"])).cuda())
@@ -264,7 +264,7 @@ def contractions_run(laph, torch, n_mom=4, reps=3):
     """Meson doublets and baryon triplets of 64 LapH vectors on every timeslice of
     32^3 x 64 for n_mom momenta: average time per call (HIP events over reps calls
     after one warm call) and the rates against the FP64 matrix-core and HBM peaks."""
-    cfg = ls.CONFIGS["c4"]
+    cfg = ls.CONFIGS["perambulator_32x32x32x64"]
     dims, nev = cfg["dims"], cfg["nev"]
     lat = laph.Lattice(dims)
     Vd = torch.from_numpy(ls.orthonormal_laph_vectors(dims, nev, cfg["seed_v"])).cuda()
@@ -331,7 +331,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c4")
+    ap.add_argument("--config", default="perambulator_32x32x32x64")
     ap.add_argument("--prec", default="f16n")
     ap.add_argument("--chunk", type=int, default=128)
     ap.add_argument("--rhs-tile", type=int, default=0, help="RHS per link load (0: autotuned)")

@@ -1,13 +1,13 @@
-"""Write tests/golden/c3_gradients.json from the FP64 oracle only.
+"""Write tests/golden/gradients_8x8x8x8.json from the FP64 oracle only.
 
-C3 (8^4, m0 = 0.05, c_sw = 1, N_ev = 16 seeded orthonormal LapH vectors,
+The gradient workload (8^4, m0 = 0.05, c_sw = 1, N_ev = 16 seeded orthonormal LapH vectors,
 64 spin-diluted sources at t0 = 0, L = sum |tau[t_sink = 4]|^2): the loss, the
 adjoint-formula gradients with respect to m0 and to the sources, and central
 differences at h = 1e-4 along seeded directions (one supported on the t0 slice,
 one on the full lattice) and for 8 single source components.  The GPU
 gradient test compares against these numbers.
 
-Run:  python tests/golden/make_c3_gradients.py
+Run:  python tests/golden/make_gradients_8x8x8x8.py
 """
 import json
 import os
@@ -39,7 +39,7 @@ def single_components(shape, seed, n=8):
 
 
 def main():
-    cfg = ls.CONFIGS["c3"]
+    cfg = ls.CONFIGS["gradients_8x8x8x8"]
     dims, m0, csw, ts, h = cfg["dims"], cfg["masses"][0], cfg["csw"], cfg["t_sink"], cfg["fd_h"]
     U = ls.gauge_field(dims, cfg["seed_u"])
     V = ls.orthonormal_laph_vectors(dims, cfg["nev"], cfg["seed_v"])
@@ -49,7 +49,7 @@ def main():
     print("L", L, "grad_m0", gm, flush=True)
     fd_m = laph.fd_mass(U, V, b, m0, csw, ts, h=h)
     print("fd_m0", fd_m, flush=True)
-    out = dict(config="c3", dims=list(dims), m0=m0, csw=csw, t_sink=ts, h=h, L=L, grad_m0=gm, fd_m0=fd_m,
+    out = dict(config="gradients_8x8x8x8", dims=list(dims), m0=m0, csw=csw, t_sink=ts, h=h, L=L, grad_m0=gm, fd_m0=fd_m,
                grad_b_norm=float(np.linalg.norm(Z)), directions=[], components=[])
     for name, d in zip(("t0_slice", "full"), directions(b.shape, cfg["seed_fd"])):
         fd = laph.fd_source(D, V, b, d, ts, h=h)
@@ -71,7 +71,7 @@ def main():
         an = float(np.real(Z[idx]))
         print("component", idx, an, fd, flush=True)
         out["components"].append(dict(index=list(idx), adjoint=an, fd=fd))
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c3_gradients.json")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "gradients_8x8x8x8.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print("wrote", path)

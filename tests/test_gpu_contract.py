@@ -75,7 +75,7 @@ def test_many_momenta():
 
 
 def test_full_lattice_sampled():
-    cfg = ls.CONFIGS["c4"]
+    cfg = ls.CONFIGS["perambulator_32x32x32x64"]
     dims, nev = cfg["dims"], cfg["nev"]
     V = ls.orthonormal_laph_vectors(dims, nev, cfg["seed_v"])
     lat = _lattice(dims)

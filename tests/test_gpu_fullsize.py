@@ -3,15 +3,15 @@
 The oracle cannot solve 32^3 x 64 (or 24^3 x 48) in test time, so these checks
 use outputs it computes one by one and properties that hold at any size:
 
-* C4 (32^3 x 64, nev 64, m0 0.02): the fused perambulator for t0 = 0 and t0 = 1
+* the perambulator workload (32^3 x 64, nev 64, m0 0.02): the fused perambulator for t0 = 0 and t0 = 1
   (FP16N inner, LDS stencil, chunks of 128 -- the bench configuration) obeys
   gamma5 reciprocity between the two source times; a perambulator over 8 LapH
   vectors and a solve of the same sources made with the same parameters give
   solutions that pass the oracle's D at sampled sites (pointwise residual) and
   whose oracle projection reproduces the sampled tau entries;
-* C2 (24^3 x 48, four masses split 40/72/64/80 in one batched solve): per-RHS
+* the multi-mass workload (24^3 x 48, four masses split 40/72/64/80 in one batched solve): per-RHS
   FP64 residual reported by the library and the oracle's D at sampled sites;
-* C1 (16^3 x 32, single-RHS solver, FP32 and FP16N inner): sampled RHS against
+* the single-RHS workload (16^3 x 32, single-RHS solver, FP32 and FP16N inner): sampled RHS against
   full oracle solves (1e-8).
 """
 import numpy as np
@@ -42,25 +42,25 @@ def _pointwise_residual(U, X, B, sites, m0, csw):
 
 
 @pytest.fixture()
-def c4():
+def peramb_case():
     require_gpu()
-    cfg = ls.CONFIGS["c4"]
+    cfg = ls.CONFIGS["perambulator_32x32x32x64"]
     dims = cfg["dims"]
-    log_case("c4 inputs", dims=dims)
+    log_case("32^3x64 inputs", dims=dims)
     U = ls.gauge_field(dims, cfg["seed_u"])
     V = ls.orthonormal_laph_vectors(dims, cfg["nev"], cfg["seed_v"])
     lat = make_lattice(dims, U, masses=cfg["masses"], csw=cfg["csw"])
     return dict(cfg=cfg, U=U, V=V, lat=lat, Vd=dev(V))
 
 
-def test_c4_perambulator_sampled_and_reciprocal(c4):
+def test_perambulator_32x32x32x64_sampled_and_reciprocal(peramb_case):
     import paper_2510_26313_amd as pl
-    cfg, U, V, lat, Vd = c4["cfg"], c4["U"], c4["V"], c4["lat"], c4["Vd"]
+    cfg, U, V, lat, Vd = peramb_case["cfg"], peramb_case["U"], peramb_case["V"], peramb_case["lat"], peramb_case["Vd"]
     m0, csw = cfg["masses"][0], cfg["csw"]
     p = pl.default_params(inner_prec="f16n", chunk=128, rhs_tile=16, stencil=2)
-    log_case("c4 perambulator", t0=0)
+    log_case("32^3x64 perambulator", t0=0)
     tauA, stA = lat.perambulator_raw(Vd, 0, 0, 1e-10, p)
-    log_case("c4 perambulator", t0=1)
+    log_case("32^3x64 perambulator", t0=1)
     tauB, stB = lat.perambulator_raw(Vd, 1, 0, 1e-10, p)
     assert all(s["status"] == "converged" and s["true_res"] <= 1e-10 for s in stA + stB)
     tauA, tauB = host(tauA), host(tauB)
@@ -80,12 +80,12 @@ def test_c4_perambulator_sampled_and_reciprocal(c4):
     nev8 = 8
     V8 = np.ascontiguousarray(V[:, :nev8])
     p32 = pl.default_params(inner_prec="f16n", chunk=32, rhs_tile=16, stencil=2)
-    log_case("c4 perambulator", t0=0, nev=nev8, chunk=32)
+    log_case("32^3x64 perambulator", t0=0, nev=nev8, chunk=32)
     tauC, stC = lat.perambulator_raw(dev(V8), 0, 0, 1e-10, p32)
     tauC = host(tauC)
     rhs = [5, 18, 31]
     B = laph.laph_sources(V8, 0)
-    log_case("c4 sampled solves", nrhs=B.shape[0])
+    log_case("32^3x64 sampled solves", nrhs=B.shape[0])
     Xd, st = lat.solve_raw(dev(B), 0, 1e-10, p32)
     X = host(Xd[rhs])
     del Xd
@@ -105,26 +105,26 @@ def test_c4_perambulator_sampled_and_reciprocal(c4):
         assert np.linalg.norm(tauA[0, :nev8, k, :, al] - tauC[0, :, k, :, al]) <= 1e-6 * np.linalg.norm(tauC[0, :, k, :, al])
 
 
-def test_c2_multimass_batched_sampled():
+def test_multimass_24x24x24x48_batched_sampled():
     import gc
     import paper_2510_26313_amd as pl
     require_gpu()
     gc.collect()
     torch.cuda.empty_cache()
-    cfg = ls.CONFIGS["c2"]
+    cfg = ls.CONFIGS["multimass_24x24x24x48"]
     dims = cfg["dims"]
-    log_case("c2 inputs", dims=dims)
+    log_case("24^3x48 inputs", dims=dims)
     U = ls.gauge_field(dims, cfg["seed_u"])
     V = ls.orthonormal_laph_vectors(dims, cfg["nev"], cfg["seed_v"])
     lat = make_lattice(dims, U, masses=cfg["masses"], csw=cfg["csw"])
     mi = ls.rhs_masses(cfg)
     Vd = dev(V)
     B = lat.make_sources(Vd, 0)
-    log_case("c2 batched solve", nrhs=len(mi))
+    log_case("24^3x48 batched solve", nrhs=len(mi))
     X, st = lat.solve_raw(B, mi, 1e-10, pl.default_params(inner_prec="f16n", rhs_tile=16, stencil=2))
     assert all(s["status"] == "converged" and s["true_res"] <= 1e-10 for s in st)
     iters = {m: [s["iters"] for s, mm in zip(st, mi) if mm == m] for m in range(4)}
-    print("c2 iterations per mass", {cfg["masses"][m]: (min(v), max(v)) for m, v in iters.items()}, flush=True)
+    print("24^3x48 iterations per mass", {cfg["masses"][m]: (min(v), max(v)) for m, v in iters.items()}, flush=True)
     pick = [0, 39, 40, 111, 112, 175, 176, 255]   # two per mass, at the range edges
     Xs, Bs = host(X[pick]), host(B[pick])
     del X
@@ -135,14 +135,14 @@ def test_c2_multimass_batched_sampled():
 
 
 @pytest.fixture(scope="module")
-def c1():
+def single_case():
     require_gpu()
-    cfg = ls.CONFIGS["c1"]
+    cfg = ls.CONFIGS["single_rhs_16x16x16x32"]
     dims = cfg["dims"]
     U = ls.gauge_field(dims, cfg["seed_u"])
     V = ls.orthonormal_laph_vectors(dims, cfg["nev"], cfg["seed_v"])
     B = laph.laph_sources(V, 0)[[0, 77]]
-    log_case("c1 oracle solves", nrhs=2)
+    log_case("16^3x32 oracle solves", nrhs=2)
     D = dirac.WilsonClover(U, cfg["masses"][0], cfg["csw"])
     x_ref, _ = solvers.bicgstab(D.apply, B, tol=1e-13)
     lat = make_lattice(dims, U, masses=cfg["masses"], csw=cfg["csw"])
@@ -150,9 +150,9 @@ def c1():
 
 
 @pytest.mark.parametrize("prec", ["f32", "f16n"])
-def test_c1_single_rhs_vs_oracle(c1, prec):
+def test_single_rhs_16x16x16x32_vs_oracle(single_case, prec):
     import paper_2510_26313_amd as pl
-    log_case("c1 single-rhs", prec=prec)
-    X, st = c1["lat"].solve_raw(dev(c1["B"]), 0, 1e-10, pl.default_params(inner_prec=prec, batched=0))
-    assert per_rhs_rel(host(X), c1["x_ref"]).max() < 1e-8
+    log_case("16^3x32 single-rhs", prec=prec)
+    X, st = single_case["lat"].solve_raw(dev(single_case["B"]), 0, 1e-10, pl.default_params(inner_prec=prec, batched=0))
+    assert per_rhs_rel(host(X), single_case["x_ref"]).max() < 1e-8
     assert all(s["status"] == "converged" and s["true_res"] <= 1e-10 for s in st)

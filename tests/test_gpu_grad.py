@@ -1,12 +1,12 @@
-"""GPU gradients of the perambulator loss (C3) against the FP64 oracle.
+"""GPU gradients of the perambulator loss (8^4 gradient workload) against the FP64 oracle.
 
-C3: 8^4 lattice, m0 = 0.05, c_sw = 1, N_ev = 16 seeded orthonormal LapH vectors,
+8^4 lattice, m0 = 0.05, c_sw = 1, N_ev = 16 seeded orthonormal LapH vectors,
 64 spin-diluted sources at t0 = 0, L = sum |tau[t_sink = 4]|^2.  The GPU
 gradients with respect to the sources and to m0 come from the differentiable
 wrappers (adjoint solve = the library's dagger solve, inner FP32 or FP16-norm
 iterations with FP64 reliable updates).  Reference numbers -- the oracle's
 adjoint-formula gradients and its central differences at h = 1e-4 -- are in
-tests/golden/c3_gradients.json, written by tests/golden/make_c3_gradients.py
+tests/golden/gradients_8x8x8x8.json, written by tests/golden/make_gradients_8x8x8x8.py
 (oracle only).  Tolerance 1e-5 relative (per checked scalar, floored at 1e-3 of
 the largest gradient entry for components).
 """
@@ -21,15 +21,15 @@ import laph_synth as ls
 from gpu_common import dev, host, log_case, make_lattice, require_gpu
 
 pytestmark = pytest.mark.gpu
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_gradients.json")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "gradients_8x8x8x8.json")
 
 
 @pytest.fixture(scope="module")
-def c3():
+def grad_case():
     require_gpu()
-    from golden.make_c3_gradients import directions, single_components  # noqa: F401
+    from golden.make_gradients_8x8x8x8 import directions, single_components  # noqa: F401
     ref = json.load(open(GOLDEN))
-    cfg = ls.CONFIGS["c3"]
+    cfg = ls.CONFIGS["gradients_8x8x8x8"]
     dims = cfg["dims"]
     U = ls.gauge_field(dims, cfg["seed_u"])
     V = ls.orthonormal_laph_vectors(dims, cfg["nev"], cfg["seed_v"])
@@ -41,13 +41,13 @@ def _close(a, b, tol, floor=0.0):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f16n"])
-def test_gradients_vs_oracle_and_fd(c3, prec):
+def test_gradients_vs_oracle_and_fd(grad_case, prec):
     import paper_2510_26313_amd as pl
-    from golden.make_c3_gradients import directions
-    cfg, ref = c3["cfg"], c3["ref"]
+    from golden.make_gradients_8x8x8x8 import directions
+    cfg, ref = grad_case["cfg"], grad_case["ref"]
     log_case("gradients", prec=prec)
-    lat = make_lattice(cfg["dims"], c3["U"], masses=cfg["masses"], csw=cfg["csw"])
-    Vd = dev(c3["V"])
+    lat = make_lattice(cfg["dims"], grad_case["U"], masses=cfg["masses"], csw=cfg["csw"])
+    Vd = dev(grad_case["V"])
     B = lat.make_sources(Vd, 0).requires_grad_(True)
     m0 = torch.tensor(cfg["masses"][0], dtype=torch.float64, requires_grad=True)
     X = pl.solve(lat, B, m0, tol=1e-10, inner_prec=prec)
@@ -70,12 +70,12 @@ def test_gradients_vs_oracle_and_fd(c3, prec):
         assert _close(an, c["fd"], 1e-5, 1e-3 * gmax)
 
 
-def test_perambulator_autograd_matches_fused(c3):
+def test_perambulator_autograd_matches_fused(grad_case):
     """The composed differentiable perambulator equals the fused library call."""
     import paper_2510_26313_amd as pl
-    cfg, ref = c3["cfg"], c3["ref"]
-    lat = make_lattice(cfg["dims"], c3["U"], masses=cfg["masses"], csw=cfg["csw"])
-    Vd = dev(c3["V"])
+    cfg, ref = grad_case["cfg"], grad_case["ref"]
+    lat = make_lattice(cfg["dims"], grad_case["U"], masses=cfg["masses"], csw=cfg["csw"])
+    Vd = dev(grad_case["V"])
     log_case("perambulator_autograd")
     m0 = torch.tensor(cfg["masses"][0], dtype=torch.float64, requires_grad=True)
     tau_g = pl.perambulator(lat, Vd, 0, m0, tol=1e-10, csw=cfg["csw"], inner_prec="f32")

@@ -2,7 +2,7 @@
 
 * (-Delta) X against the oracle's stencil on a ragged lattice (1e-13);
 * the nev lowest eigenpairs against the oracle's dense eigendecomposition per
-  timeslice (C0 4^4 with nev 8, 8^3 x 4 with nev 16, a non-cubic 6x4x4x6 with an odd
+  timeslice (4^4 with nev 8, 8^3 x 4 with nev 16, a non-cubic 6x4x4x6 with an odd
   nev 5 and 4^4 with a single vector): eigenvalues within 1e-10,
   eigenvectors (both sides in the same phase convention) within 1e-8; the same at
   8^3 x 4 with the orthonormalisation forced through either of its two paths;
@@ -107,7 +107,7 @@ def test_eigvecs_16cubed_vs_arpack():
 
 
 def test_eigvecs_full_lattice_residuals():
-    cfg = ls.CONFIGS["c4"]
+    cfg = ls.CONFIGS["perambulator_32x32x32x64"]
     dims, nev = cfg["dims"], cfg["nev"]
     U, lat = _lattice(dims, cfg["seed_u"])
     log_case("laplacian_eigvecs", dims=dims, nev=nev)
@@ -122,10 +122,10 @@ def test_eigvecs_full_lattice_residuals():
 
 
 def test_perambulator_from_gpu_laph_vectors():
-    """The whole pipeline on C0: LapH vectors from the GPU eigensolver, then the fused
+    """The whole pipeline on the 4^4 workload: LapH vectors from the GPU eigensolver, then the fused
     perambulator, against the oracle's dense-inverse perambulator on the oracle's vectors."""
     import paper_2510_26313_amd as pl
-    cfg = ls.CONFIGS["c0"]
+    cfg = ls.CONFIGS["dense_4x4x4x4"]
     dims = cfg["dims"]
     U = ls.gauge_field(dims, cfg["seed_u"])
     lat = make_lattice(dims, U, masses=cfg["masses"], csw=cfg["csw"])

@@ -160,10 +160,10 @@ def test_make_sources(ragged):
 # solves
 # ---------------------------------------------------------------------------
 
-def test_solve_c0_dense():
-    """C0: 4^4, LapH sources of the lowest Laplacian eigenvectors, FP64 solve to 1e-12 vs dense LU."""
+def test_solve_4x4x4x4_dense():
+    """4^4, LapH sources of the lowest Laplacian eigenvectors, FP64 solve to 1e-12 vs dense LU."""
     import paper_2510_26313_amd as pl
-    cfg = ls.CONFIGS["c0"]
+    cfg = ls.CONFIGS["dense_4x4x4x4"]
     U = ls.gauge_field(cfg["dims"], cfg["seed_u"])
     V, _, _ = laph.laplacian_eigvecs(U, cfg["nev"])
     b = laph.laph_sources(V, 0)
@@ -171,7 +171,7 @@ def test_solve_c0_dense():
     x_ref = solvers.dense_solve(D, b)
     lat = make_lattice(cfg["dims"], U, masses=cfg["masses"])
     for batched in (1, 0):
-        log_case("solve_c0", batched=batched)
+        log_case("solve_4x4x4x4", batched=batched)
         X, st = lat.solve_raw(dev(b), 0, 1e-12, pl.default_params(inner_prec="f64", batched=batched))
         e = per_rhs_rel(host(X), x_ref)
         assert e.max() < 1e-10, e.max()
@@ -326,9 +326,9 @@ def test_solve_x0_warm_start(ragged, ragged_ref):
 # perambulators
 # ---------------------------------------------------------------------------
 
-def test_perambulator_c0():
+def test_perambulator_4x4x4x4():
     import paper_2510_26313_amd as pl
-    cfg = ls.CONFIGS["c0"]
+    cfg = ls.CONFIGS["dense_4x4x4x4"]
     U = ls.gauge_field(cfg["dims"], cfg["seed_u"])
     V, _, _ = laph.laplacian_eigvecs(U, cfg["nev"])
     tau_ref, _ = laph.perambulator(U, V, 0, cfg["masses"][0], method="dense")

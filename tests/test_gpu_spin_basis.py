@@ -1,5 +1,5 @@
 """GPU spin-basis rotation of perambulators against the oracle: random blocks (also in
-place), and the C0 perambulator in the Dirac-Pauli basis."""
+place), and the 4^4 perambulator in the Dirac-Pauli basis."""
 import numpy as np
 import pytest
 
@@ -32,7 +32,7 @@ def test_spin_rotate_random_blocks():
 
 def test_perambulator_dirac_pauli_c0():
     import paper_2510_26313_amd as pl
-    cfg = ls.CONFIGS["c0"]
+    cfg = ls.CONFIGS["dense_4x4x4x4"]
     U = ls.gauge_field(cfg["dims"], cfg["seed_u"])
     V, _, _ = laph.laplacian_eigvecs(U, cfg["nev"])
     tau_ref, _ = laph.perambulator(U, V, 0, cfg["masses"][0], method="dense")

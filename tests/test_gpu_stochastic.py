@@ -1,7 +1,7 @@
 """GPU stochastic LapH (noise-diluted sources), against the oracle.
 
 * the diluted noise sources against the oracle's, on a ragged lattice;
-* the fused stochastic perambulator at C0 (4^4, Laplacian eigenvectors, Z4 noise,
+* the fused stochastic perambulator on 4^4 ( Laplacian eigenvectors, Z4 noise,
   3 interlaced groups) against the oracle's dense-inverse result, FP64 and FP16N inner;
 * full dilution with unit noise reproduces the GPU perambulator;
 * invalid dilution raises.
@@ -39,16 +39,16 @@ def test_noise_sources_vs_oracle():
     assert np.abs(B - ref).max() <= 1e-15 * np.abs(ref).max()
 
 
-def test_stochastic_perambulator_c0():
+def test_stochastic_perambulator_4x4x4x4():
     import paper_2510_26313_amd as pl
-    cfg = ls.CONFIGS["c0"]
+    cfg = ls.CONFIGS["dense_4x4x4x4"]
     U = ls.gauge_field(cfg["dims"], cfg["seed_u"])
     V, _, _ = laph.laplacian_eigvecs(U, cfg["nev"])
     rho = _z4(cfg["nev"], 74)
     phi_ref, _ = laph.stochastic_perambulator(U, V, 1, cfg["masses"][0], rho, 3, method="dense")
     lat = make_lattice(cfg["dims"], U, masses=cfg["masses"])
     for prec in ("f64", "f16n"):
-        log_case("stochastic_perambulator_c0", prec=prec)
+        log_case("stochastic_perambulator_4x4x4x4", prec=prec)
         phi, st = lat.stochastic_perambulator_raw(dev(V), 1, dev(rho), 3, 0, 1e-12 if prec == "f64" else 1e-10,
                                                   pl.default_params(inner_prec=prec))
         assert len(st) == 12 and all(s["status"] == "converged" for s in st)

@@ -250,8 +250,8 @@ def test_perambulator_gauge_invariance():
 # ---------------------------------------------------------------------------
 
 def test_dense_inverse_c0():
-    """P1: BiCGStab on the C0 lattice and LapH sources agrees with LU of the dense 3072^2 D."""
-    cfg = ls.CONFIGS["c0"]
+    """P1: BiCGStab on the 4^4 lattice and LapH sources agrees with LU of the dense 3072^2 D."""
+    cfg = ls.CONFIGS["dense_4x4x4x4"]
     U = ls.gauge_field(cfg["dims"], cfg["seed_u"])
     V, lam, gap = laph.laplacian_eigvecs(U, cfg["nev"])
     assert gap.min() > 0
@@ -329,7 +329,7 @@ def test_free_laplacian_spectrum():
 
 def test_laplacian_eigvecs_c0():
     """Orthonormal, eigen-residual small, ascending, phase convention applied."""
-    cfg = ls.CONFIGS["c0"]
+    cfg = ls.CONFIGS["dense_4x4x4x4"]
     U = ls.gauge_field(cfg["dims"], cfg["seed_u"])
     V, lam, gap = laph.laplacian_eigvecs(U, cfg["nev"])
     lt = U.shape[0]
