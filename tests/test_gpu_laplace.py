@@ -1,6 +1,7 @@
 """GPU LapH vectors: -Delta on every timeslice and its lowest eigenpairs, against the oracle.
 
-* (-Delta) X against the oracle's stencil on a ragged lattice (1e-13);
+* (-Delta) X against the oracle's stencil on a ragged lattice and on one whose x
+  extent is a block row (1e-13);
 * the nev lowest eigenpairs against the oracle's dense eigendecomposition per
   timeslice (4^4 with nev 8, 8^3 x 4 with nev 16, a non-cubic 6x4x4x6 with an odd
   nev 5 and 4^4 with a single vector): eigenvalues within 1e-10,
@@ -44,8 +45,10 @@ def _residuals(U3, V, lam):
     return np.linalg.norm(r.reshape(V.shape[0], -1), axis=1)
 
 
-def test_apply_laplacian_vs_oracle():
-    dims = (6, 4, 4, 10)
+@pytest.mark.parametrize("dims", [(6, 4, 4, 10), (32, 8, 4, 4)])
+def test_apply_laplacian_vs_oracle(dims):
+    """(6, 4, 4, 10): blocks of 32 sites that straddle x rows; (32, 8, 4, 4): one x row
+    per block, rows visited in tiles of (y, z)."""
     U, lat = _lattice(dims, 61)
     X = _colour_fields(dims, 5, 62)
     log_case("apply_laplacian", dims=dims)
