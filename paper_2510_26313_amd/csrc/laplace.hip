@@ -68,12 +68,13 @@ __device__ __forceinline__ void site3(const Geom &g, int s, int &x, int &y, int 
 // neighbour indices, then each wave runs two vectors at a time (lanes 0-31 and
 // 32-63), so every link is read from HBM once for all vectors of the block.
 constexpr int kLapSites = 32;
-// vectors per group (grid dimension, outermost): 32 measured best at 32^3 x 64 with 96
-// vectors (4.03 s for the eigensolver, against 4.24 s with one group of all vectors,
-// 4.19 s with 16 and 4.46 s with 8: groups re-stage the links, all-vector blocks lose
-// the L2 reuse of their neighbour rows)
+// vectors per group (grid dimension, outermost): groups re-stage the links, all-vector
+// blocks lose the L2 reuse of their neighbour rows.  At 32^3 x 64 with 96 vectors and
+// rows in memory order, 32 measured best (4.03 s for an earlier eigensolver, against
+// 4.24 s with one group of all vectors, 4.19 s with 16 and 4.46 s with 8); with the
+// (y, z) row tiles below, 48 (2.81 s, against 2.88 s with 32 and 2.95 s with 96)
 #ifndef LAPH_LAP_VG
-#define LAPH_LAP_VG 32
+#define LAPH_LAP_VG 48
 #endif
 // rows of a timeslice (one row = kLapSites sites) visited in T x T tiles of (y, z)
 // when the x extent is one row (0: memory order), so the blocks in flight hold more of
