@@ -27,12 +27,13 @@ import laph_synth as ls  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
 # FP32 vector peak without packed-FP32 instructions (the build disables them):
-# 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz
 ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
-# flops per output site and RHS of a fused stage: 8 hops x 180 (projection 24,
-# two SU(3) x colour-vector products 132, spin reconstruction 24) + two Hermitian
-# 6x6 clover blocks 2 x 252
-STAGE_FLOPS_PER_SITE_RHS = 8 * 180 + 2 * 252
+# flops per output site and RHS of a fused stage, the standard counts: the Wilson
+# hop 1320 (per direction: spin projection 12, two SU(3) x colour-vector products
+# 132, reconstruction and accumulation 24; the first accumulation is a copy) and
+# two Hermitian 6x6 clover blocks 504
+STAGE_FLOPS_PER_SITE_RHS = 1320 + 504
 
 
 def stage_bytes_per_site(prec, n_rhs, stage):
@@ -48,54 +49,48 @@ def stage_bytes_per_site(prec, n_rhs, stage):
     return n_rhs * per_rhs + 8 * link + clov
 
 
-def cpu_baseline(cfg, dims, U, v_src, seconds_budget=20.0):
-    """The FP64 oracle timed on the host: full-lattice BiCGStab iterations on the
-    headline lattice for one LapH source, scaled to RHS/s with the iteration count
-    the oracle needs for 1e-10 on the same parameters (measured on 8^3 x 16).
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    One iteration costs T(2 iterations) - T(1 iteration) of the oracle's solver
-    (each call also forms the initial and the final true residual)."""
+
+def cpu_baseline(cfg, dims, U, V, t0):
+    """The FP64 oracle timed on the host: one complete perambulator column of the
+    headline workload -- the solve of one spin-diluted LapH source (k = 0, alpha = 0
+    at source time t0) by the oracle's full-lattice BiCGStab to a relative residual
+    of 1e-10, and its projection onto the LapH vectors of every sink timeslice --
+    as RHS/s.  The clover term is built before the clock starts (the GPU's timed
+    region also starts with it built)."""
     from oracle import dirac, laph as olaph, solvers
     m0, csw = cfg["masses"][0], cfg["csw"]
-    # iteration count at the same mass and gauge parameters on a small lattice
-    small = (8, 8, 8, 16)
-    Us = ls.gauge_field(small, cfg["seed_u"])
-    Vs = ls.orthonormal_laph_vectors(small, 1, cfg["seed_v"])
-    Ds = dirac.WilsonClover(Us, m0, csw)
-    _, info = solvers.bicgstab(Ds.apply, olaph.laph_sources(Vs, 0)[:1], tol=1e-10)
-    n_it = int(info["iters"][0])
-    # full-size iterations on the bench's gauge field and first LapH vector, bounded
     D = dirac.WilsonClover(U, m0, csw)
-    b = olaph.laph_sources(v_src, 0)[:1]
-    D.apply(b)  # first touch
-
-    def run(k_iters):
-        t = time.perf_counter()
-        solvers.bicgstab(D.apply, b, tol=1e-30, maxiter=k_iters, max_restarts=0)
-        return time.perf_counter() - t
-
-    t1, t2, reps = [], [], 0
-    t_start = time.perf_counter()
-    while reps < 4:
-        t1.append(run(1))
-        t2.append(run(2))
-        reps += 1
-        if time.perf_counter() - t_start > seconds_budget:
-            break
-    per_iter = max(min(t2) - min(t1), 1e-9)
-    rhs_per_s = 1.0 / (per_iter * n_it)
+    b = olaph.laph_sources(V[:, :1], t0)[:1]
+    D.apply(b)   # first touch of the clover term
+    t = time.perf_counter()
+    x, info = solvers.bicgstab(D.apply, b, tol=1e-10)
+    X4 = np.zeros((4,) + x.shape[1:], dtype=np.complex128)
+    X4[0] = x[0]
+    olaph.project(V, X4, 1)
+    dt = time.perf_counter() - t
     cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
-    return {"value": rhs_per_s, "unit": "RHS/s", "cores": cores, "kind": "oracle",
-            "sample": "1 LapH source on %s: the FP64 oracle BiCGStab run for 1 and for 2 iterations (%d times "
-                      "each); one iteration = the difference of the fastest runs (%.2f s), times the %d "
-                      "iterations the oracle needs for 1e-10 at m0=%g (measured on 8^3x16)"
-                      % ("x".join(map(str, dims)), reps, per_iter, n_it, m0)}
+    return {"value": 1.0 / dt, "unit": "RHS/s", "cores": cores, "kind": "oracle",
+            "sample": "one complete perambulator column on %s: the FP64 oracle's full-lattice BiCGStab of the "
+                      "LapH source k=0, alpha=0 at t0=%d to 1e-10 (%d iterations, %d restart(s), true residual "
+                      "%.2e) and its projection on all %d sinks, %.1f s; OpenMP threads of the oracle's hop: %d"
+                      % ("x".join(map(str, dims)), t0, int(info["iters"][0]), int(info["restarts"][0]),
+                         float(info["true_res"][0]), dims[3], dt, cores),
+            "seconds": round(dt, 2), "cpu_model": cpu_model(), "cpu_count": os.cpu_count()}
 
 
 # The stencil sources whose counters a stored traffic figure describes.
 STAGE_SOURCES = ["dslash_kernels.h", "dslash_lds.h", "laph_internal.h", "dslash_f16.hip", "dslash_f32.hip",
                  "dslash_f64.hip", "dslash.hip"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stage1_pmc_traffic.md")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def stage_source_digest():
@@ -108,20 +103,24 @@ def stage_source_digest():
 
 
 def stored_traffic(key):
-    """HBM bytes per launch of the dominant stage from the committed counter
-    summary, or None when there is none for this shape or the stencil sources
-    changed since the counters were taken."""
+    """HBM bytes per launch of a stage shape from the committed counter summaries
+    (lines ``traffic: key=... sources=... bytes_per_launch=...`` in profiles/*.md), or
+    None when there is none for this shape or the stencil sources changed since the
+    counters were taken."""
+    digest = stage_source_digest()
     try:
-        with open(TRAFFIC_FILE) as fh:
-            lines = fh.read().splitlines()
+        names = sorted(os.listdir(PROFILES))
     except OSError:
         return None
-    digest = stage_source_digest()
-    for ln in lines:
-        if ln.startswith("traffic:"):
-            f = dict(kv.split("=", 1) for kv in ln[len("traffic:"):].split())
-            if f.get("key") == key and f.get("sources") == digest:
-                return float(f["bytes_per_launch"])
+    for name in names:
+        if not name.endswith(".md"):
+            continue
+        with open(os.path.join(PROFILES, name)) as fh:
+            for ln in fh.read().splitlines():
+                if ln.startswith("traffic:"):
+                    f = dict(kv.split("=", 1) for kv in ln[len("traffic:"):].split())
+                    if f.get("key") == key and f.get("sources") == digest:
+                        return float(f["bytes_per_launch"])
     return None
 
 
@@ -298,32 +297,46 @@ def contractions_run(laph, torch, n_mom=4, reps=3):
     return out
 
 
-def stage_key(args, dims):
-    return "%s/%s/n%d/s%d/t%d/v%d" % ("x".join(map(str, dims)), args.prec, args.chunk, args.stencil,
-                                      args.rhs_tile, args.traversal)
+# Stage shapes whose counters the probe collects: the bench's dominant shape (128 RHS,
+# LDS links x16, tile sweeps) and the bandwidth-bound small batches.
+PROBE_SHAPES = [("f16n", 128, 2, 16, 2), ("f32", 1, 1, 1, 1), ("f16n", 1, 1, 1, 1), ("f16n", 2, 1, 2, 1),
+                ("f16n", 4, 1, 4, 1), ("f32", 8, 2, 8, 1), ("f16n", 8, 2, 8, 1)]
+
+
+def stage_key(dims, prec, nrhs, stencil, tile, traversal, stage):
+    return "%s/%s/n%d/s%d/t%d/v%d/stage%d" % ("x".join(map(str, dims)), prec, nrhs, stencil, tile, traversal, stage)
 
 
 def pmc_probe(args, cfg, torch, laph):
-    """Launch the dominant stage of the bench workload (shape given on the command
-    line; unit gauge, the traffic does not depend on the values) and a plain
-    copy of known size, for hardware-counter runs."""
+    """Launch the stage shapes of PROBE_SHAPES (unit gauge: the traffic does not depend
+    on the values), each stage 1 and stage 2 once to warm and three times timed, then
+    three streaming copies of 2 GiB with the library's copy kernel that calibrate the
+    byte counters, for hardware-counter runs."""
     dims = cfg["dims"]
-    if args.stencil == 0 or args.rhs_tile <= 0 or args.traversal == 0:
-        sys.exit("--pmc-probe needs an explicit --stencil, --rhs-tile and --traversal")
     lat = laph.Lattice(dims)
     lat.load_gauge(torch.from_numpy(ls.unit_gauge(dims)).cuda())
     lat.set_masses([cfg["masses"][0]], cfg["csw"])
-    ms1, ms2 = lat.time_stages(args.prec, args.chunk, args.rhs_tile, 0, reps=3, stencil=args.stencil,
-                               traversal=args.traversal)
-    print("stage key %s sources %s: stage1 %.4f ms stage2 %.4f ms (3 timed launches each, after one warm "
-          "launch)" % (stage_key(args, dims), stage_source_digest(), ms1, ms2), flush=True)
+    for prec, n, st, tile, trav in PROBE_SHAPES:
+        ms1, ms2 = lat.time_stages(prec, n, tile, 0, reps=3, stencil=st, traversal=trav)
+        print("probe %s %s sources %s: stage1 %.4f ms stage2 %.4f ms (3 timed launches each after one warm "
+              "launch)" % (stage_key(dims, prec, n, st, tile, trav, 1), stage_key(dims, prec, n, st, tile, trav, 2),
+                           stage_source_digest(), ms1, ms2), flush=True)
+        lat.release_scratch()
     x = torch.empty(2 ** 29, dtype=torch.float32, device="cuda").fill_(1.0)
     y = torch.empty_like(x)
-    torch.cuda.synchronize()
-    for _ in range(3):
-        y.copy_(x)
-    torch.cuda.synchronize()
-    print("copy: 3 x 2 GiB device-to-device", flush=True)
+    ms = lat.stream_copy(y, x, reps=2)
+    print("copy: stream_copy_kernel, 1 warm + 2 timed copies of 2 GiB, %.4f ms each" % ms, flush=True)
+
+
+def copy_peak(lat, torch, gib=4):
+    """Read + write GB/s of the library's streaming copy of a gib GiB buffer."""
+    n = (gib << 30) // 4
+    xa = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+    xb = torch.empty_like(xa)
+    ms = lat.stream_copy(xb, xa, reps=5)
+    del xa, xb
+    torch.cuda.empty_cache()
+    return 2.0 * (gib << 30) / (ms * 1e-3) / 1e9, ms
 
 
 def main():
@@ -338,7 +351,6 @@ def main():
     ap.add_argument("--stencil", type=int, default=0, help="1 register RHS tiles, 2 LDS-staged links, 0 autotuned")
     ap.add_argument("--traversal", type=int, default=0, help="1 tiles of a site block together, 2 tile sweeps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--fp64-sample", type=int, default=4, help="RHS for the plain FP64 single-RHS comparison")
     ap.add_argument("--extra", action="store_true",
                     help="also measure the 16^3x32 single-RHS, 24^3x48 four-mass and gradient workloads")
@@ -349,8 +361,8 @@ def main():
                     help="only compute meson doublets and baryon triplets of 64 vectors on 32^3x64 for 4 "
                          "momenta and print their timing as one JSON line")
     ap.add_argument("--pmc-probe", action="store_true",
-                    help="only launch the dominant stage (and a 2 GiB copy for the counter scale), for "
-                         "rocprofv3 --pmc runs; needs --stencil, --rhs-tile and --traversal")
+                    help="only launch the stage shapes whose counters are kept (and a 2 GiB copy for the "
+                         "counter scale), for rocprofv3 --pmc runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the perambulator path is measured on one MI355X "
@@ -383,10 +395,8 @@ def main():
     lat.load_gauge(torch.from_numpy(U).cuda())
     lat.set_masses([m0], cfg["csw"])
     Vd = torch.from_numpy(V).cuda()
-    v_src = np.ascontiguousarray(V[:, :1])
-    del V
     if args.no_cpu_baseline:
-        del U
+        del U, V
     tuned = None
     if args.stencil == 0 or args.rhs_tile <= 0:
         # the library's autotuner picks the stencil form and RHS per link load for this batch
@@ -445,52 +455,46 @@ def main():
     ms1, ms2 = lat.time_stages(args.prec, args.chunk, args.rhs_tile, 0, reps=20, stencil=args.stencil,
                                traversal=args.traversal)
     vh = int(np.prod(dims)) // 2
-    b1 = stage_bytes_per_site(args.prec, args.chunk, 1) * vh
-    gbs1 = b1 / (ms1 * 1e-3) / 1e9
-    fl1 = STAGE_FLOPS_PER_SITE_RHS * args.chunk * vh
-    tfl1 = fl1 / (ms1 * 1e-3) / 1e12
+    shape = (args.prec, args.chunk, args.stencil, args.rhs_tile, args.traversal)
+    copy_gbs, copy_ms = copy_peak(lat, torch)
+
+    def stage_figures(ms, stage, sh):
+        prec, n = sh[0], sh[1]
+        b = stage_bytes_per_site(prec, n, stage) * vh
+        fl = STAGE_FLOPS_PER_SITE_RHS * n * vh
+        gbs, tfl = b / (ms * 1e-3) / 1e9, fl / (ms * 1e-3) / 1e12
+        tb = stored_traffic(stage_key(dims, *sh, stage))
+        f = {"ms_per_launch": round(ms, 4), "algorithmic_bytes": b, "hbm_gbs": round(gbs, 1),
+             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "of_copy": round(gbs / copy_gbs, 4), "tflops": round(tfl, 3),
+             "alu_frac": round(tfl / ALU_PEAK_TFLOPS, 4), "counter_bytes": tb,
+             "counter_gbs": round(tb / (ms * 1e-3) / 1e9, 1) if tb else None}
+        return f, gbs, tfl, tb
+
+    f1, gbs1, tfl1, tb1 = stage_figures(ms1, 1, shape)
+    f2, _, _, _ = stage_figures(ms2, 2, shape)
     if tfl1 / ALU_PEAK_TFLOPS >= gbs1 / HBM_PEAK_GBS:
         roofline = {"bound": "alu", "achieved": round(tfl1, 3), "peak": round(ALU_PEAK_TFLOPS, 1),
-                    "unit": "TFLOP/s", "frac": round(tfl1 / ALU_PEAK_TFLOPS, 4), "traffic": None}
+                    "unit": "TFLOP/s", "frac": round(tfl1 / ALU_PEAK_TFLOPS, 4), "traffic": tb1}
     else:
         roofline = {"bound": "hbm", "achieved": round(gbs1, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(gbs1 / HBM_PEAK_GBS, 4), "traffic": None}
-    tb = stored_traffic(stage_key(args, dims))
-    roofline["traffic"] = tb
+                    "frac": round(gbs1 / HBM_PEAK_GBS, 4), "traffic": tb1}
     # the chip's FP32 vector figure counts packed FP32 FMAs, which this build does not emit
     roofline["peak_fp32_packed"] = 157.3
     roofline["frac_of_packed_peak"] = round(tfl1 / 157.3, 4)
     roofline.update({"kernel": "%s (stage 1: A_oo^-1 H_oe, %s, %d RHS per link load, %d RHS)"
                                % ("stage_lds_kernel" if args.stencil == 2 else "stage_kernel", args.prec,
                                   args.rhs_tile, args.chunk),
-                     "ms_per_launch": round(ms1, 4), "algorithmic_bytes": b1, "hbm_gbs": round(gbs1, 1),
-                     "hbm_frac": round(gbs1 / HBM_PEAK_GBS, 4), "tflops": round(tfl1, 3),
-                     "stage2_ms_per_launch": round(ms2, 4)})
+                     "flops_per_site_rhs": STAGE_FLOPS_PER_SITE_RHS, "stage1": f1, "stage2": f2,
+                     "stage2_alu_frac": f2["alu_frac"],
+                     "copy_kernel_gbs": round(copy_gbs, 1), "copy_kernel_ms_4gib": round(copy_ms, 3)})
 
-    # a plain device-to-device copy of 2 GiB: the HBM rate a streaming kernel reaches here
-    xa = torch.empty(2 ** 29, dtype=torch.float32, device="cuda").fill_(1.0)
-    xb = torch.empty_like(xa)
-    xb.copy_(xa)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        xb.copy_(xa)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 2 * xa.numel() * 4 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del xa, xb
-    # the stencil at small batches: HBM-bound at one RHS, at the FP32 ridge by eight
-    # (algorithmic bytes and flops / time; register tiles up to 4 RHS, LDS links at 8)
-    dslash = {"copy_gbs": round(copy_gbs, 1)}
-    for prec, nrhs, st, tile in (("f32", 1, 1, 1), ("f16n", 1, 1, 1), ("f16n", 2, 1, 2), ("f16n", 4, 1, 4),
-                                 ("f32", 8, 2, 8), ("f16n", 8, 2, 8)):
-        m1, _ = lat.time_stages(prec, nrhs, tile, 0, reps=10, stencil=st, traversal=1)
-        gb = stage_bytes_per_site(prec, nrhs, 1) * vh / (m1 * 1e-3) / 1e9
-        tf = STAGE_FLOPS_PER_SITE_RHS * nrhs * vh / (m1 * 1e-3) / 1e12
-        dslash["%s_nrhs%d" % (prec, nrhs)] = {"ms": round(m1, 4), "gbs": round(gb, 1),
-                                              "hbm_frac": round(gb / HBM_PEAK_GBS, 4),
-                                              "of_copy": round(gb / copy_gbs, 4), "tflops": round(tf, 2),
-                                              "alu_frac": round(tf / ALU_PEAK_TFLOPS, 4)}
+    # the stencil at small batches: HBM-bound at one RHS, near the FP32 ridge by eight
+    # (algorithmic bytes and flops / time; counter bytes where committed for this build)
+    dslash = {"copy_kernel_gbs": round(copy_gbs, 1)}
+    for sh in PROBE_SHAPES[1:]:
+        m1, m2 = lat.time_stages(sh[0], sh[1], sh[3], 0, reps=10, stencil=sh[2], traversal=sh[4])
+        dslash["%s_nrhs%d" % (sh[0], sh[1])] = {"stage1": stage_figures(m1, 1, sh)[0],
+                                                "stage2": stage_figures(m2, 2, sh)[0]}
 
     out = {
         "metric": "perambulator RHS solved/s at rel. residual 1e-10; Dslash HBM GB/s vs peak",
@@ -515,12 +519,14 @@ def main():
                    "stage1_small_batches": dslash},
     }
     if args.extra:
-        del tau, lat, Vd
+        lat.release_scratch()
         torch.cuda.empty_cache()
         out["detail"]["extra"] = extra_suite(laph, torch)
     if not args.no_cpu_baseline:
         progress("GPU measurements done; timing the CPU oracle")
-        out["cpu_baseline"] = cpu_baseline(cfg, dims, U, v_src, args.cpu_seconds)
+        del tau, Vd
+        lat.release_scratch()
+        out["cpu_baseline"] = cpu_baseline(cfg, dims, U, V, t0s[0])
     print(json.dumps(out), flush=True)
 
 

@@ -26,7 +26,10 @@
  *    laph_perambulator synchronise that stream before returning (they return
  *    host statistics); every other call is asynchronous.
  *  - Inputs are never modified.  No call aborts or throws: each returns a
- *    laph_status and, on failure, a message readable with laph_last_error().
+ *    laph_status and, on failure, a message readable with laph_last_error();
+ *    C++ exceptions inside the library (e.g. host allocation failures) are
+ *    caught at the boundary and returned as LAPH_ERR_HOST (size queries then
+ *    return 0).
  *  - Canonical (boundary) layouts, C order, complex128 as interleaved (re, im):
  *      gauge   U  [Lt][Lz][Ly][Lx][mu=4][3][3]
  *      spinor  psi[nrhs][Lt][Lz][Ly][Lx][spin=4][colour=3]
@@ -55,7 +58,9 @@ typedef enum {
     LAPH_ERR_WORKSPACE = 3,  /* state or workspace missing or too small */
     LAPH_ERR_NOCONV = 4,     /* some RHS missed the tolerance within maxiter (X, stats still written) */
     LAPH_ERR_BREAKDOWN = 5,  /* BiCGStab broke down more often than the restart budget allows */
-    LAPH_ERR_NONFINITE = 6   /* a source or an iterate became NaN/Inf (that RHS only) */
+    LAPH_ERR_NONFINITE = 6,  /* a source or an iterate became NaN/Inf (that RHS only) */
+    LAPH_ERR_HOST = 7        /* host-side failure inside the library (out of host memory or an
+                                internal C++ exception); outputs of that call are undefined */
 } laph_status;
 
 /* Storage precision of internal fields and of the solver's inner iterations. */
@@ -112,7 +117,8 @@ laph_status laph_create(laph_ctx *out, const int dims[4], int t_antiperiodic,
                         int n_mass_max, void *hip_stream);
 laph_status laph_destroy(laph_ctx ctx);
 
-/* Message of the last failure on the calling thread (valid until the next call). */
+/* Message of the last failure on the calling thread (valid until the next failing
+ * call on that thread; a fixed buffer owned by the library, never freed). */
 const char *laph_last_error(void);
 
 /* Device bytes for the context state (gauge copies in FP64 / FP32 / FP16 and
@@ -307,6 +313,65 @@ laph_status laph_time_stages(laph_ctx ctx, int prec, int nrhs, int stencil, int 
  * lattice.  work: laph_time_stages_workspace_bytes(ctx, prec, nrhs, 16). */
 laph_status laph_autotune(laph_ctx ctx, int prec, int nrhs, int mass_idx, void *work, size_t work_bytes,
                           int *stencil_out, int *rhs_tile_out, int *traversal_out, double *ms_host);
+
+/* The autotuner's stored choice for (prec, nrhs) in this context, without timing
+ * anything: *found = 1 and the shape (stencil 1 or 2, rhs_tile, traversal 1 or 2)
+ * if the context tuned that key or read it from the LAPH_TUNE_CACHE file at
+ * creation, else *found = 0.  Cache entries are keyed by the lattice extents,
+ * the device architecture (e.g. gfx950) and a digest of the stencil sources the
+ * library was built from; entries of another architecture or build are ignored. */
+laph_status laph_tuned_choice(laph_ctx ctx, int prec, int nrhs, int *found, int *stencil_out, int *rhs_tile_out,
+                              int *traversal_out);
+
+/* One fused stage of the batched solver's even-odd operator
+ *   M_hat = 1 - 1/4 A_ee^-1 H_eo A_oo^-1 H_oe
+ * (the symmetric Schur complement of D = A - 1/2 H), run with exactly the kernels
+ * and launch shape laph_solve uses for its inner iterations (and, with
+ * prec = LAPH_F64, for its reliable updates), on internal parity-only fields of
+ * nrhs right-hand sides of the mass stored at mass_idx:
+ *   which = 1:  out_o = A_oo^-1 H_oe in_e                      (stage 1; y, w unused)
+ *   which = 2:  out_e = y_e - 1/4 A_ee^-1 H_eo in_o            (stage 2 of v = M_hat p)
+ *               dots_host[3 r + 0, 1] = <w_r, out_r>  (re, im)
+ *   which = 3:  out_e = y_e - 1/4 A_ee^-1 H_eo in_o            (stage 2 of t = M_hat s)
+ *               dots_host[3 r + 0, 1] = <out_r, y_r>, dots_host[3 r + 2] = |out_r|^2
+ * with <a, b> = sum conj(a) b over the sites and spin-colour components of one
+ * parity.  The inner products are those the solver's BiCGStab takes its scalars
+ * from: accumulated from the stage's arithmetic-precision results before they are
+ * stored, per site block in FP64 and over blocks in a fixed order.  dagger = 1
+ * replaces H by gamma5 H gamma5.  stencil (1 register RHS tiles, 2 LDS-staged
+ * links), rhs_tile (1, 2, 4 for register tiles; 4, 8, 16 for LDS links) and
+ * traversal (1 the tiles of one site block together, 2 each tile sweeps the
+ * lattice) select the launch shape as in laph_solve_params.
+ *   in, out, y, w: laph_field_bytes(ctx, prec, nrhs, 1)-byte internal fields
+ *       (RHS r at offset r * laph_field_bytes(ctx, prec, 1, 1)); out must not
+ *       alias in, y or w.
+ *   dots_host: 3 * nrhs doubles on the host (which 2, 3; may be NULL for which 1).
+ *   work: laph_apply_stage_workspace_bytes(ctx, nrhs) bytes of device memory.
+ * Synchronises the context stream when it returns dots (which 2, 3). */
+size_t laph_apply_stage_workspace_bytes(laph_ctx ctx, int nrhs);
+laph_status laph_apply_stage(laph_ctx ctx, int which, void *out, const void *in, const void *y, const void *w,
+                             int prec, int nrhs, int mass_idx, int dagger, int stencil, int rhs_tile, int traversal,
+                             double *dots_host, void *work, size_t work_bytes);
+
+/* Mass gradient of the differentiable solve.  For X = D(m0)^-1 B (nrhs RHS,
+ * canonical complex128 layout) and a real loss L(X), dD/dm0 = 1 gives
+ * dX/dm0 = -D^-1 X, so with the adjoint solutions Z = D^-dagger G (G = dL/dRe X
+ * + i dL/dIm X, solved by laph_solve with dagger = 1)
+ *   *g_host = dL/dm0 = -sum_r Re <Z_r, X_r>
+ * summed in FP64 in a fixed order (per thread, per block, then over blocks).
+ * Z, X: device arrays of nrhs full-lattice spinors; work:
+ * laph_mass_gradient_workspace_bytes(ctx) bytes of device memory (a fixed size).
+ * Synchronises the context stream. */
+size_t laph_mass_gradient_workspace_bytes(laph_ctx ctx);
+laph_status laph_mass_gradient(laph_ctx ctx, double *g_host, const double *Z, const double *X, int nrhs,
+                               void *work, size_t work_bytes);
+
+/* Measurement: copy `bytes` (a multiple of 16) from src to dst on the device with
+ * the library's streaming kernel (16-byte loads, four in flight per thread),
+ * once to warm up and then reps times; *ms_host = average ms per copy (HIP events
+ * on the context stream).  Read + written bytes / time is the HBM rate a
+ * bandwidth-bound kernel of the library can reach.  dst and src must not overlap. */
+laph_status laph_stream_copy(laph_ctx ctx, void *dst, const void *src, size_t bytes, int reps, double *ms_host);
 
 #ifdef __cplusplus
 }

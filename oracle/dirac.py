@@ -265,19 +265,22 @@ def clover_matrix_at(U, site, m0, csw):
     return clover_matrix(_patch(U, t, z, y, x), m0, csw)[1, 1, 1, 1]
 
 
-def apply_at_sites(U, psi, sites, m0, csw, antiperiodic_t=True, dagger=False):
-    """(D psi)(x) (or D^dagger) at the listed sites (t, z, y, x), straight from the
-    definition; psi has a leading RHS axis.  Returns (nrhs, nsites, 4, 3)."""
+def clover_inverse_at(U, site, m0, csw):
+    """A(x)^-1 at one site (the inverse of each chiral block of clover_matrix_at)."""
+    return clover_inverse(clover_matrix_at(U, site, m0, csw)[None])[0]
+
+
+def hop_at_sites(U, psi, sites, antiperiodic_t=True, dagger=False):
+    """(H psi)(x) (dagger: gamma5 H gamma5) at the listed sites (t, z, y, x), straight
+    from the definition, one neighbour at a time; psi has a leading RHS axis.
+    Returns (nrhs, nsites, 4, 3)."""
     lt, lz, ly, lx = U.shape[:4]
     ext = (lx, ly, lz, lt)
     sg = -1.0 if dagger else 1.0
     out = np.zeros((psi.shape[0], len(sites), 4, 3), dtype=np.complex128)
     for i, (t, z, y, x) in enumerate(sites):
         c = [x, y, z, t]
-        A = clover_matrix_at(U, (t, z, y, x), m0, csw)
-        v = psi[:, t, z, y, x].reshape(-1, 12)
-        res = (v @ A.T).reshape(-1, 4, 3)
-        hop = np.zeros_like(res)
+        hop = np.zeros((psi.shape[0], 4, 3), dtype=np.complex128)
         for mu in range(4):
             for k in (+1, -1):
                 n = list(c)
@@ -296,5 +299,17 @@ def apply_at_sites(U, psi, sites, m0, csw, antiperiodic_t=True, dagger=False):
                     spin = np.eye(4) + sg * GAMMA[mu]
                 w = eta * np.einsum("ab,rsb->rsa", link, nb)
                 hop += np.einsum("st,rta->rsa", spin, w)
-        out[:, i] = res - 0.5 * hop
+        out[:, i] = hop
+    return out
+
+
+def apply_at_sites(U, psi, sites, m0, csw, antiperiodic_t=True, dagger=False):
+    """(D psi)(x) (or D^dagger) at the listed sites (t, z, y, x), straight from the
+    definition; psi has a leading RHS axis.  Returns (nrhs, nsites, 4, 3)."""
+    hop = hop_at_sites(U, psi, sites, antiperiodic_t, dagger)
+    out = np.zeros_like(hop)
+    for i, (t, z, y, x) in enumerate(sites):
+        A = clover_matrix_at(U, (t, z, y, x), m0, csw)
+        v = psi[:, t, z, y, x].reshape(-1, 12)
+        out[:, i] = (v @ A.T).reshape(-1, 4, 3) - 0.5 * hop[:, i]
     return out

@@ -16,11 +16,12 @@ c_void_p = ctypes.c_void_p
 P = ctypes.POINTER
 
 LAPH_OK, LAPH_ERR_INVALID, LAPH_ERR_HIP, LAPH_ERR_WORKSPACE, LAPH_ERR_NOCONV, LAPH_ERR_BREAKDOWN, \
-    LAPH_ERR_NONFINITE = range(7)
+    LAPH_ERR_NONFINITE, LAPH_ERR_HOST = range(8)
 LAPH_F64, LAPH_F32, LAPH_F16N = range(3)
 PREC = {"f64": LAPH_F64, "f32": LAPH_F32, "f16n": LAPH_F16N}
 RHS_STATUS = {0: "active", 1: "converged", 2: "noconv", 3: "breakdown", 4: "nonfinite"}
-STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "HIP", 3: "WORKSPACE", 4: "NOCONV", 5: "BREAKDOWN", 6: "NONFINITE"}
+STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "HIP", 3: "WORKSPACE", 4: "NOCONV", 5: "BREAKDOWN", 6: "NONFINITE",
+                7: "HOST"}
 
 
 class SolveParams(ctypes.Structure):
@@ -78,6 +79,13 @@ _SIGS = [
                                  P(c_double)]),
     ("laph_autotune", c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_size_t, P(c_int), P(c_int), P(c_int),
                               P(c_double)]),
+    ("laph_tuned_choice", c_int, [c_void_p, c_int, c_int, P(c_int), P(c_int), P(c_int), P(c_int)]),
+    ("laph_apply_stage_workspace_bytes", c_size_t, [c_void_p, c_int]),
+    ("laph_apply_stage", c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int,
+                                 c_int, c_int, c_int, c_void_p, c_void_p, c_size_t]),
+    ("laph_mass_gradient_workspace_bytes", c_size_t, [c_void_p]),
+    ("laph_mass_gradient", c_int, [c_void_p, P(c_double), c_void_p, c_void_p, c_int, c_void_p, c_size_t]),
+    ("laph_stream_copy", c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_int, P(c_double)]),
 ]
 EXPORTED = [s[0] for s in _SIGS]
 

@@ -157,12 +157,24 @@ class Lattice:
     def field_bytes(self, prec, nrhs, parity_only=True):
         return self.lib.laph_field_bytes(self.ctx, L.PREC[prec], nrhs, int(parity_only))
 
-    def pack(self, psi, prec="f64", parity=-1):
+    def pack(self, psi, prec="f64", parity=-1, out=None, rhs_offset=0):
+        """Canonical psi -> internal layout; into RHS slots rhs_offset.. of out if given."""
         n = psi.shape[0]
         _check_tensor(psi, self.spinor_shape(n), "psi")
-        out = self._workspace(self.field_bytes(prec, n, parity >= 0))
-        L.check(self._run(self.lib.laph_pack_spinor, self.ctx, _ptr(out), _ptr(psi), L.PREC[prec], n, parity))
+        per = self.field_bytes(prec, 1, parity >= 0)
+        if out is None:
+            out = self._workspace(per * n)
+            rhs_offset = 0
+        elif out.numel() < per * (rhs_offset + n):
+            raise ValueError("out holds fewer than rhs_offset + n fields")
+        dst = ctypes.c_void_p(out.data_ptr() + per * int(rhs_offset))
+        L.check(self._run(self.lib.laph_pack_spinor, self.ctx, dst, _ptr(psi), L.PREC[prec], n, parity))
         return out
+
+    def field_slice(self, buf, prec, rhs, n=1, parity_only=True):
+        """The internal fields rhs .. rhs + n - 1 of buf (a view)."""
+        per = self.field_bytes(prec, 1, parity_only)
+        return buf[per * rhs: per * (rhs + n)]
 
     def unpack(self, buf, nrhs, prec="f64", parity=-1):
         out = torch.zeros(self.spinor_shape(nrhs), dtype=torch.complex128, device=self.device)
@@ -253,6 +265,50 @@ class Lattice:
         L.check(self._run(self.lib.laph_autotune, self.ctx, L.PREC[prec], nrhs, mass_idx, _ptr(w), w.numel(),
                           ctypes.byref(st), ctypes.byref(tile), ctypes.byref(trav), ctypes.byref(ms)))
         return dict(stencil=st.value, rhs_tile=tile.value, traversal=trav.value, ms=ms.value)
+
+    def tuned_choice(self, prec, nrhs):
+        """The stored autotuner choice for (prec, nrhs), or None (nothing is timed)."""
+        f, st, tile, trav = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        L.check(self.lib.laph_tuned_choice(self.ctx, L.PREC[prec], int(nrhs), ctypes.byref(f), ctypes.byref(st),
+                                           ctypes.byref(tile), ctypes.byref(trav)))
+        return dict(stencil=st.value, rhs_tile=tile.value, traversal=trav.value) if f.value else None
+
+    def apply_stage(self, which, buf_in, nrhs, prec="f32", y=None, w=None, mass_idx=0, dagger=False, stencil=2,
+                    rhs_tile=16, traversal=2):
+        """One fused stage of the solver's M_hat on internal parity-only fields (see
+        laph_apply_stage): which 1 -> out_o = A_oo^-1 H_oe in; 2 -> out_e = y - 1/4
+        A_ee^-1 H_eo in with <w, out>; 3 -> the same with <out, y>, |out|^2.
+        Returns (out buffer, dots numpy [nrhs][3] or None)."""
+        out = self._workspace(self.field_bytes(prec, nrhs, True))
+        ws = self._scratch(self.lib.laph_apply_stage_workspace_bytes(self.ctx, nrhs))
+        dots = np.zeros((nrhs, 3)) if which >= 2 else None
+        nullp = ctypes.c_void_p(0)
+        L.check(self._run(self.lib.laph_apply_stage, self.ctx, int(which), _ptr(out), _ptr(buf_in),
+                          _ptr(y) if y is not None else nullp, _ptr(w) if w is not None else nullp, L.PREC[prec],
+                          int(nrhs), int(mass_idx), int(bool(dagger)), int(stencil), int(rhs_tile), int(traversal),
+                          dots.ctypes.data_as(ctypes.c_void_p) if dots is not None else nullp, _ptr(ws), ws.numel()))
+        return out, dots
+
+    def mass_gradient(self, Z, X):
+        """-sum_r Re<Z_r, X_r> over canonical spinor fields (the library's FP64 reduction)."""
+        n = X.shape[0]
+        _check_tensor(X, self.spinor_shape(n), "X")
+        _check_tensor(Z, self.spinor_shape(n), "Z")
+        w = self._workspace(self.lib.laph_mass_gradient_workspace_bytes(self.ctx))
+        g = ctypes.c_double()
+        L.check(self._run(self.lib.laph_mass_gradient, self.ctx, ctypes.byref(g), _ptr(Z), _ptr(X), n, _ptr(w),
+                          w.numel()))
+        return g.value
+
+    def stream_copy(self, dst, src, reps=5):
+        """Average ms of the library's streaming copy of src into dst (device tensors)."""
+        nbytes = src.numel() * src.element_size()
+        if dst.numel() * dst.element_size() < nbytes:
+            raise ValueError("dst smaller than src")
+        ms = ctypes.c_double()
+        L.check(self._run(self.lib.laph_stream_copy, self.ctx, _ptr(dst), _ptr(src), nbytes, int(reps),
+                          ctypes.byref(ms)))
+        return ms.value
 
     def apply_laplacian(self, X):
         """(-Delta) X on every timeslice; X: complex128 [Lt][nvec][Lz][Ly][Lx][3] on the device."""
@@ -399,8 +455,8 @@ class _SolveFn(torch.autograd.Function):
         kw = dict(ctx.kw)
         kw["dagger"] = 1
         Z, _ = lat.solve_raw(gX.contiguous(), 0, ctx.tol, default_params(**kw))
-        g_m0 = -torch.sum(torch.real(torch.conj(Z) * X))
-        return None, Z, g_m0.to(torch.float64).reshape(()), None, None
+        g_m0 = torch.tensor(lat.mass_gradient(Z, X), dtype=torch.float64)
+        return None, Z, g_m0, None, None
 
 
 class _ProjectFn(torch.autograd.Function):

@@ -3,6 +3,7 @@
 Usage: python -m paper_2510_26313_amd.build [--jobs N]
 """
 import concurrent.futures
+import hashlib
 import os
 import subprocess
 import sys
@@ -12,7 +13,10 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblaph.so")
 SOURCES = ["dslash_f64.hip", "dslash_f32.hip", "dslash_f16.hip", "capi.hip", "setup.hip", "dslash.hip",
-           "blas.hip", "solver.hip", "project.hip", "tune.hip", "laplace.hip", "contract.hip"]
+           "blas.hip", "solver.hip", "project.hip", "tune.hip", "laplace.hip", "contract.hip", "reduce.hip"]
+# The autotuner's cache is keyed by a digest of the sources its choices depend on.
+STENCIL_SOURCES = ["dslash_kernels.h", "dslash_lds.h", "laph_internal.h", "dslash_f16.hip", "dslash_f32.hip",
+                   "dslash_f64.hip", "dslash.hip", "tune.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -23,9 +27,18 @@ FLAGS = [
 ]
 
 
+def stencil_digest():
+    """First 16 hex digits of the SHA-256 of the stencil sources (the autotune cache key)."""
+    h = hashlib.sha256()
+    for f in STENCIL_SOURCES:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def _compile(src):
     obj = os.path.join(OBJ, src.replace(".hip", ".o"))
-    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + FLAGS + ['-DLAPH_STENCIL_DIGEST="%s"' % stencil_digest(), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr[-8000:]))

@@ -4,23 +4,26 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <exception>
 #include <memory>
+#include <new>
 #include <string>
 
+#include "laph_reduce.h"
 #include "laph_solver.h"
 
 namespace laph {
 
-static thread_local std::string g_err;
+// The last failure message of the calling thread: a fixed buffer, so that
+// reporting an out-of-memory failure does not itself allocate.
+static thread_local char g_err[1024];
 constexpr int kIdentMax = 4096;   // identity tile table in the state buffer (standalone calls)
 
 laph_status set_error(laph_status st, const char *fmt, ...) {
-    char buf[1024];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof(buf), fmt, ap);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
     va_end(ap);
-    g_err = buf;
     return st;
 }
 
@@ -77,6 +80,26 @@ static Tiles ident_tiles(const Ctx &c, int n) {
 
 using namespace laph;
 
+// Exception barrier of the C ABI: every extern "C" body below is a
+// function-try-block whose handlers turn a C++ exception (std::bad_alloc from a
+// host container, anything else thrown inside the library) into LAPH_ERR_HOST;
+// size queries return 0.  Nothing throws across the boundary.
+#define LAPH_CATCH_STATUS                                                                          \
+    catch (const std::bad_alloc &) {                                                               \
+        return ::laph::set_error(LAPH_ERR_HOST, "out of host memory");                             \
+    }                                                                                              \
+    catch (const std::exception &e_) {                                                             \
+        return ::laph::set_error(LAPH_ERR_HOST, "internal error: %s", e_.what());                  \
+    }                                                                                              \
+    catch (...) {                                                                                  \
+        return ::laph::set_error(LAPH_ERR_HOST, "internal error (unknown exception)");             \
+    }
+#define LAPH_CATCH_SIZE                                                                            \
+    catch (...) {                                                                                  \
+        ::laph::set_error(LAPH_ERR_HOST, "host-side failure in a size query");                     \
+        return 0;                                                                                  \
+    }
+
 static laph_status check_ctx(laph_ctx h, bool need_gauge = false, bool need_clover = false) {
     if (!h) return set_error(LAPH_ERR_INVALID, "null context");
     Ctx *c = reinterpret_cast<Ctx *>(h);
@@ -107,9 +130,9 @@ void laph_default_params(laph_solve_params *p) {
     p->rhs_tile64 = 0;
 }
 
-const char *laph_last_error(void) { return g_err.c_str(); }
+const char *laph_last_error(void) { return g_err; }
 
-laph_status laph_create(laph_ctx *out, const int dims[4], int t_antiperiodic, int n_mass_max, void *hip_stream) {
+laph_status laph_create(laph_ctx *out, const int dims[4], int t_antiperiodic, int n_mass_max, void *hip_stream) try {
     if (!out || !dims) return set_error(LAPH_ERR_INVALID, "null argument");
     *out = nullptr;
     for (int i = 0; i < 4; ++i)
@@ -130,6 +153,20 @@ laph_status laph_create(laph_ctx *out, const int dims[4], int t_antiperiodic, in
     c->n_mass_max = n_mass_max;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     compute_layout(*c);
+    {
+        int d = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&d) == hipSuccess && hipGetDeviceProperties(&prop, d) == hipSuccess) {
+            size_t k = 0;
+            while (k + 1 < sizeof(c->arch) && prop.gcnArchName[k] && prop.gcnArchName[k] != ':') {
+                c->arch[k] = prop.gcnArchName[k];
+                ++k;
+            }
+            c->arch[k] = 0;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
     load_tune_cache(*c);
     for (int i = 0; i < 4; ++i) {
         hipError_t e = hipEventCreate(&c->ev[i]);
@@ -137,20 +174,20 @@ laph_status laph_create(laph_ctx *out, const int dims[4], int t_antiperiodic, in
     }
     *out = reinterpret_cast<laph_ctx>(c.release());
     return LAPH_OK;
-}
+} LAPH_CATCH_STATUS
 
-laph_status laph_destroy(laph_ctx h) {
+laph_status laph_destroy(laph_ctx h) try {
     if (!h) return LAPH_OK;
     Ctx *c = reinterpret_cast<Ctx *>(h);
     for (int i = 0; i < 4; ++i)
         if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
     delete c;
     return LAPH_OK;
-}
+} LAPH_CATCH_STATUS
 
 size_t laph_state_bytes(laph_ctx h) { return h ? C(h).state_size : 0; }
 
-laph_status laph_attach_state(laph_ctx h, void *dev, size_t bytes) {
+laph_status laph_attach_state(laph_ctx h, void *dev, size_t bytes) try {
     if (!h || !dev) return set_error(LAPH_ERR_INVALID, "null argument");
     Ctx &c = C(h);
     if (bytes < c.state_size) return set_error(LAPH_ERR_WORKSPACE, "state buffer too small: %zu < %zu", bytes, c.state_size);
@@ -175,15 +212,15 @@ laph_status laph_attach_state(laph_ctx h, void *dev, size_t bytes) {
     c.gauge_loaded = false;
     c.n_mass = 0;
     return LAPH_OK;
-}
+} LAPH_CATCH_STATUS
 
-laph_status laph_load_gauge(laph_ctx h, const double *U) {
+laph_status laph_load_gauge(laph_ctx h, const double *U) try {
     LAPH_TRY(check_ctx(h));
     if (!U) return set_error(LAPH_ERR_INVALID, "null gauge pointer");
     return load_gauge(C(h), U);
-}
+} LAPH_CATCH_STATUS
 
-laph_status laph_set_clover(laph_ctx h, double csw, int n_mass, const double *m0_host) {
+laph_status laph_set_clover(laph_ctx h, double csw, int n_mass, const double *m0_host) try {
     LAPH_TRY(check_ctx(h, true));
     Ctx &c = C(h);
     if (n_mass < 1 || n_mass > c.n_mass_max || !m0_host)
@@ -193,12 +230,12 @@ laph_status laph_set_clover(laph_ctx h, double csw, int n_mass, const double *m0
             return set_error(LAPH_ERR_INVALID, "mass %d: 4 + m0 must be positive", i);
     if (!std::isfinite(csw)) return set_error(LAPH_ERR_INVALID, "c_sw not finite");
     return build_clover(c, csw, n_mass, m0_host);
-}
+} LAPH_CATCH_STATUS
 
-size_t laph_field_bytes(laph_ctx h, int prec, int nrhs, int parity_only) {
+size_t laph_field_bytes(laph_ctx h, int prec, int nrhs, int parity_only) try {
     if (!h || !valid_prec(prec) || nrhs < 0) return 0;
     return (size_t)nrhs * (parity_only ? 1 : 2) * C(h).hv(prec);
-}
+} LAPH_CATCH_SIZE
 
 static laph_status pack_common(laph_ctx h, int prec, int nrhs, int parity) {
     LAPH_TRY(check_ctx(h));
@@ -208,7 +245,7 @@ static laph_status pack_common(laph_ctx h, int prec, int nrhs, int parity) {
     return LAPH_OK;
 }
 
-laph_status laph_pack_spinor(laph_ctx h, void *out, const double *in, int prec, int nrhs, int parity) {
+laph_status laph_pack_spinor(laph_ctx h, void *out, const double *in, int prec, int nrhs, int parity) try {
     LAPH_TRY(pack_common(h, prec, nrhs, parity));
     if (nrhs && (!out || !in)) return set_error(LAPH_ERR_INVALID, "null field pointer");
     Ctx &c = C(h);
@@ -216,9 +253,9 @@ laph_status laph_pack_spinor(laph_ctx h, void *out, const double *in, int prec, 
     o.base = reinterpret_cast<char *>(out);
     o.stride = (parity < 0 ? 2 : 1) * c.hv(prec);
     return pack_spinor(c, o, in, prec, nrhs, parity);
-}
+} LAPH_CATCH_STATUS
 
-laph_status laph_unpack_spinor(laph_ctx h, double *out, const void *in, int prec, int nrhs, int parity) {
+laph_status laph_unpack_spinor(laph_ctx h, double *out, const void *in, int prec, int nrhs, int parity) try {
     LAPH_TRY(pack_common(h, prec, nrhs, parity));
     if (nrhs && (!out || !in)) return set_error(LAPH_ERR_INVALID, "null field pointer");
     Ctx &c = C(h);
@@ -226,9 +263,9 @@ laph_status laph_unpack_spinor(laph_ctx h, double *out, const void *in, int prec
     i.base = reinterpret_cast<char *>(const_cast<void *>(in));
     i.stride = (parity < 0 ? 2 : 1) * c.hv(prec);
     return unpack_spinor(c, out, i, prec, nrhs, parity);
-}
+} LAPH_CATCH_STATUS
 
-laph_status laph_apply_dslash(laph_ctx h, void *out, const void *in, int out_parity, int prec, int nrhs, int dagger) {
+laph_status laph_apply_dslash(laph_ctx h, void *out, const void *in, int out_parity, int prec, int nrhs, int dagger) try {
     LAPH_TRY(check_ctx(h, true));
     if (!valid_prec(prec) || (out_parity != 0 && out_parity != 1) || nrhs < 0)
         return set_error(LAPH_ERR_INVALID, "bad precision, parity or nrhs");
@@ -250,10 +287,10 @@ laph_status laph_apply_dslash(laph_ctx h, void *out, const void *in, int out_par
         LAPH_TRY(launch_stage(c, s));
     }
     return LAPH_OK;
-}
+} LAPH_CATCH_STATUS
 
 laph_status laph_apply_clover(laph_ctx h, void *out, const void *in, int parity, int mass_idx, int inverse, int prec,
-                              int nrhs) {
+                              int nrhs) try {
     LAPH_TRY(check_ctx(h, true, true));
     Ctx &c = C(h);
     if (!valid_prec(prec) || (parity != 0 && parity != 1) || nrhs < 0 || mass_idx < 0 || mass_idx >= c.n_mass)
@@ -271,7 +308,7 @@ laph_status laph_apply_clover(laph_ctx h, void *out, const void *in, int parity,
     s.mass_idx = mass_idx;
     s.n = nrhs;
     return launch_clover(c, s);
-}
+} LAPH_CATCH_STATUS
 
 laph_status laph_apply_D(laph_ctx h, double *out, const double *in, int mass_idx, int nrhs, int dagger, void *work,
                          size_t work_bytes) {
@@ -335,13 +372,13 @@ static laph_status check_params(const laph_solve_params *p, double tol) {
     return LAPH_OK;
 }
 
-size_t laph_solve_workspace_bytes(laph_ctx h, int nrhs, const laph_solve_params *p) {
+size_t laph_solve_workspace_bytes(laph_ctx h, int nrhs, const laph_solve_params *p) try {
     if (!h || !p || nrhs <= 0) return 0;
     return solver_workspace_bytes(C(h), p->batched ? nrhs : 1, *p);
-}
+} LAPH_CATCH_SIZE
 
 laph_status laph_solve(laph_ctx h, double *X, const double *B, int nrhs, const int *mass_idx_host, double tol,
-                       const laph_solve_params *p, laph_rhs_stats *stats_host, void *work, size_t work_bytes) {
+                       const laph_solve_params *p, laph_rhs_stats *stats_host, void *work, size_t work_bytes) try {
     LAPH_TRY(check_ctx(h, true, true));
     LAPH_TRY(check_params(p, tol));
     Ctx &c = C(h);
@@ -381,7 +418,7 @@ laph_status laph_solve(laph_ctx h, double *X, const double *B, int nrhs, const i
     c.last_ms[2] = 0;
     if (worst != LAPH_OK) return set_error((laph_status)worst, "some right-hand sides did not converge (see stats)");
     return LAPH_OK;
-}
+} LAPH_CATCH_STATUS
 
 static int peramb_chunk(int nev, const laph_solve_params *p) {
     const int nrhs = 4 * nev;
@@ -390,12 +427,12 @@ static int peramb_chunk(int nev, const laph_solve_params *p) {
     return std::min(chunk, nrhs);
 }
 
-size_t laph_perambulator_workspace_bytes(laph_ctx h, int nev, const laph_solve_params *p) {
+size_t laph_perambulator_workspace_bytes(laph_ctx h, int nev, const laph_solve_params *p) try {
     if (!h || !p || nev <= 0) return 0;
     Ctx &c = C(h);
     const int chunk = peramb_chunk(nev, p);
     return packed_v_bytes(c, nev) + project_scratch_bytes(c, nev, chunk) + solver_workspace_bytes(c, chunk, *p);
-}
+} LAPH_CATCH_SIZE
 
 // sources -> batched solves -> projection, streamed in RHS chunks: the perambulator's
 // 4 nev sources (rho null) or 4 n_dil diluted noise sources
@@ -471,42 +508,42 @@ static laph_status peramb_run(laph_ctx h, double *tau, const double *V, int nev,
 }
 
 laph_status laph_perambulator(laph_ctx h, double *tau, const double *V, int nev, int t0, int mass_idx, double tol,
-                              const laph_solve_params *p, laph_rhs_stats *stats_host, void *work, size_t work_bytes) {
+                              const laph_solve_params *p, laph_rhs_stats *stats_host, void *work, size_t work_bytes) try {
     return peramb_run(h, tau, V, nev, t0, mass_idx, nullptr, 0, tol, p, stats_host, work, work_bytes);
-}
+} LAPH_CATCH_STATUS
 
 laph_status laph_stochastic_perambulator(laph_ctx h, double *phi, const double *V, int nev, int t0, int mass_idx,
                                          const double *rho, int n_dil, double tol, const laph_solve_params *p,
-                                         laph_rhs_stats *stats_host, void *work, size_t work_bytes) {
+                                         laph_rhs_stats *stats_host, void *work, size_t work_bytes) try {
     if (!rho) return set_error(LAPH_ERR_INVALID, "null noise");
     if (n_dil < 1 || n_dil > nev) return set_error(LAPH_ERR_INVALID, "n_dil must be in 1..nev");
     return peramb_run(h, phi, V, nev, t0, mass_idx, rho, n_dil, tol, p, stats_host, work, work_bytes);
-}
+} LAPH_CATCH_STATUS
 
-size_t laph_laplacian_workspace_bytes(laph_ctx h, int nev) {
+size_t laph_laplacian_workspace_bytes(laph_ctx h, int nev) try {
     if (!h || nev < 1 || nev > 64) return 0;
     return laplacian_eig_workspace_bytes(C(h), nev);
-}
+} LAPH_CATCH_SIZE
 
-laph_status laph_apply_laplacian(laph_ctx h, double *out, const double *in, int nvec) {
+laph_status laph_apply_laplacian(laph_ctx h, double *out, const double *in, int nvec) try {
     LAPH_TRY(check_ctx(h, true, false));
     if (!out || !in || nvec <= 0 || nvec > 65535 || out == in) return set_error(LAPH_ERR_INVALID, "bad arguments");
     return apply_neg_laplacian(C(h), out, in, nvec);
-}
+} LAPH_CATCH_STATUS
 
 laph_status laph_laplacian_eigvecs(laph_ctx h, double *V, double *lambda_host, int nev, double tol, int max_iter,
                                    int degree, void *work, size_t work_bytes, int *iters_host,
-                                   double *residual_host) {
+                                   double *residual_host) try {
     LAPH_TRY(check_ctx(h, true, false));
     if (!V || !lambda_host) return set_error(LAPH_ERR_INVALID, "null V or lambda");
     return laplacian_eigvecs(C(h), V, lambda_host, nev, tol, max_iter, degree, reinterpret_cast<char *>(work),
                              work_bytes, iters_host, residual_host);
-}
+} LAPH_CATCH_STATUS
 
-size_t laph_contract_workspace_bytes(laph_ctx h, int kind, int nev, int n_mom) {
+size_t laph_contract_workspace_bytes(laph_ctx h, int kind, int nev, int n_mom) try {
     if (!h) return 0;
     return contract_workspace_bytes(C(h), kind, nev, n_mom);
-}
+} LAPH_CATCH_SIZE
 
 static laph_status contract_entry(laph_ctx h, int kind, double *out, const double *V, int nev, int n_mom,
                                   const int *mom_host, void *work, size_t work_bytes) {
@@ -516,40 +553,40 @@ static laph_status contract_entry(laph_ctx h, int kind, double *out, const doubl
 }
 
 laph_status laph_meson_doublets(laph_ctx h, double *phi, const double *V, int nev, int n_mom, const int *mom_host,
-                                void *work, size_t work_bytes) {
+                                void *work, size_t work_bytes) try {
     return contract_entry(h, 0, phi, V, nev, n_mom, mom_host, work, work_bytes);
-}
+} LAPH_CATCH_STATUS
 
 laph_status laph_baryon_triplets(laph_ctx h, double *B, const double *V, int nev, int n_mom, const int *mom_host,
-                                 void *work, size_t work_bytes) {
+                                 void *work, size_t work_bytes) try {
     return contract_entry(h, 1, B, V, nev, n_mom, mom_host, work, work_bytes);
-}
+} LAPH_CATCH_STATUS
 
-laph_status laph_make_sources(laph_ctx h, double *B, const double *V, int nev, int t0) {
+laph_status laph_make_sources(laph_ctx h, double *B, const double *V, int nev, int t0) try {
     LAPH_TRY(check_ctx(h));
     Ctx &c = C(h);
     if (!B || !V || nev <= 0 || nev > 16383 || t0 < 0 || t0 >= c.g.lt) return set_error(LAPH_ERR_INVALID, "bad arguments");
     return make_sources_canonical(c, B, V, nev, t0);
-}
+} LAPH_CATCH_STATUS
 
 laph_status laph_make_noise_sources(laph_ctx h, double *B, const double *V, int nev, int t0, const double *rho,
-                                    int n_dil) {
+                                    int n_dil) try {
     LAPH_TRY(check_ctx(h));
     Ctx &c = C(h);
     if (!B || !V || !rho || nev <= 0 || nev > 16383 || t0 < 0 || t0 >= c.g.lt || n_dil < 1 || n_dil > nev)
         return set_error(LAPH_ERR_INVALID, "bad arguments");
     return make_sources_canonical(c, B, V, nev, t0, rho, n_dil);
-}
+} LAPH_CATCH_STATUS
 
-size_t laph_project_workspace_bytes(laph_ctx h, int nev, int nev_src) {
+size_t laph_project_workspace_bytes(laph_ctx h, int nev, int nev_src) try {
     if (!h || nev <= 0 || nev_src <= 0) return 0;
     Ctx &c = C(h);
     const int n = std::min(4 * nev_src, 128);
     return packed_v_bytes(c, nev) + project_scratch_bytes(c, nev, n) + 2 * (size_t)n * c.hv(LAPH_F64);
-}
+} LAPH_CATCH_SIZE
 
 laph_status laph_project(laph_ctx h, double *tau, const double *X, const double *V, int nev, int nev_src, void *work,
-                         size_t work_bytes) {
+                         size_t work_bytes) try {
     LAPH_TRY(check_ctx(h));
     Ctx &c = C(h);
     if (!tau || !X || !V || nev <= 0 || nev > 64 || nev_src <= 0) return set_error(LAPH_ERR_INVALID, "bad arguments");
@@ -581,19 +618,19 @@ laph_status laph_project(laph_ctx h, double *tau, const double *X, const double 
         LAPH_TRY(project(c, ps));
     }
     return LAPH_OK;
-}
+} LAPH_CATCH_STATUS
 
-laph_status laph_spin_rotate(laph_ctx h, double *out, const double *tau, long n_blocks, const double *S_host) {
+laph_status laph_spin_rotate(laph_ctx h, double *out, const double *tau, long n_blocks, const double *S_host) try {
     if (!h) return set_error(LAPH_ERR_INVALID, "null context");
     if (!out || !tau || !S_host || n_blocks < 0) return set_error(LAPH_ERR_INVALID, "bad arguments");
     return spin_rotate(C(h), out, tau, n_blocks, S_host);
-}
+} LAPH_CATCH_STATUS
 
-laph_status laph_project_adjoint(laph_ctx h, double *GX, const double *Gtau, const double *V, int nev, int nev_src) {
+laph_status laph_project_adjoint(laph_ctx h, double *GX, const double *Gtau, const double *V, int nev, int nev_src) try {
     LAPH_TRY(check_ctx(h));
     if (!GX || !Gtau || !V || nev <= 0 || nev_src <= 0 || nev_src > 16383) return set_error(LAPH_ERR_INVALID, "bad arguments");
     return project_adjoint(C(h), GX, Gtau, V, nev, nev_src);
-}
+} LAPH_CATCH_STATUS
 
 static size_t time_stages_layout(const Ctx &c, int prec, int nrhs, size_t *off_ints, size_t *off_part) {
     const size_t hv = c.hv(prec);
@@ -605,15 +642,15 @@ static size_t time_stages_layout(const Ctx &c, int prec, int nrhs, size_t *off_i
     return off;
 }
 
-size_t laph_time_stages_workspace_bytes(laph_ctx h, int prec, int nrhs, int rhs_tile) {
+size_t laph_time_stages_workspace_bytes(laph_ctx h, int prec, int nrhs, int rhs_tile) try {
     (void)rhs_tile;
     if (!h || !valid_prec(prec) || nrhs <= 0) return 0;
     size_t a, b;
     return time_stages_layout(C(h), prec, nrhs, &a, &b);
-}
+} LAPH_CATCH_SIZE
 
 laph_status laph_time_stages(laph_ctx h, int prec, int nrhs, int stencil, int rhs_tile, int traversal, int mass_idx,
-                             int reps, void *work, size_t work_bytes, double *ms_host2) {
+                             int reps, void *work, size_t work_bytes, double *ms_host2) try {
     LAPH_TRY(check_ctx(h, true, true));
     Ctx &c = C(h);
     const int form = stencil == 2 ? kFormLds : kFormRegister;
@@ -628,10 +665,10 @@ laph_status laph_time_stages(laph_ctx h, int prec, int nrhs, int stencil, int rh
     char *w = reinterpret_cast<char *>(work);
     return time_stage_pair(c, prec, nrhs, form, rhs_tile, traversal == 2 ? 1 : 0, mass_idx, reps, w,
                            reinterpret_cast<double *>(w + off_part), reinterpret_cast<int *>(w + off_ints), ms_host2);
-}
+} LAPH_CATCH_STATUS
 
 laph_status laph_autotune(laph_ctx h, int prec, int nrhs, int mass_idx, void *work, size_t work_bytes,
-                          int *stencil_out, int *rhs_tile_out, int *traversal_out, double *ms_out) {
+                          int *stencil_out, int *rhs_tile_out, int *traversal_out, double *ms_out) try {
     LAPH_TRY(check_ctx(h, true, true));
     Ctx &c = C(h);
     if (!valid_prec(prec) || nrhs <= 0 || nrhs > 65535 || mass_idx < 0 || mass_idx >= c.n_mass)
@@ -647,12 +684,138 @@ laph_status laph_autotune(laph_ctx h, int prec, int nrhs, int mass_idx, void *wo
     if (rhs_tile_out) *rhs_tile_out = sh.tile;
     if (traversal_out) *traversal_out = sh.site_major ? 2 : 1;
     return LAPH_OK;
-}
+} LAPH_CATCH_STATUS
 
-laph_status laph_last_timings(laph_ctx h, double *ms_host3) {
+laph_status laph_last_timings(laph_ctx h, double *ms_host3) try {
     if (!h || !ms_host3) return set_error(LAPH_ERR_INVALID, "null argument");
     for (int i = 0; i < 3; ++i) ms_host3[i] = C(h).last_ms[i];
     return LAPH_OK;
+} LAPH_CATCH_STATUS
+
+laph_status laph_tuned_choice(laph_ctx h, int prec, int nrhs, int *found, int *stencil_out, int *rhs_tile_out,
+                              int *traversal_out) try {
+    if (!h || !found) return set_error(LAPH_ERR_INVALID, "null argument");
+    Ctx &c = C(h);
+    auto it = c.tuned.find({prec, nrhs});
+    *found = it != c.tuned.end() ? 1 : 0;
+    if (*found) {
+        if (stencil_out) *stencil_out = it->second.form == kFormLds ? 2 : 1;
+        if (rhs_tile_out) *rhs_tile_out = it->second.tile;
+        if (traversal_out) *traversal_out = it->second.site_major ? 2 : 1;
+    }
+    return LAPH_OK;
+} LAPH_CATCH_STATUS
+
+static size_t stage_ws_layout(const Ctx &c, int nrhs, size_t *off_part, size_t *off_dots) {
+    size_t off = round256(tune_ints(nrhs) * sizeof(int));
+    if (off_part) *off_part = off;
+    off += round256((size_t)nrhs * 3 * partial_stride(c) * sizeof(double));
+    if (off_dots) *off_dots = off;
+    off += round256((size_t)nrhs * 3 * sizeof(double));
+    return off;
 }
+
+size_t laph_apply_stage_workspace_bytes(laph_ctx h, int nrhs) try {
+    if (!h || nrhs <= 0 || nrhs > 65535) return 0;
+    return stage_ws_layout(C(h), nrhs, nullptr, nullptr);
+} LAPH_CATCH_SIZE
+
+laph_status laph_apply_stage(laph_ctx h, int which, void *out, const void *in, const void *y, const void *w,
+                             int prec, int nrhs, int mass_idx, int dagger, int stencil, int rhs_tile, int traversal,
+                             double *dots_host, void *work, size_t work_bytes) try {
+    LAPH_TRY(check_ctx(h, true, true));
+    Ctx &c = C(h);
+    const int form = stencil == 2 ? kFormLds : kFormRegister;
+    const bool tile_ok = form == kFormLds ? (rhs_tile == 4 || rhs_tile == 8 || rhs_tile == 16)
+                                          : (rhs_tile == 1 || rhs_tile == 2 || rhs_tile == 4);
+    if (which < 1 || which > 3 || !valid_prec(prec) || nrhs <= 0 || nrhs > 65535 || mass_idx < 0 ||
+        mass_idx >= c.n_mass || (stencil != 1 && stencil != 2) || (traversal != 1 && traversal != 2) || !tile_ok)
+        return set_error(LAPH_ERR_INVALID, "bad stage, precision, nrhs, mass index or launch shape");
+    if (!out || !in || (which >= 2 && !y) || (which == 2 && !w) || (which >= 2 && !dots_host))
+        return set_error(LAPH_ERR_INVALID, "null field or dots pointer");
+    if (out == in || (which >= 2 && (out == y || (which == 2 && out == w))))
+        return set_error(LAPH_ERR_INVALID, "out must not alias in, y or w");
+    size_t off_part, off_dots;
+    const size_t need = stage_ws_layout(c, nrhs, &off_part, &off_dots);
+    if (!work || work_bytes < need) return set_error(LAPH_ERR_WORKSPACE, "apply_stage workspace too small: %zu < %zu", work_bytes, need);
+    char *wk = reinterpret_cast<char *>(work);
+    int *d_ints = reinterpret_cast<int *>(wk);
+    double *partials = reinterpret_cast<double *>(wk + off_part);
+    double *dots = reinterpret_cast<double *>(wk + off_dots);
+    // tile table: tile j holds RHS j * rhs_tile .. (ragged last tile padded with -1), all of mass_idx
+    const int ntiles = (nrhs + rhs_tile - 1) / rhs_tile;
+    std::vector<int> ints((size_t)ntiles * rhs_tile + ntiles + 1, -1);
+    for (int r = 0; r < nrhs; ++r) ints[r] = r;
+    for (int t = 0; t < ntiles; ++t) ints[(size_t)ntiles * rhs_tile + t] = mass_idx;
+    ints.back() = ntiles;
+    LAPH_HIP(hipMemcpyAsync(d_ints, ints.data(), ints.size() * sizeof(int), hipMemcpyHostToDevice, c.stream));
+    Tiles t;
+    t.slots = d_ints;
+    t.mass = d_ints + (size_t)ntiles * rhs_tile;
+    t.ntiles = d_ints + (size_t)ntiles * rhs_tile + ntiles;
+    t.ntiles_max = ntiles;
+    t.nr = rhs_tile;
+    const size_t hv = c.hv(prec);
+    auto op = [&](const void *p) { return Operand{reinterpret_cast<char *>(const_cast<void *>(p)), hv}; };
+    StageSpec s;
+    s.prec = prec;
+    s.form = form;
+    s.site_major = traversal == 2 ? 1 : 0;
+    s.dagger = dagger ? 1 : 0;
+    s.clover = 1;
+    s.in = op(in);
+    s.out = op(out);
+    s.tiles = t;
+    s.partials = partials;
+    s.pstride = partial_stride(c);
+    if (which == 1) {
+        s.out_parity = 1;
+    } else {
+        s.out_parity = 0;
+        s.post = 1;
+        s.y = op(y);
+        s.a = 1.0;
+        s.b = -0.25;
+        s.red = which == 2 ? 1 : 2;
+        if (which == 2) s.w = op(w);
+    }
+    // the tile table must have reached the device before the host vector goes
+    LAPH_HIP(hipStreamSynchronize(c.stream));
+    LAPH_TRY(launch_stage(c, s));
+    if (which >= 2) {
+        const int nq = which == 2 ? 2 : 3;
+        LAPH_TRY(sum_stage_partials(c, partials, s.pstride, stage_nsb(c, form), nrhs, nq, dots));
+        LAPH_HIP(hipMemcpyAsync(dots_host, dots, (size_t)nrhs * 3 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+        LAPH_HIP(hipStreamSynchronize(c.stream));
+        if (which == 2)
+            for (int r = 0; r < nrhs; ++r) dots_host[3 * r + 2] = 0.0;
+    }
+    return LAPH_OK;
+} LAPH_CATCH_STATUS
+
+size_t laph_mass_gradient_workspace_bytes(laph_ctx h) try {
+    if (!h) return 0;
+    return round256(kGradScratchDoubles * sizeof(double));
+} LAPH_CATCH_SIZE
+
+laph_status laph_mass_gradient(laph_ctx h, double *g_host, const double *Z, const double *X, int nrhs, void *work,
+                               size_t work_bytes) try {
+    if (!h) return set_error(LAPH_ERR_INVALID, "null context");
+    Ctx &c = C(h);
+    if (!g_host || !Z || !X || nrhs <= 0 || nrhs > 65535) return set_error(LAPH_ERR_INVALID, "bad arguments");
+    if (!work || work_bytes < kGradScratchDoubles * sizeof(double))
+        return set_error(LAPH_ERR_WORKSPACE, "mass_gradient workspace too small");
+    const size_t n = (size_t)nrhs * 2 * c.g.vh * 12;
+    return mass_gradient(c, g_host, Z, X, n, reinterpret_cast<double *>(work));
+} LAPH_CATCH_STATUS
+
+laph_status laph_stream_copy(laph_ctx h, void *dst, const void *src, size_t bytes, int reps, double *ms_host) try {
+    if (!h) return set_error(LAPH_ERR_INVALID, "null context");
+    if (!dst || !src || !ms_host || bytes == 0 || bytes % 16 || reps <= 0)
+        return set_error(LAPH_ERR_INVALID, "bad arguments (bytes must be a positive multiple of 16)");
+    const char *d = reinterpret_cast<const char *>(dst), *sp = reinterpret_cast<const char *>(src);
+    if (d < sp + bytes && sp < d + bytes) return set_error(LAPH_ERR_INVALID, "dst and src overlap");
+    return stream_copy(C(h), dst, src, bytes, reps, ms_host);
+} LAPH_CATCH_STATUS
 
 }  // extern "C"

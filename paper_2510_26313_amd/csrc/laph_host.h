@@ -66,6 +66,8 @@ struct Ctx {
     size_t pinned_i_len = 0;
     hipEvent_t ev[4]{};
     double last_ms[3]{};
+    // device architecture (gcnArchName up to the first ':'), the autotune cache key
+    char arch[64] = "unknown";
     // autotuned stencil shape per (inner precision, batch size)
     struct Shape {
         int form, tile, site_major;

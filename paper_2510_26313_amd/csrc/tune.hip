@@ -7,9 +7,12 @@
 // M_hat on the solver's own workspace and is timed with HIP events; the
 // fastest pair wins.  Choices live in the context for its lifetime and, when
 // the environment variable LAPH_TUNE_CACHE names a file, are appended to that
-// file and read back by later contexts.
+// file and read back by later contexts of the same lattice, device
+// architecture and stencil build.
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
+#include <string>
 #include <vector>
 
 #include "laph_solver.h"
@@ -85,19 +88,47 @@ static std::vector<Ctx::Shape> candidates(int prec, int nrhs) {
 
 static const char *cache_path() { return std::getenv("LAPH_TUNE_CACHE"); }
 
+// Digest of the stencil sources this library was built from (set by the build
+// script): a choice measured on other kernels is not reused.
+#ifndef LAPH_STENCIL_DIGEST
+#define LAPH_STENCIL_DIGEST "unversioned"
+#endif
+static const char *kCacheTag = "laph-tune-2";
+
+// Cache lines: tag arch digest Lx Ly Lz Lt prec nrhs form tile site_major ms.
+// The file is read whole; only lines of this lattice, architecture and
+// stencil build are taken (a later line of the same key wins).
 void load_tune_cache(Ctx &c) {
     const char *path = cache_path();
     if (!path) return;
-    FILE *f = std::fopen(path, "r");
+    FILE *f = std::fopen(path, "rb");
     if (!f) return;
-    int d[4], prec, ns, form, tile, sm;
-    double ms;
-    while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %lf", &d[0], &d[1], &d[2], &d[3], &prec, &ns, &form, &tile,
-                       &sm, &ms) == 10) {
+    std::string text;
+    if (std::fseek(f, 0, SEEK_END) == 0) {
+        const long n = std::ftell(f);
+        if (n > 0 && std::fseek(f, 0, SEEK_SET) == 0) {
+            text.resize((size_t)n);
+            text.resize(std::fread(&text[0], 1, (size_t)n, f));
+        }
+    }
+    std::fclose(f);
+    size_t pos = 0;
+    while (pos < text.size()) {
+        size_t eol = text.find('\n', pos);
+        if (eol == std::string::npos) eol = text.size();
+        const std::string line = text.substr(pos, eol - pos);
+        pos = eol + 1;
+        char tag[32], arch[64], digest[64];
+        int d[4], prec, ns, form, tile, sm;
+        double ms;
+        if (std::sscanf(line.c_str(), "%31s %63s %63s %d %d %d %d %d %d %d %d %d %lf", tag, arch, digest, &d[0],
+                        &d[1], &d[2], &d[3], &prec, &ns, &form, &tile, &sm, &ms) != 13)
+            continue;
+        if (std::strcmp(tag, kCacheTag) || std::strcmp(arch, c.arch) || std::strcmp(digest, LAPH_STENCIL_DIGEST))
+            continue;
         if (d[0] == c.dims[0] && d[1] == c.dims[1] && d[2] == c.dims[2] && d[3] == c.dims[3])
             c.tuned[{prec, ns}] = Ctx::Shape{form, tile, sm};
     }
-    std::fclose(f);
 }
 
 static void store_tune_cache(const Ctx &c, int prec, int ns, const Ctx::Shape &sh, double ms) {
@@ -105,8 +136,8 @@ static void store_tune_cache(const Ctx &c, int prec, int ns, const Ctx::Shape &s
     if (!path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%d %d %d %d %d %d %d %d %d %.6f\n", c.dims[0], c.dims[1], c.dims[2], c.dims[3], prec, ns,
-                 sh.form, sh.tile, sh.site_major, ms);
+    std::fprintf(f, "%s %s %s %d %d %d %d %d %d %d %d %d %.6f\n", kCacheTag, c.arch, LAPH_STENCIL_DIGEST, c.dims[0],
+                 c.dims[1], c.dims[2], c.dims[3], prec, ns, sh.form, sh.tile, sh.site_major, ms);
     std::fclose(f);
 }
 

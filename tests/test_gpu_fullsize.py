@@ -156,3 +156,79 @@ def test_single_rhs_16x16x16x32_vs_oracle(single_case, prec):
     X, st = single_case["lat"].solve_raw(dev(single_case["B"]), 0, 1e-10, pl.default_params(inner_prec=prec, batched=0))
     assert per_rhs_rel(host(X), single_case["x_ref"]).max() < 1e-8
     assert all(s["status"] == "converged" and s["true_res"] <= 1e-10 for s in st)
+
+
+def _odd_even_sites(dims, n, seed, parity):
+    lx, ly, lz, lt = dims
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        t, z, y = int(rng.integers(0, lt)), int(rng.integers(0, lz)), int(rng.integers(0, ly))
+        x = int(rng.integers(0, lx // 2)) * 2
+        x += (parity + t + z + y + x) % 2
+        out.append((t, z, y, x))
+    return out
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-6), ("f16n", 3e-3)])
+def test_stages_32x32x32x64_128rhs_sampled(prec, tol):
+    """The bench's dominant launches at full size: 128 RHS of one mass, links staged in
+    LDS with 16 RHS per link load, each tile sweeping the lattice.  Inputs are seeded
+    combinations of four random base fields (RHS r: sum_k c_rk B_k), so the oracle's
+    one-site hop and clover inverse give the expected output of any sampled (RHS, site);
+    stage 2's fused <y, out> of sampled RHS is checked against an FP64 dot of the
+    kernel's own stored output."""
+    import gc
+    import torch
+    require_gpu()
+    gc.collect()
+    torch.cuda.empty_cache()
+    cfg = ls.CONFIGS["perambulator_32x32x32x64"]
+    dims, m0, csw, n = cfg["dims"], cfg["masses"][0], cfg["csw"], 128
+    U = ls.gauge_field(dims, cfg["seed_u"])
+    lat = make_lattice(dims, U, masses=cfg["masses"], csw=csw)
+    base = ls.random_spinor(ls.spinor_shape(dims, 4), 7200)
+    rng = np.random.default_rng(7201)
+    c_in = rng.standard_normal((n, 4)) + 1j * rng.standard_normal((n, 4))
+    c_y = 0.3 * (rng.standard_normal((n, 4)) + 1j * rng.standard_normal((n, 4)))
+    base_d = dev(base).reshape(4, -1)
+    per = lat.field_bytes(prec, 1)
+    bufs = {}
+    for name, coef, parity in (("e_in", c_in, 0), ("o_in", c_in, 1), ("y", c_y, 0)):
+        buf = torch.empty(per * n, dtype=torch.uint8, device="cuda")
+        for r0 in range(0, n, 8):
+            chunk = torch.matmul(dev(coef[r0:r0 + 8]), base_d).reshape(lat.spinor_shape(8))
+            lat.pack(chunk, prec, parity=parity, out=buf, rhs_offset=r0)
+            del chunk
+        bufs[name] = buf
+    del base_d
+    kw = dict(prec=prec, stencil=2, rhs_tile=16, traversal=2)
+    log_case("32^3x64 stage 1, 128 RHS", prec=prec)
+    o1, _ = lat.apply_stage(1, bufs["e_in"], n, **kw)
+    log_case("32^3x64 stage 2, 128 RHS", prec=prec)
+    o2, d2 = lat.apply_stage(2, bufs["o_in"], n, y=bufs["y"], w=bufs["y"], **kw)
+    assert np.all(np.isfinite(d2)) and np.all(np.abs(d2[:, 0]) > 0)
+    sites1 = _odd_even_sites(dims, 12, 7202, 1)
+    sites2 = _odd_even_sites(dims, 12, 7203, 0)
+    h1 = dirac.hop_at_sites(U, base, sites1)      # [k][site][4][3]; odd sites read even neighbours only
+    h2 = dirac.hop_at_sites(U, base, sites2)
+    ai1 = [dirac.clover_inverse_at(U, s, m0, csw) for s in sites1]
+    ai2 = [dirac.clover_inverse_at(U, s, m0, csw) for s in sites2]
+    for r in (0, 15, 16, 77, 127):
+        g1 = host(lat.unpack(lat.field_slice(o1, prec, r), 1, prec, parity=1))[0]
+        g2 = host(lat.unpack(lat.field_slice(o2, prec, r), 1, prec, parity=0))[0]
+        yr = host(lat.unpack(lat.field_slice(bufs["y"], prec, r), 1, prec, parity=0))[0]
+        got1 = np.stack([g1[s] for s in sites1])
+        got2 = np.stack([g2[s] for s in sites2])
+        exp1 = np.stack([(ai1[i] @ np.tensordot(c_in[r], h1[:, i], 1).reshape(12)).reshape(4, 3)
+                         for i in range(len(sites1))])
+        ysite = np.stack([np.tensordot(c_y[r], base[:, t, z, y, x], 1) for (t, z, y, x) in sites2])
+        exp2 = np.stack([ysite[i] - 0.25 * (ai2[i] @ np.tensordot(c_in[r], h2[:, i], 1).reshape(12)).reshape(4, 3)
+                         for i in range(len(sites2))])
+        assert np.linalg.norm(got1 - exp1) < tol * np.linalg.norm(exp1), r
+        assert np.linalg.norm(got2 - exp2) < tol * np.linalg.norm(exp2), r
+        own = np.vdot(yr, g2)
+        bound = (tol if prec == "f32" else 3e-3) * np.linalg.norm(yr) * np.linalg.norm(g2)
+        assert abs(d2[r, 0] + 1j * d2[r, 1] - own) <= bound, r
+    del bufs, o1, o2
+    torch.cuda.empty_cache()

@@ -85,3 +85,22 @@ def test_perambulator_autograd_matches_fused(grad_case):
     assert np.linalg.norm(t1 - t2) <= 1e-8 * np.linalg.norm(t2)
     (tau_g[cfg["t_sink"]].abs() ** 2).sum().backward()
     assert _close(float(m0.grad), ref["grad_m0"], 1e-6)
+
+
+@pytest.mark.parametrize("dims,nrhs", [((6, 4, 4, 10), 3), ((16, 16, 16, 32), 1)])
+def test_mass_gradient_reduction_vs_fsum(dims, nrhs):
+    """The library's FP64 reduction -sum_r Re<Z_r, X_r> against an exactly rounded sum
+    (math.fsum) of the same products, on seeded random fields."""
+    import math
+    require_gpu()
+    U = ls.gauge_field(dims, 81)
+    lat = make_lattice(dims, U)
+    Z = ls.random_spinor(ls.spinor_shape(dims, nrhs), 8100)
+    X = ls.random_spinor(ls.spinor_shape(dims, nrhs), 8101)
+    log_case("mass_gradient", dims=dims, nrhs=nrhs)
+    g = lat.mass_gradient(dev(Z), dev(X))
+    terms = np.concatenate([(Z.real * X.real).ravel(), (Z.imag * X.imag).ravel()])
+    exact = -math.fsum(terms)
+    assert abs(g - exact) <= 1e-13 * math.fsum(np.abs(terms))
+    # fixed summation order: the same call gives the same bits
+    assert lat.mass_gradient(dev(Z), dev(X)) == g

@@ -187,11 +187,23 @@ def ragged_ref(ragged):
     return b, x_ref
 
 
+@pytest.fixture(scope="module")
+def f64_iters(ragged, ragged_ref):
+    """Iterations of the plain FP64 even-odd BiCGStab (no reliable updates) per RHS."""
+    import paper_2510_26313_amd as pl
+    U, lat = ragged
+    b, _ = ragged_ref
+    log_case("solve f64 reference iterations")
+    _, st = lat.solve_raw(dev(b), 1, 1e-10, pl.default_params(inner_prec="f64", batched=1, rhs_tile=1, stencil=1,
+                                                                traversal=1))
+    return [s["iters"] for s in st]
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16n"])
 @pytest.mark.parametrize("batched,tile,stencil,trav", [(1, 0, 0, 0), (1, 2, 1, 2), (1, 4, 2, 1), (1, 8, 2, 2),
                                                       (0, 1, 1, 1)])
 @pytest.mark.parametrize("graph", [1, 0])
-def test_solve_mixed_precision(ragged, ragged_ref, prec, batched, tile, stencil, trav, graph):
+def test_solve_mixed_precision(ragged, ragged_ref, f64_iters, prec, batched, tile, stencil, trav, graph):
     import paper_2510_26313_amd as pl
     U, lat = ragged
     b, x_ref = ragged_ref
@@ -202,6 +214,10 @@ def test_solve_mixed_precision(ragged, ragged_ref, prec, batched, tile, stencil,
     e = per_rhs_rel(host(X), x_ref)
     assert e.max() < 1e-8, (e.max(), st)
     assert all(s["status"] == "converged" and s["true_res"] <= 1e-10 for s in st), st
+    # an error in the inner operator would cost iterations (the FP64 reliable updates
+    # would still correct the solution): bound them by the FP64 solver's count
+    iters = [s["iters"] for s in st]
+    assert all(i <= j + 3 for i, j in zip(iters, f64_iters)), (iters, f64_iters)
     if prec != "f64":
         assert all(s["updates"] >= 2 for s in st)
 
@@ -406,3 +422,35 @@ def test_invalid_gauge_rejected():
     log_case("invalid_gauge")
     with pytest.raises(pl.LaphError):
         lat.load_gauge(dev(U))
+
+
+def test_tune_cache_reuse_and_key(tmp_path, monkeypatch):
+    """A tuned choice written to the cache is reused by a new context without timing;
+    cache lines of another architecture or stencil build are ignored; and the tuned
+    shape is no slower than the library's default shape for that batch."""
+    import paper_2510_26313_amd as pl
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("LAPH_TUNE_CACHE", str(cache))
+    dims = (16, 8, 8, 8)
+    U = ls.gauge_field(dims, 44)
+    lat = make_lattice(dims, U, masses=(0.05,))
+    assert lat.tuned_choice("f16n", 32) is None
+    log_case("autotune for the cache", dims=dims)
+    t = lat.autotune("f16n", 32, 0)
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].split()[0] == "laph-tune-2" and lines[0].split()[1].startswith("gfx")
+    lat2 = make_lattice(dims, U, masses=(0.05,))
+    assert lat2.tuned_choice("f16n", 32) == dict(stencil=t["stencil"], rhs_tile=t["rhs_tile"],
+                                                 traversal=t["traversal"])
+    # the same line with another architecture or another stencil digest is not taken
+    f = lines[0].split()
+    other = [" ".join(["laph-tune-2", "gfx000"] + f[2:]), " ".join(f[:2] + ["0000000000000000"] + f[3:])]
+    cache.write_text("\n".join(other) + "\n")
+    lat3 = make_lattice(dims, U, masses=(0.05,))
+    assert lat3.tuned_choice("f16n", 32) is None
+    # tuned vs the default shape of a 32-RHS F16N batch (LDS links, 16 RHS per load, tile-major)
+    best = lambda **kw: min(sum(lat.time_stages("f16n", 32, mass_idx=0, reps=10, **kw)) for _ in range(3))
+    log_case("tuned vs default shape")
+    tuned = best(rhs_tile=t["rhs_tile"], stencil=t["stencil"], traversal=t["traversal"])
+    default = best(rhs_tile=16, stencil=2, traversal=1)
+    assert tuned <= 1.05 * default, (tuned, default)
