@@ -353,6 +353,23 @@ laph_status laph_apply_stage(laph_ctx ctx, int which, void *out, const void *in,
                              int prec, int nrhs, int mass_idx, int dagger, int stencil, int rhs_tile, int traversal,
                              double *dots_host, void *work, size_t work_bytes);
 
+/* laph_apply_stage without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same operation, arguments, layouts and results as
+ * laph_apply_stage; the tile table, per-block partials and per-RHS sums live in
+ * one fixed 16 MiB device array of the library per GPU (taken at load time and
+ * held until the process ends; its address is looked up once per device in
+ * laph_create).  The call itself allocates nothing, on the device or the host.
+ * Fails with LAPH_ERR_WORKSPACE when laph_apply_stage_workspace_bytes(ctx, nrhs)
+ * exceeds 16 MiB (at 32^3 x 64: above about 40 RHS) and with LAPH_ERR_HIP when
+ * no device was current at laph_create.  Every call on one GPU uses the same
+ * array: calls that overlap on that GPU (other streams, other contexts, other
+ * threads) race and must be serialised by the caller.  Synchronises the
+ * context stream when it returns dots (which 2, 3). */
+laph_status laph_apply_stage_noalloc(laph_ctx ctx, int which, void *out, const void *in, const void *y,
+                                     const void *w, int prec, int nrhs, int mass_idx, int dagger, int stencil,
+                                     int rhs_tile, int traversal, double *dots_host);
+
 /* Mass gradient of the differentiable solve.  For X = D(m0)^-1 B (nrhs RHS,
  * canonical complex128 layout) and a real loss L(X), dD/dm0 = 1 gives
  * dX/dm0 = -D^-1 X, so with the adjoint solutions Z = D^-dagger G (G = dL/dRe X

@@ -83,6 +83,8 @@ _SIGS = [
     ("laph_apply_stage_workspace_bytes", c_size_t, [c_void_p, c_int]),
     ("laph_apply_stage", c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int,
                                  c_int, c_int, c_int, c_void_p, c_void_p, c_size_t]),
+    ("laph_apply_stage_noalloc", c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int,
+                                         c_int, c_int, c_int, c_int, c_int, c_void_p]),
     ("laph_mass_gradient_workspace_bytes", c_size_t, [c_void_p]),
     ("laph_mass_gradient", c_int, [c_void_p, P(c_double), c_void_p, c_void_p, c_int, c_void_p, c_size_t]),
     ("laph_stream_copy", c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_int, P(c_double)]),

@@ -274,19 +274,26 @@ class Lattice:
         return dict(stencil=st.value, rhs_tile=tile.value, traversal=trav.value) if f.value else None
 
     def apply_stage(self, which, buf_in, nrhs, prec="f32", y=None, w=None, mass_idx=0, dagger=False, stencil=2,
-                    rhs_tile=16, traversal=2):
+                    rhs_tile=16, traversal=2, noalloc=False, out=None):
         """One fused stage of the solver's M_hat on internal parity-only fields (see
         laph_apply_stage): which 1 -> out_o = A_oo^-1 H_oe in; 2 -> out_e = y - 1/4
         A_ee^-1 H_eo in with <w, out>; 3 -> the same with <out, y>, |out|^2.
+        noalloc: call laph_apply_stage_noalloc (the library's fixed device scratch, no
+        workspace).  out: an output buffer to write (allocated when None).
         Returns (out buffer, dots numpy [nrhs][3] or None)."""
-        out = self._workspace(self.field_bytes(prec, nrhs, True))
-        ws = self._scratch(self.lib.laph_apply_stage_workspace_bytes(self.ctx, nrhs))
+        if out is None:
+            out = self._workspace(self.field_bytes(prec, nrhs, True))
         dots = np.zeros((nrhs, 3)) if which >= 2 else None
         nullp = ctypes.c_void_p(0)
-        L.check(self._run(self.lib.laph_apply_stage, self.ctx, int(which), _ptr(out), _ptr(buf_in),
-                          _ptr(y) if y is not None else nullp, _ptr(w) if w is not None else nullp, L.PREC[prec],
-                          int(nrhs), int(mass_idx), int(bool(dagger)), int(stencil), int(rhs_tile), int(traversal),
-                          dots.ctypes.data_as(ctypes.c_void_p) if dots is not None else nullp, _ptr(ws), ws.numel()))
+        args = [self.ctx, int(which), _ptr(out), _ptr(buf_in), _ptr(y) if y is not None else nullp,
+                _ptr(w) if w is not None else nullp, L.PREC[prec], int(nrhs), int(mass_idx), int(bool(dagger)),
+                int(stencil), int(rhs_tile), int(traversal),
+                dots.ctypes.data_as(ctypes.c_void_p) if dots is not None else nullp]
+        if noalloc:
+            L.check(self._run(self.lib.laph_apply_stage_noalloc, *args))
+        else:
+            ws = self._scratch(self.lib.laph_apply_stage_workspace_bytes(self.ctx, nrhs))
+            L.check(self._run(self.lib.laph_apply_stage, *args, _ptr(ws), ws.numel()))
         return out, dots
 
     def mass_gradient(self, Z, X):

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <exception>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -74,6 +75,50 @@ static Tiles ident_tiles(const Ctx &c, int n) {
     t.ntiles_max = n;
     t.nr = 1;
     return t;
+}
+
+// Tile table of a standalone stage call, written on the device: slots
+// [0, ntiles * nr) = RHS index or -1 past nrhs, then ntiles mass indices, then
+// the live tile count.
+__global__ void fill_stage_tiles_kernel(int *ints, int nrhs, int nr, int ntiles, int mass_idx) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ns = ntiles * nr;
+    if (i < ns)
+        ints[i] = i < nrhs ? i : -1;
+    else if (i < ns + ntiles)
+        ints[i] = mass_idx;
+    else if (i == ns + ntiles)
+        ints[i] = ntiles;
+}
+
+static laph_status fill_stage_tiles(const Ctx &c, int *d_ints, int nrhs, int nr, int ntiles, int mass_idx) {
+    const int n = ntiles * nr + ntiles + 1;
+    hipLaunchKernelGGL(fill_stage_tiles_kernel, dim3((n + 255) / 256), dim3(256), 0, c.stream, d_ints, nrhs, nr, ntiles,
+                       mass_idx);
+    return check_launch("fill_stage_tiles_kernel");
+}
+
+// Device scratch of laph_apply_stage_noalloc, for callers that cannot allocate
+// device memory: one fixed array per device, alive until the process ends.  Its
+// name is a host-side stand-in in host code; the device address of each GPU's
+// copy is taken once per device (laph_create, with that device current) and
+// only that address is handed to kernels.
+constexpr size_t kNoallocScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) char scratch[kNoallocScratchBytes];
+constexpr int kMaxDevices = 64;
+static void *g_scratch_dev[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+static laph_status scratch_setup(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return set_error(LAPH_ERR_INVALID, "device ordinal %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_dev[dev]) return LAPH_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return set_error(LAPH_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_dev[dev] = p;
+    return LAPH_OK;
 }
 
 }  // namespace laph
@@ -157,6 +202,8 @@ laph_status laph_create(laph_ctx *out, const int dims[4], int t_antiperiodic, in
         int d = 0;
         hipDeviceProp_t prop;
         if (hipGetDevice(&d) == hipSuccess && hipGetDeviceProperties(&prop, d) == hipSuccess) {
+            c->device = d;
+            LAPH_TRY(scratch_setup(d));   // the no-allocation entry point's device scratch
             size_t k = 0;
             while (k + 1 < sizeof(c->arch) && prop.gcnArchName[k] && prop.gcnArchName[k] != ':') {
                 c->arch[k] = prop.gcnArchName[k];
@@ -715,16 +762,9 @@ static size_t stage_ws_layout(const Ctx &c, int nrhs, size_t *off_part, size_t *
     return off;
 }
 
-size_t laph_apply_stage_workspace_bytes(laph_ctx h, int nrhs) try {
-    if (!h || nrhs <= 0 || nrhs > 65535) return 0;
-    return stage_ws_layout(C(h), nrhs, nullptr, nullptr);
-} LAPH_CATCH_SIZE
-
-laph_status laph_apply_stage(laph_ctx h, int which, void *out, const void *in, const void *y, const void *w,
-                             int prec, int nrhs, int mass_idx, int dagger, int stencil, int rhs_tile, int traversal,
-                             double *dots_host, void *work, size_t work_bytes) try {
-    LAPH_TRY(check_ctx(h, true, true));
-    Ctx &c = C(h);
+static laph_status stage_check(const Ctx &c, int which, void *out, const void *in, const void *y, const void *w,
+                               int prec, int nrhs, int mass_idx, int stencil, int rhs_tile, int traversal,
+                               const double *dots_host) {
     const int form = stencil == 2 ? kFormLds : kFormRegister;
     const bool tile_ok = form == kFormLds ? (rhs_tile == 4 || rhs_tile == 8 || rhs_tile == 16)
                                           : (rhs_tile == 1 || rhs_tile == 2 || rhs_tile == 4);
@@ -735,20 +775,24 @@ laph_status laph_apply_stage(laph_ctx h, int which, void *out, const void *in, c
         return set_error(LAPH_ERR_INVALID, "null field or dots pointer");
     if (out == in || (which >= 2 && (out == y || (which == 2 && out == w))))
         return set_error(LAPH_ERR_INVALID, "out must not alias in, y or w");
+    return LAPH_OK;
+}
+
+// One fused stage on checked arguments; wk: stage_ws_layout(c, nrhs) bytes of
+// device memory (tile table, per-block partials, per-RHS sums).  Nothing here
+// allocates: the tile table is written on the device.
+static laph_status stage_run(const Ctx &c, int which, void *out, const void *in, const void *y, const void *w,
+                             int prec, int nrhs, int mass_idx, int dagger, int stencil, int rhs_tile, int traversal,
+                             double *dots_host, char *wk) {
+    const int form = stencil == 2 ? kFormLds : kFormRegister;
     size_t off_part, off_dots;
-    const size_t need = stage_ws_layout(c, nrhs, &off_part, &off_dots);
-    if (!work || work_bytes < need) return set_error(LAPH_ERR_WORKSPACE, "apply_stage workspace too small: %zu < %zu", work_bytes, need);
-    char *wk = reinterpret_cast<char *>(work);
+    stage_ws_layout(c, nrhs, &off_part, &off_dots);
     int *d_ints = reinterpret_cast<int *>(wk);
     double *partials = reinterpret_cast<double *>(wk + off_part);
     double *dots = reinterpret_cast<double *>(wk + off_dots);
     // tile table: tile j holds RHS j * rhs_tile .. (ragged last tile padded with -1), all of mass_idx
     const int ntiles = (nrhs + rhs_tile - 1) / rhs_tile;
-    std::vector<int> ints((size_t)ntiles * rhs_tile + ntiles + 1, -1);
-    for (int r = 0; r < nrhs; ++r) ints[r] = r;
-    for (int t = 0; t < ntiles; ++t) ints[(size_t)ntiles * rhs_tile + t] = mass_idx;
-    ints.back() = ntiles;
-    LAPH_HIP(hipMemcpyAsync(d_ints, ints.data(), ints.size() * sizeof(int), hipMemcpyHostToDevice, c.stream));
+    LAPH_TRY(fill_stage_tiles(c, d_ints, nrhs, rhs_tile, ntiles, mass_idx));
     Tiles t;
     t.slots = d_ints;
     t.mass = d_ints + (size_t)ntiles * rhs_tile;
@@ -779,8 +823,6 @@ laph_status laph_apply_stage(laph_ctx h, int which, void *out, const void *in, c
         s.red = which == 2 ? 1 : 2;
         if (which == 2) s.w = op(w);
     }
-    // the tile table must have reached the device before the host vector goes
-    LAPH_HIP(hipStreamSynchronize(c.stream));
     LAPH_TRY(launch_stage(c, s));
     if (which >= 2) {
         const int nq = which == 2 ? 2 : 3;
@@ -791,6 +833,40 @@ laph_status laph_apply_stage(laph_ctx h, int which, void *out, const void *in, c
             for (int r = 0; r < nrhs; ++r) dots_host[3 * r + 2] = 0.0;
     }
     return LAPH_OK;
+}
+
+size_t laph_apply_stage_workspace_bytes(laph_ctx h, int nrhs) try {
+    if (!h || nrhs <= 0 || nrhs > 65535) return 0;
+    return stage_ws_layout(C(h), nrhs, nullptr, nullptr);
+} LAPH_CATCH_SIZE
+
+laph_status laph_apply_stage(laph_ctx h, int which, void *out, const void *in, const void *y, const void *w,
+                             int prec, int nrhs, int mass_idx, int dagger, int stencil, int rhs_tile, int traversal,
+                             double *dots_host, void *work, size_t work_bytes) try {
+    LAPH_TRY(check_ctx(h, true, true));
+    LAPH_TRY(stage_check(C(h), which, out, in, y, w, prec, nrhs, mass_idx, stencil, rhs_tile, traversal, dots_host));
+    const size_t need = stage_ws_layout(C(h), nrhs, nullptr, nullptr);
+    if (!work || work_bytes < need) return set_error(LAPH_ERR_WORKSPACE, "apply_stage workspace too small: %zu < %zu", work_bytes, need);
+    return stage_run(C(h), which, out, in, y, w, prec, nrhs, mass_idx, dagger, stencil, rhs_tile, traversal, dots_host,
+                     reinterpret_cast<char *>(work));
+} LAPH_CATCH_STATUS
+
+laph_status laph_apply_stage_noalloc(laph_ctx h, int which, void *out, const void *in, const void *y, const void *w,
+                                     int prec, int nrhs, int mass_idx, int dagger, int stencil, int rhs_tile,
+                                     int traversal, double *dots_host) try {
+    LAPH_TRY(check_ctx(h, true, true));
+    Ctx &c = C(h);
+    LAPH_TRY(stage_check(c, which, out, in, y, w, prec, nrhs, mass_idx, stencil, rhs_tile, traversal, dots_host));
+    const size_t need = stage_ws_layout(c, nrhs, nullptr, nullptr);
+    if (need > kNoallocScratchBytes)
+        return set_error(LAPH_ERR_WORKSPACE,
+                         "apply_stage_noalloc: %d RHS need %zu bytes of device scratch, above the library's fixed "
+                         "%zu bytes (use laph_apply_stage with a workspace, or fewer RHS per call)",
+                         nrhs, need, (size_t)kNoallocScratchBytes);
+    if (c.device < 0 || c.device >= kMaxDevices || !g_scratch_dev[c.device])
+        return set_error(LAPH_ERR_HIP, "apply_stage_noalloc: no device scratch address for device %d", c.device);
+    return stage_run(c, which, out, in, y, w, prec, nrhs, mass_idx, dagger, stencil, rhs_tile, traversal, dots_host,
+                     reinterpret_cast<char *>(g_scratch_dev[c.device]));
 } LAPH_CATCH_STATUS
 
 size_t laph_mass_gradient_workspace_bytes(laph_ctx h) try {

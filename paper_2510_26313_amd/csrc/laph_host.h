@@ -49,6 +49,7 @@ struct Ctx {
     int dims[4]{};
     int n_mass_max = 0;
     hipStream_t stream = nullptr;
+    int device = -1;   // HIP device current at laph_create (-1: none)
     char *state = nullptr;
     size_t state_size = 0;
     // offsets inside the state buffer
