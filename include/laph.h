@@ -390,6 +390,89 @@ laph_status laph_mass_gradient(laph_ctx ctx, double *g_host, const double *Z, co
  * bandwidth-bound kernel of the library can reach.  dst and src must not overlap. */
 laph_status laph_stream_copy(laph_ctx ctx, void *dst, const void *src, size_t bytes, int reps, double *ms_host);
 
+/* ---- Two-level aggregation multigrid -------------------------------------------
+ * The paper's production solver is an adaptive geometric multigrid (Sec. "QUDA";
+ * Sec. "Performance Measurement Method" names a mixed-precision multigrid solve the
+ * kernel of the computation; Sec. "Batched Linear Solves" batches it because coarse
+ * grids have little parallelism).  This is its two-level aggregation form:
+ *   - near-null vectors: the caller's nvec start fields relaxed by null_passes
+ *     inverse-iteration solves x <- D^-1 x (the library's batched FP32-inner solver
+ *     to relative residual null_tol; a pass that misses null_tol still counts);
+ *   - prolongator P: on every aggregate (a block[0] x .. x block[3] block of sites)
+ *     and chirality (spins 0,1 and 2,3, gamma5 = diag(1,1,-1,-1)) the restricted
+ *     halves of the vectors, Gram-Schmidt orthonormalised in vector order;
+ *   - coarse matrix D_c = P^dagger D P (nearest-neighbour stencil of 2 nvec x 2 nvec
+ *     complex blocks on the coarse lattice), built on the device in FP64;
+ *   - solve: flexible GCR(restart) on the full system with x, r, b in FP64 and one
+ *     multigrid cycle per iteration in FP32 (pre-smoother, coarse correction by
+ *     coarse_iters BiCGStab iterations to coarse_tol, post-smoother; the smoother is
+ *     smooth_iters minimal-residual steps on the even-odd Schur system); every
+ *     restart recomputes the residual in FP64 (a reliable update).
+ * The multigrid belongs to one mass (mass_idx of laph_set_clover) and is detached by
+ * laph_load_gauge, laph_set_clover and any failed laph_mg_setup.
+ * Coarse vectors: complex128 [n][Tc][Zc][Yc][Xc][2][nvec] (coarse extents L/block, then
+ * chirality, then vector); coarse matrix: complex128 [nc][9][2 nvec][2 nvec] with the
+ * coarse site index ((tc Zc + zc) Yc + yc) Xc + xc, direction 0 = the aggregate itself,
+ * 1 + 2 mu / 2 + 2 mu = the neighbour aggregate in +mu / -mu, row / column index
+ * chirality * nvec + vector. */
+typedef struct {
+    int nvec;            /* near-null vectors, 1..16 (2 nvec coarse components per aggregate) */
+    int block[4];        /* aggregate extents in x, y, z, t; each divides the lattice extent,
+                            their product is at most 256 */
+    int null_passes;     /* inverse-iteration passes (0: the start vectors are used as given) */
+    double null_tol;     /* relative residual of each pass's solve, in (0, 1) */
+    int smooth_iters;    /* minimal-residual steps per smoother application, >= 1 */
+    int coarse_iters;    /* coarse BiCGStab iterations per cycle at most, >= 1 */
+    double coarse_tol;   /* relative residual at which a coarse solve stops, in (0, 1) */
+    int restart;         /* GCR directions between FP64 residual recomputations, 1..16 */
+    int maxiter;         /* outer iterations at most, >= 1 */
+} laph_mg_params;
+
+/* Defaults: nvec 12, block 4 x 4 x 4 x 4, null_passes 2, null_tol 1e-2, smooth_iters 4,
+ * coarse_iters 16, coarse_tol 0.1, restart 8, maxiter 500. */
+void laph_mg_default_params(laph_mg_params *p);
+/* Bytes of the caller's multigrid buffer (basis: nvec full FP64 fields; coarse matrix)
+ * and of the setup workspace; 0 for invalid parameters. */
+size_t laph_mg_state_bytes(laph_ctx ctx, const laph_mg_params *p);
+size_t laph_mg_setup_workspace_bytes(laph_ctx ctx, const laph_mg_params *p);
+/* Build the multigrid of mass mass_idx from V0 (device, nvec canonical complex128 spinor
+ * fields, not modified) into state (device, laph_mg_state_bytes; must stay allocated
+ * while the multigrid is used).  Fails with LAPH_ERR_INVALID for a bad shape or when a
+ * vector is linearly dependent on an aggregate.  Synchronises the context stream. */
+laph_status laph_mg_setup(laph_ctx ctx, int mass_idx, const laph_mg_params *p, const double *V0, void *state,
+                          size_t state_bytes, void *work, size_t work_bytes);
+/* The basis (P's columns) as nvec canonical spinor fields; the coarse matrix (layouts above). */
+laph_status laph_mg_basis(laph_ctx ctx, double *out);
+laph_status laph_mg_coarse_matrix(laph_ctx ctx, double *out);
+/* c = P^dagger f and f = P c on n canonical spinor fields / coarse vectors; work:
+ * laph_mg_field_workspace_bytes(ctx, n) bytes of device memory. */
+size_t laph_mg_field_workspace_bytes(laph_ctx ctx, int n);
+laph_status laph_mg_restrict(laph_ctx ctx, double *c_out, const double *f, int n, void *work, size_t work_bytes);
+laph_status laph_mg_prolong(laph_ctx ctx, double *f_out, const double *c, int n, void *work, size_t work_bytes);
+/* out = D_c in on n coarse vectors (out must not alias in). */
+laph_status laph_mg_coarse_apply(laph_ctx ctx, double *out, const double *in, int n);
+/* One building block of the multigrid cycle on n inputs (for tests), with the cycle
+ * parameters of p (NULL: the setup's): what 0: out = D in computed in FP32; 1: the
+ * smoother (smooth_iters MR steps on the even-odd system, odd half reconstructed);
+ * 2: one whole cycle; 4: out = D in computed in FP64 (the reliable update's operator);
+ * these on n canonical spinor fields; 3: the coarse BiCGStab (coarse_iters iterations,
+ * stopping at coarse_tol) on n coarse vectors; 5 and 6: the normalised GCR directions
+ * z_k (5) or w_k = D z_k (6), k < restart, after maxiter iterations of the solve of
+ * D x = in, as restart x n canonical fields ([k][r]).
+ * work: laph_mg_solve_workspace_bytes(ctx, n, p) bytes.  Synchronises the stream. */
+laph_status laph_mg_component(laph_ctx ctx, int what, double *out, const double *in, int n,
+                              const laph_mg_params *p, void *work, size_t work_bytes);
+/* X = D^-1 B for nrhs canonical complex128 fields, all in one batch, to the per-RHS
+ * full-lattice FP64 relative residual tol.  p (may be NULL: the setup's values) gives
+ * the cycle parameters of this call (smooth_iters, coarse_iters, coarse_tol, restart,
+ * maxiter; its other fields are ignored).  stats_host (may be NULL): iters = GCR
+ * iterations, updates = FP64 residual recomputations, true_res at exit.  Returns
+ * LAPH_ERR_NOCONV if an RHS misses tol within maxiter (X and stats still written).
+ * work: laph_mg_solve_workspace_bytes(ctx, nrhs, p) bytes.  Synchronises the stream. */
+size_t laph_mg_solve_workspace_bytes(laph_ctx ctx, int nrhs, const laph_mg_params *p);
+laph_status laph_mg_solve(laph_ctx ctx, double *X, const double *B, int nrhs, double tol,
+                          const laph_mg_params *p, laph_rhs_stats *stats_host, void *work, size_t work_bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -138,3 +138,122 @@ def coarse_neighbour(dims, block, a, mu, k):
     co = [a % xc, (a // xc) % yc, (a // (xc * yc)) % zc, a // (xc * yc * zc)]
     co[mu] = (co[mu] + k) % ext[mu]
     return ((co[3] * zc + co[2]) * yc + co[1]) * xc + co[0]
+
+
+# ---------------------------------------------------------------------------
+# the cycle (the reading of the method's steps used by the library)
+# ---------------------------------------------------------------------------
+# The multigrid-preconditioned solve returns D^-1 b whatever the cycle does, and is
+# checked against the plain solvers.  The cycle itself is this project's reading of
+# the method (the paper names the solver class only); its pieces are pinned below by
+# identities of their own (tests/test_oracle_mg.py), not by values the paper gives.
+
+def _dot(a, b):
+    return np.sum(np.conj(a) * b)
+
+
+def smoother(D, r, iters):
+    """Approximate D^-1 r through the even-odd Schur system: b^ = A_ee^-1 (r_e + 1/2
+    H_eo A_oo^-1 r_o); `iters` minimal-residual steps on M^ e_e = b^ from e_e = 0
+    (rho <- b^ - M^ e_e, alpha = <M^ rho, rho> / |M^ rho|^2); e_o = A_oo^-1 (r_o +
+    1/2 H_oe e_e).  Returns (e, rho): the full-lattice e and the last MR residual."""
+    from .dirac import EvenOdd
+    eo = EvenOdd(D)
+    rho = eo.prepare(r)
+    e_e = np.zeros_like(r)
+    for _ in range(iters):
+        t = eo.M_hat(rho)
+        tt = _dot(t, t).real
+        a = _dot(t, rho) / tt if tt > 0 else 0.0
+        e_e = e_e + a * rho
+        rho = rho - a * t
+    return eo.reconstruct(r, e_e), rho
+
+
+def coarse_bicgstab(Dc, b, iters, tol):
+    """BiCGStab on the dense coarse matrix from x = 0, r^ = r = b, for at most `iters`
+    iterations, stopping once |r| <= tol |b| (checked after each iteration)."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    rh = b.copy()
+    p = np.zeros_like(b)
+    v = np.zeros_like(b)
+    rho = alpha = omega = 1.0
+    b2 = _dot(b, b).real
+    if not b2 > 0:
+        return x
+    for _ in range(iters):
+        rn = _dot(rh, r)
+        if rn == 0:
+            break
+        beta = (rn / rho) * (alpha / omega)
+        rho = rn
+        p = r + beta * (p - omega * v)
+        v = Dc @ p
+        sg = _dot(rh, v)
+        if sg == 0:
+            break
+        alpha = rho / sg
+        s = r - alpha * v
+        t = Dc @ s
+        tt = _dot(t, t).real
+        omega = _dot(t, s) / tt if tt > 0 else 0.0
+        x = x + alpha * p + omega * s
+        r = s - omega * t
+        if _dot(r, r).real <= tol * tol * b2:
+            break
+    return x
+
+
+def cycle(D, basis, block, Dc, r, smooth_iters, coarse_iters, coarse_tol):
+    """One two-level cycle for D e = r: pre-smoother, coarse correction of its
+    residual (restrict, coarse BiCGStab, prolong), post-smoother on what remains."""
+    from .dirac import apply_site_matrix
+    dims = D.dims
+    e1, rho = smoother(D, r, smooth_iters)
+    res = apply_site_matrix(D.A, rho)          # r - D e1: A_ee times the MR residual (odd part 0)
+    rc = restrict(basis, res[None], dims, block)[0]
+    ec = coarse_bicgstab(Dc, rc.ravel(), coarse_iters, coarse_tol).reshape(rc.shape)
+    q = prolong(basis, ec[None], dims, block)[0]
+    res2 = res - D.apply(q)
+    e3, _ = smoother(D, res2, smooth_iters)
+    return e1 + q + e3
+
+
+def gcr(D, basis, block, Dc, b, tol, smooth_iters, coarse_iters, coarse_tol, restart, maxiter, directions=False):
+    """Flexible GCR(restart) for D x = b preconditioned by one cycle per iteration,
+    from x = 0: z_k = cycle(r), w_k = D z_k, w_k and z_k made orthogonal to the
+    earlier w_j of the cycle (coefficients <w_j, w_k> of the normalised w_j, all from
+    the unmodified w_k), then x += g z_k, r -= g w_k with g = <w_k, r> / |w_k|^2 and
+    w_k, z_k normalised by |w_k|.  Every `restart` iterations, or once |r| <= tol |b| / 2,
+    the residual is recomputed as b - D x; the solve stops when that is <= tol |b| or
+    after maxiter iterations.  Returns (x, iterations), and with directions=True also
+    the normalised z and w of the last restart cycle."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    b2 = _dot(b, b).real
+    it = 0
+    while it < maxiter and _dot(r, r).real > tol * tol * b2:
+        Z, W = [], []
+        for _ in range(restart):
+            if it >= maxiter:
+                break
+            z = cycle(D, basis, block, Dc, r, smooth_iters, coarse_iters, coarse_tol)
+            w = D.apply(z)
+            betas = [_dot(wj, w) for wj in W]
+            for bj, zj, wj in zip(betas, Z, W):
+                w = w - bj * wj
+                z = z - bj * zj
+            n2 = _dot(w, w).real
+            g = _dot(w, r) / n2
+            x = x + g * z
+            r = r - g * w
+            W.append(w / np.sqrt(n2))
+            Z.append(z / np.sqrt(n2))
+            it += 1
+            if _dot(r, r).real <= 0.25 * tol * tol * b2:
+                break
+        r = b - D.apply(x)
+    if directions:
+        return x, it, Z, W
+    return x, it

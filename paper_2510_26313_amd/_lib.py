@@ -36,6 +36,12 @@ class RhsStats(ctypes.Structure):
                 ("true_res", c_double)]
 
 
+class MgParams(ctypes.Structure):
+    _fields_ = [("nvec", c_int), ("block", c_int * 4), ("null_passes", c_int), ("null_tol", c_double),
+                ("smooth_iters", c_int), ("coarse_iters", c_int), ("coarse_tol", c_double), ("restart", c_int),
+                ("maxiter", c_int)]
+
+
 # (name, restype, argtypes)
 _SIGS = [
     ("laph_default_params", None, [P(SolveParams)]),
@@ -88,6 +94,20 @@ _SIGS = [
     ("laph_mass_gradient_workspace_bytes", c_size_t, [c_void_p]),
     ("laph_mass_gradient", c_int, [c_void_p, P(c_double), c_void_p, c_void_p, c_int, c_void_p, c_size_t]),
     ("laph_stream_copy", c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_int, P(c_double)]),
+    ("laph_mg_default_params", None, [P(MgParams)]),
+    ("laph_mg_state_bytes", c_size_t, [c_void_p, P(MgParams)]),
+    ("laph_mg_setup_workspace_bytes", c_size_t, [c_void_p, P(MgParams)]),
+    ("laph_mg_setup", c_int, [c_void_p, c_int, P(MgParams), c_void_p, c_void_p, c_size_t, c_void_p, c_size_t]),
+    ("laph_mg_basis", c_int, [c_void_p, c_void_p]),
+    ("laph_mg_coarse_matrix", c_int, [c_void_p, c_void_p]),
+    ("laph_mg_field_workspace_bytes", c_size_t, [c_void_p, c_int]),
+    ("laph_mg_restrict", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_size_t]),
+    ("laph_mg_prolong", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_size_t]),
+    ("laph_mg_coarse_apply", c_int, [c_void_p, c_void_p, c_void_p, c_int]),
+    ("laph_mg_component", c_int, [c_void_p, c_int, c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_size_t]),
+    ("laph_mg_solve_workspace_bytes", c_size_t, [c_void_p, c_int, c_void_p]),
+    ("laph_mg_solve", c_int, [c_void_p, c_void_p, c_void_p, c_int, c_double, c_void_p, P(RhsStats), c_void_p,
+                              c_size_t]),
 ]
 EXPORTED = [s[0] for s in _SIGS]
 

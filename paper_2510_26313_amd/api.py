@@ -307,6 +307,131 @@ class Lattice:
                           w.numel()))
         return g.value
 
+    # -- two-level aggregation multigrid ---------------------------------------------------
+    def mg_params(self, **kw):
+        p = L.MgParams()
+        self.lib.laph_mg_default_params(ctypes.byref(p))
+        for k, v in kw.items():
+            if k == "block":
+                for i in range(4):
+                    p.block[i] = int(v[i])
+                continue
+            if not hasattr(p, k):
+                raise TypeError("unknown multigrid parameter %r" % k)
+            setattr(p, k, v)
+        return p
+
+    def mg_setup(self, V0, block, mass_idx=0, **kw):
+        """Build the multigrid of mass mass_idx from the start vectors V0 (complex128
+        [nvec][Lt][Lz][Ly][Lx][4][3] on the device); kw: the laph_mg_params fields."""
+        nvec = V0.shape[0]
+        _check_tensor(V0, (nvec,) + self.spinor_shape(1)[1:], "V0")
+        p = self.mg_params(nvec=nvec, block=block, **kw)
+        self._mg_state = None
+        nbytes = self.lib.laph_mg_state_bytes(self.ctx, ctypes.byref(p))
+        if nbytes == 0:
+            # invalid shape: let the library report why (and detach any multigrid)
+            L.check(self._run(self.lib.laph_mg_setup, self.ctx, int(mass_idx), ctypes.byref(p), _ptr(V0),
+                              ctypes.c_void_p(0), 0, ctypes.c_void_p(0), 0))
+        state = self._workspace(nbytes)
+        ws = self._scratch(self.lib.laph_mg_setup_workspace_bytes(self.ctx, ctypes.byref(p)))
+        L.check(self._run(self.lib.laph_mg_setup, self.ctx, int(mass_idx), ctypes.byref(p), _ptr(V0), _ptr(state),
+                          state.numel(), _ptr(ws), ws.numel()))
+        self._mg_state = state   # the library uses it until the next setup
+        self._mg_params = p
+        self._mg_block = tuple(int(b) for b in block)
+        return p
+
+    def mg_coarse_shape(self, n):
+        xc, yc, zc, tc = (d // b for d, b in zip(self.dims, self._mg_block))
+        return (n, tc, zc, yc, xc, 2, self._mg_params.nvec)
+
+    def mg_basis(self):
+        if getattr(self, "_mg_state", None) is None:
+            L.check(self.lib.laph_mg_basis(self.ctx, ctypes.c_void_p(0)))
+        out = torch.empty((self._mg_params.nvec,) + self.spinor_shape(1)[1:], dtype=torch.complex128,
+                          device=self.device)
+        L.check(self._run(self.lib.laph_mg_basis, self.ctx, _ptr(out)))
+        return out
+
+    def mg_coarse_matrix(self):
+        xc, yc, zc, tc = (d // b for d, b in zip(self.dims, self._mg_block))
+        m = 2 * self._mg_params.nvec
+        out = torch.empty((xc * yc * zc * tc, 9, m, m), dtype=torch.complex128, device=self.device)
+        L.check(self._run(self.lib.laph_mg_coarse_matrix, self.ctx, _ptr(out)))
+        return out
+
+    def mg_restrict(self, F):
+        n = F.shape[0]
+        _check_tensor(F, self.spinor_shape(n), "F")
+        out = torch.empty(self.mg_coarse_shape(n), dtype=torch.complex128, device=self.device)
+        ws = self._scratch(self.lib.laph_mg_field_workspace_bytes(self.ctx, n))
+        L.check(self._run(self.lib.laph_mg_restrict, self.ctx, _ptr(out), _ptr(F), n, _ptr(ws), ws.numel()))
+        return out
+
+    def mg_prolong(self, c):
+        n = c.shape[0]
+        _check_tensor(c, self.mg_coarse_shape(n), "c")
+        out = torch.empty(self.spinor_shape(n), dtype=torch.complex128, device=self.device)
+        ws = self._scratch(self.lib.laph_mg_field_workspace_bytes(self.ctx, n))
+        L.check(self._run(self.lib.laph_mg_prolong, self.ctx, _ptr(out), _ptr(c), n, _ptr(ws), ws.numel()))
+        return out
+
+    def mg_coarse_apply(self, c):
+        n = c.shape[0]
+        _check_tensor(c, self.mg_coarse_shape(n), "c")
+        out = torch.empty_like(c)
+        L.check(self._run(self.lib.laph_mg_coarse_apply, self.ctx, _ptr(out), _ptr(c), n))
+        return out
+
+    def _mg_run_params(self, kw):
+        if not kw:
+            return None
+        p = L.MgParams()
+        ctypes.memmove(ctypes.byref(p), ctypes.byref(self._mg_params), ctypes.sizeof(p))
+        for k, v in kw.items():
+            if k not in ("smooth_iters", "coarse_iters", "coarse_tol", "restart", "maxiter"):
+                raise TypeError("not a cycle parameter: %r" % k)
+            setattr(p, k, v)
+        return p
+
+    def mg_component(self, what, F, **kw):
+        """One building block of the multigrid cycle (laph_mg_component): what 0 D in FP32,
+        1 the smoother, 2 the cycle, 4 D in FP64 (spinor fields); 3 the coarse solve (coarse
+        vectors); 5, 6 the GCR directions z, w after kw['maxiter'] iterations."""
+        n = F.shape[0]
+        _check_tensor(F, self.mg_coarse_shape(n) if what == 3 else self.spinor_shape(n), "F")
+        p = self._mg_run_params(kw)
+        pp = ctypes.byref(p) if p is not None else None
+        if what in (5, 6):
+            m = (p or self._mg_params).restart
+            out = torch.empty((m,) + tuple(F.shape), dtype=torch.complex128, device=self.device)
+        else:
+            out = torch.empty_like(F)
+        ws = self._scratch(self.lib.laph_mg_solve_workspace_bytes(self.ctx, n, pp))
+        L.check(self._run(self.lib.laph_mg_component, self.ctx, int(what), _ptr(out), _ptr(F), n, pp, _ptr(ws),
+                          ws.numel()))
+        return out
+
+    def mg_solve(self, B, tol=1e-10, allow_noconv=False, **kw):
+        """X = D^-1 B by multigrid-preconditioned GCR (all RHS in one batch); kw: cycle
+        parameters of this call (smooth_iters, coarse_iters, coarse_tol, restart, maxiter).
+        Returns (X, per-RHS stats); raises LaphNoConvergence with the stats attached
+        unless allow_noconv."""
+        n = B.shape[0]
+        _check_tensor(B, self.spinor_shape(n), "B")
+        p = self._mg_run_params(kw)
+        pp = ctypes.byref(p) if p is not None else None
+        X = torch.empty_like(B)
+        stats = (L.RhsStats * n)()
+        ws = self._scratch(self.lib.laph_mg_solve_workspace_bytes(self.ctx, n, pp))
+        st = self._run(self.lib.laph_mg_solve, self.ctx, _ptr(X), _ptr(B), n, float(tol), pp, stats, _ptr(ws),
+                       ws.numel())
+        lst = _stats_list(stats, n)
+        if not (allow_noconv and st == L.LAPH_ERR_NOCONV):
+            L.check(st, lst)
+        return X, lst
+
     def stream_copy(self, dst, src, reps=5):
         """Average ms of the library's streaming copy of src into dst (device tensors)."""
         nbytes = src.numel() * src.element_size()

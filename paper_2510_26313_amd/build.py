@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblaph.so")
 SOURCES = ["dslash_f64.hip", "dslash_f32.hip", "dslash_f16.hip", "capi.hip", "setup.hip", "dslash.hip",
-           "blas.hip", "solver.hip", "project.hip", "tune.hip", "laplace.hip", "contract.hip", "reduce.hip"]
+           "blas.hip", "solver.hip", "project.hip", "tune.hip", "laplace.hip", "contract.hip", "reduce.hip", "mg.hip"]
 # The autotuner's cache is keyed by a digest of the sources its choices depend on.
 STENCIL_SOURCES = ["dslash_kernels.h", "dslash_lds.h", "laph_internal.h", "dslash_f16.hip", "dslash_f32.hip",
                    "dslash_f64.hip", "dslash.hip", "tune.hip"]

@@ -10,6 +10,7 @@
 #include <new>
 #include <string>
 
+#include "laph_mg.h"
 #include "laph_reduce.h"
 #include "laph_solver.h"
 
@@ -264,6 +265,7 @@ laph_status laph_attach_state(laph_ctx h, void *dev, size_t bytes) try {
 laph_status laph_load_gauge(laph_ctx h, const double *U) try {
     LAPH_TRY(check_ctx(h));
     if (!U) return set_error(LAPH_ERR_INVALID, "null gauge pointer");
+    C(h).mgs.ready = false;   // an attached multigrid was built on the previous field
     return load_gauge(C(h), U);
 } LAPH_CATCH_STATUS
 
@@ -276,6 +278,7 @@ laph_status laph_set_clover(laph_ctx h, double csw, int n_mass, const double *m0
         if (!std::isfinite(m0_host[i]) || 4.0 + m0_host[i] <= 0)
             return set_error(LAPH_ERR_INVALID, "mass %d: 4 + m0 must be positive", i);
     if (!std::isfinite(csw)) return set_error(LAPH_ERR_INVALID, "c_sw not finite");
+    c.mgs.ready = false;   // an attached multigrid was built on the previous clover term
     return build_clover(c, csw, n_mass, m0_host);
 } LAPH_CATCH_STATUS
 
@@ -892,6 +895,154 @@ laph_status laph_stream_copy(laph_ctx h, void *dst, const void *src, size_t byte
     const char *d = reinterpret_cast<const char *>(dst), *sp = reinterpret_cast<const char *>(src);
     if (d < sp + bytes && sp < d + bytes) return set_error(LAPH_ERR_INVALID, "dst and src overlap");
     return stream_copy(C(h), dst, src, bytes, reps, ms_host);
+} LAPH_CATCH_STATUS
+
+// ---- two-level aggregation multigrid ----------------------------------------------
+
+void laph_mg_default_params(laph_mg_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->nvec = 12;
+    for (int i = 0; i < 4; ++i) p->block[i] = 4;
+    p->null_passes = 2;
+    p->null_tol = 1e-2;
+    p->smooth_iters = 4;
+    p->coarse_iters = 16;
+    p->coarse_tol = 0.1;
+    p->restart = 8;
+    p->maxiter = 500;
+}
+
+static laph_status mg_params_geo(const Ctx &c, const laph_mg_params *p, MgGeom &g) {
+    if (!p) return set_error(LAPH_ERR_INVALID, "null multigrid parameters");
+    if (p->null_passes < 0 || (p->null_passes > 0 && !(p->null_tol > 0 && p->null_tol < 1)) || p->smooth_iters < 1 ||
+        p->coarse_iters < 1 || !(p->coarse_tol > 0 && p->coarse_tol < 1) || p->restart < 1 ||
+        p->restart > kMgMaxRestart || p->maxiter < 1)
+        return set_error(LAPH_ERR_INVALID, "bad multigrid parameters");
+    return mg_geometry(c, p->nvec, p->block, g);
+}
+
+size_t laph_mg_state_bytes(laph_ctx h, const laph_mg_params *p) try {
+    if (!h) return 0;
+    MgGeom g;
+    if (mg_params_geo(C(h), p, g) != LAPH_OK) return 0;
+    return mg_state_bytes(C(h), g);
+} LAPH_CATCH_SIZE
+
+size_t laph_mg_setup_workspace_bytes(laph_ctx h, const laph_mg_params *p) try {
+    if (!h) return 0;
+    MgGeom g;
+    if (mg_params_geo(C(h), p, g) != LAPH_OK) return 0;
+    return mg_setup_workspace_bytes(C(h), g, p->null_passes);
+} LAPH_CATCH_SIZE
+
+laph_status laph_mg_setup(laph_ctx h, int mass_idx, const laph_mg_params *p, const double *V0, void *state,
+                          size_t state_bytes, void *work, size_t work_bytes) try {
+    LAPH_TRY(check_ctx(h, true, true));
+    Ctx &c = C(h);
+    c.mgs.ready = false;   // whatever was attached is gone, also when this call fails
+    MgGeom g;
+    LAPH_TRY(mg_params_geo(c, p, g));
+    if (!V0 || !state) return set_error(LAPH_ERR_INVALID, "null start vectors or multigrid buffer");
+    if (!work && p->null_passes > 0) return set_error(LAPH_ERR_WORKSPACE, "multigrid setup needs a workspace");
+    LAPH_TRY(mg_setup(c, mass_idx, g, V0, p->null_passes, p->null_tol, reinterpret_cast<char *>(state), state_bytes,
+                      reinterpret_cast<char *>(work), work ? work_bytes : 0));
+    c.mgs.smooth_iters = p->smooth_iters;
+    c.mgs.coarse_iters = p->coarse_iters;
+    c.mgs.coarse_tol = p->coarse_tol;
+    c.mgs.restart = p->restart;
+    c.mgs.maxiter = p->maxiter;
+    return LAPH_OK;
+} LAPH_CATCH_STATUS
+
+laph_status laph_mg_basis(laph_ctx h, double *out) try {
+    LAPH_TRY(check_ctx(h));
+    if (!out) return set_error(LAPH_ERR_INVALID, "null output");
+    return mg_basis_canonical(C(h), out);
+} LAPH_CATCH_STATUS
+
+laph_status laph_mg_coarse_matrix(laph_ctx h, double *out) try {
+    LAPH_TRY(check_ctx(h));
+    Ctx &c = C(h);
+    if (!out) return set_error(LAPH_ERR_INVALID, "null output");
+    if (!c.mgs.ready) return set_error(LAPH_ERR_INVALID, "no multigrid set up (laph_mg_setup)");
+    const MgGeom &g = c.mgs.geo;
+    LAPH_HIP(hipMemcpyAsync(out, c.mgs.coarse, (size_t)g.nc * 9 * g.ncv * g.ncv * 16, hipMemcpyDeviceToDevice,
+                            c.stream));
+    return LAPH_OK;
+} LAPH_CATCH_STATUS
+
+size_t laph_mg_field_workspace_bytes(laph_ctx h, int n) try {
+    if (!h || n <= 0) return 0;
+    return (size_t)n * 2 * C(h).hv(LAPH_F64);
+} LAPH_CATCH_SIZE
+
+laph_status laph_mg_restrict(laph_ctx h, double *cvec, const double *f, int n, void *work, size_t work_bytes) try {
+    LAPH_TRY(check_ctx(h));
+    Ctx &c = C(h);
+    if (!cvec || !f || n <= 0 || n > 65535) return set_error(LAPH_ERR_INVALID, "bad arguments");
+    if (!work || work_bytes < (size_t)n * 2 * c.hv(LAPH_F64)) return set_error(LAPH_ERR_WORKSPACE, "workspace too small");
+    return mg_restrict_canonical(c, cvec, f, n, reinterpret_cast<char *>(work));
+} LAPH_CATCH_STATUS
+
+laph_status laph_mg_prolong(laph_ctx h, double *f, const double *cvec, int n, void *work, size_t work_bytes) try {
+    LAPH_TRY(check_ctx(h));
+    Ctx &c = C(h);
+    if (!cvec || !f || n <= 0 || n > 65535) return set_error(LAPH_ERR_INVALID, "bad arguments");
+    if (!work || work_bytes < (size_t)n * 2 * c.hv(LAPH_F64)) return set_error(LAPH_ERR_WORKSPACE, "workspace too small");
+    return mg_prolong_canonical(c, f, cvec, n, reinterpret_cast<char *>(work));
+} LAPH_CATCH_STATUS
+
+laph_status laph_mg_coarse_apply(laph_ctx h, double *out, const double *in, int n) try {
+    LAPH_TRY(check_ctx(h));
+    if (!out || !in || n <= 0 || n > 65535 || out == in) return set_error(LAPH_ERR_INVALID, "bad arguments");
+    return mg_coarse_apply(C(h), out, in, n);
+} LAPH_CATCH_STATUS
+
+// the attached multigrid with the cycle parameters of p (NULL: those of the setup)
+static laph_status mg_run_params(const Ctx &c, const laph_mg_params *p, MgState &run) {
+    run = c.mgs;
+    if (!p) return LAPH_OK;
+    if (p->smooth_iters < 1 || p->coarse_iters < 1 || !(p->coarse_tol > 0 && p->coarse_tol < 1) || p->restart < 1 ||
+        p->restart > kMgMaxRestart || p->maxiter < 1)
+        return set_error(LAPH_ERR_INVALID, "bad multigrid cycle parameters");
+    run.smooth_iters = p->smooth_iters;
+    run.coarse_iters = p->coarse_iters;
+    run.coarse_tol = p->coarse_tol;
+    run.restart = p->restart;
+    run.maxiter = p->maxiter;
+    return LAPH_OK;
+}
+
+laph_status laph_mg_component(laph_ctx h, int what, double *out, const double *in, int n, const laph_mg_params *p,
+                              void *work, size_t work_bytes) try {
+    LAPH_TRY(check_ctx(h, true, true));
+    if (!out || !in || n <= 0 || n > 65535 || out == in) return set_error(LAPH_ERR_INVALID, "bad arguments");
+    if (!C(h).mgs.ready) return set_error(LAPH_ERR_INVALID, "no multigrid set up (laph_mg_setup)");
+    if (!work) return set_error(LAPH_ERR_WORKSPACE, "null workspace");
+    MgState run;
+    LAPH_TRY(mg_run_params(C(h), p, run));
+    return mg_component(C(h), run, what, out, in, n, reinterpret_cast<char *>(work), work_bytes);
+} LAPH_CATCH_STATUS
+
+size_t laph_mg_solve_workspace_bytes(laph_ctx h, int nrhs, const laph_mg_params *p) try {
+    if (!h || nrhs <= 0 || !C(h).mgs.ready) return 0;
+    MgState run;
+    if (mg_run_params(C(h), p, run) != LAPH_OK) return 0;
+    return mg_solve_workspace_bytes(C(h), nrhs, run.restart);
+} LAPH_CATCH_SIZE
+
+laph_status laph_mg_solve(laph_ctx h, double *X, const double *B, int nrhs, double tol, const laph_mg_params *p,
+                          laph_rhs_stats *stats_host, void *work, size_t work_bytes) try {
+    LAPH_TRY(check_ctx(h, true, true));
+    Ctx &c = C(h);
+    if (!X || !B || nrhs <= 0 || nrhs > 65535 || !(tol > 0 && tol < 1))
+        return set_error(LAPH_ERR_INVALID, "bad arguments");
+    if (!c.mgs.ready) return set_error(LAPH_ERR_INVALID, "no multigrid set up (laph_mg_setup)");
+    if (!work) return set_error(LAPH_ERR_WORKSPACE, "null workspace");
+    MgState run;
+    LAPH_TRY(mg_run_params(c, p, run));
+    return mg_solve(c, run, X, B, nrhs, tol, stats_host, reinterpret_cast<char *>(work), work_bytes);
 } LAPH_CATCH_STATUS
 
 }  // extern "C"

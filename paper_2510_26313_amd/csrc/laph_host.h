@@ -44,6 +44,28 @@ struct Tiles {
     int nr = 1;
 };
 
+// Two-level aggregation multigrid attached to a context (mg.hip): geometry of
+// the aggregates and the device arrays inside the caller's multigrid buffer.
+struct MgGeom {
+    int block[4] = {0, 0, 0, 0};   // aggregate extents (x, y, z, t)
+    int cdim[4] = {0, 0, 0, 0};    // coarse lattice extents
+    int nc = 0;                    // coarse sites
+    int asize = 0;                 // fine sites per aggregate
+    int nv = 0;                    // near-null vectors
+    int ncv = 0;                   // coarse components per coarse site (2 nv)
+};
+struct MgState {
+    bool ready = false;
+    int mass_idx = 0;
+    MgGeom geo;
+    int smooth_iters = 4, coarse_iters = 16, restart = 8, maxiter = 200;
+    double coarse_tol = 0.1;
+    char *basis = nullptr;        // nv full FP64 fields (even half, odd half)
+    size_t basis_stride = 0;      // bytes per field
+    double2 *coarse = nullptr;    // [nc][9][ncv][ncv]
+    int *flag = nullptr;          // device int: set by a failed setup step
+};
+
 struct Ctx {
     Geom g{};
     int dims[4]{};
@@ -74,6 +96,7 @@ struct Ctx {
         int form, tile, site_major;
     };
     std::map<std::pair<int, int>, Shape> tuned;
+    MgState mgs;   // the attached multigrid (laph_mg_setup)
 
     size_t hv(int prec) const { return hv_bytes(prec, (size_t)g.vh); }
     // misc region: per-mass diagonal 4 + m0, the SU(3) deviation and the clover failure flag

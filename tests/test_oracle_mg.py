@@ -133,3 +133,50 @@ def test_free_field_closed_form():
                 b = mg.coarse_neighbour(dims, block, a, mu, k)
                 expect[a, :, b, :] += -0.5 * eta * (one + sgn * G[mu]) / block[mu]
     assert np.abs(Dc - expect.reshape(Dc.shape)).max() < 1e-13
+
+
+def _relaxed_setup(dims, block, m0, nv, seed):
+    U = ls.gauge_field(dims, seed)
+    D = dirac.WilsonClover(U, m0, 1.0)
+    V = _vecs(dims, nv, seed + 1)
+    from oracle import solvers
+    for _ in range(2):
+        V, _ = solvers.bicgstab(D.apply, V, tol=1e-2)
+    w = mg.block_orthonormalize(V, dims, block)
+    return D, w, mg.coarse_dense(D, w, block)
+
+
+def test_smoother_residual_identity_and_monotone_mr():
+    """After the smoother the odd residual vanishes and the even one is A_ee times the
+    last MR residual; each MR step cannot increase that residual."""
+    U = ls.gauge_field(DIMS, 810)
+    D = dirac.WilsonClover(U, 0.1, 1.0)
+    r = ls.random_spinor(ls.spinor_shape(DIMS), 811)
+    last = np.inf
+    for it in range(1, 5):
+        e, rho = mg.smoother(D, r, it)
+        res = r - D.apply(e)
+        expect = dirac.apply_site_matrix(D.A, rho)
+        assert np.linalg.norm(res - expect) < 1e-12 * np.linalg.norm(r)
+        odd = 1.0 - dirac.parity_mask(DIMS)
+        assert np.linalg.norm(odd * res) < 1e-12 * np.linalg.norm(r)
+        n = np.linalg.norm(rho)
+        assert n <= last * (1 + 1e-12)
+        last = n
+
+
+def test_coarse_bicgstab_reaches_the_dense_solve():
+    D, w, Dc = _relaxed_setup(DIMS, BLOCK, 0.1, NV, 812)
+    b = ls.random_spinor((Dc.shape[0],), 813)
+    x = mg.coarse_bicgstab(Dc, b, 500, 1e-14)
+    ref = np.linalg.solve(Dc, b)
+    assert np.linalg.norm(x - ref) < 1e-10 * np.linalg.norm(ref)
+
+
+def test_cycle_contracts_the_residual():
+    """With near-null vectors from two inverse-iteration passes the cycle is a good
+    approximate inverse: |r - D K r| well below |r| (a two-grid property)."""
+    D, w, Dc = _relaxed_setup(DIMS, BLOCK, 0.1, NV, 814)
+    r = ls.random_spinor(ls.spinor_shape(DIMS), 815)
+    e = mg.cycle(D, w, BLOCK, Dc, r, 4, 16, 0.1)
+    assert np.linalg.norm(r - D.apply(e)) < 0.2 * np.linalg.norm(r)
