@@ -297,6 +297,51 @@ def contractions_run(laph, torch, n_mom=4, reps=3):
     return out
 
 
+def mg_run(laph, torch, masses, n_rhs=16, block=(4, 4, 4, 4), nvec=12, skip_mg=False, tol=1e-10):
+    """The two-level multigrid against the batched FP16N BiCGStab on the 32^3 x 64 lattice:
+    n_rhs spin-diluted LapH sources at t0 = 0 solved to 1e-10 at each mass of `masses`
+    (the headline mass and lighter ones, where the plain solver needs many more
+    iterations); times, iterations and RHS/s of both, and the multigrid setup time."""
+    cfg = ls.CONFIGS["perambulator_32x32x32x64"]
+    dims = cfg["dims"]
+    lat = laph.Lattice(dims)
+    lat.load_gauge(torch.from_numpy(ls.gauge_field(dims, cfg["seed_u"])).cuda())
+    Vd = torch.from_numpy(ls.orthonormal_laph_vectors(dims, cfg["nev"], cfg["seed_v"])).cuda()
+    B = lat.make_sources(Vd[:, :n_rhs // 4].contiguous(), 0)
+    del Vd
+    out = {"lattice": "x".join(map(str, dims)), "rhs": n_rhs, "block": list(block), "nvec": nvec}
+    for m0 in masses:
+        lat.set_masses([m0], cfg["csw"])
+        tuned = lat.autotune("f16n", n_rhs, 0)
+        lat.autotune("f64", n_rhs, 0)
+        p = laph.default_params(inner_prec="f16n", stencil=tuned["stencil"], rhs_tile=tuned["rhs_tile"],
+                                traversal=tuned["traversal"])
+        (X, st), dt = _timed(torch, lambda: lat.solve_raw(B, 0, tol, p, raise_on_noconv=False))
+        del X
+        res = {"plain_f16n": _solve_summary(st, n_rhs, dt)}
+        res["plain_f16n"]["converged"] = all(s["status"] == "converged" for s in st)
+        res["plain_f16n"]["seconds"] = round(dt, 3)
+        progress("m0 %g: plain batched solver %.2f s, %.1f iterations" % (m0, dt, res["plain_f16n"]["mean_iters"]))
+        if not skip_mg:
+            V0 = torch.from_numpy(ls.random_spinor((nvec,) + ls.spinor_shape(dims), 7300)).cuda()
+            _, ts = _timed(torch, lambda: lat.mg_setup(V0, block, null_passes=4, null_tol=1e-2))
+            del V0
+            lat.mg_solve(B[:1].contiguous(), tol)   # warm
+            (X, st), dt = _timed(torch, lambda: lat.mg_solve(B, tol, allow_noconv=True))
+            del X
+            res["multigrid"] = _solve_summary(st, n_rhs, dt)
+            res["multigrid"]["converged"] = all(s["status"] == "converged" for s in st)
+            res["multigrid"].update({"seconds": round(dt, 3), "setup_seconds": round(ts, 3),
+                                     "fp64_residual_recomputations": float(np.mean([s["updates"] for s in st]))})
+            res["multigrid_over_plain"] = round(res["plain_f16n"]["seconds"] / dt, 3)
+            progress("m0 %g: multigrid %.2f s (setup %.2f s), %.1f iterations" % (m0, dt, ts,
+                                                                                 res["multigrid"]["mean_iters"]))
+        out["m0=%g" % m0] = res
+        lat.release_scratch()
+        torch.cuda.empty_cache()
+    return out
+
+
 # Stage shapes whose counters the probe collects: the bench's dominant shape (128 RHS,
 # LDS links x16, tile sweeps) and the bandwidth-bound small batches.
 PROBE_SHAPES = [("f16n", 128, 2, 16, 2), ("f32", 1, 1, 1, 1), ("f16n", 1, 1, 1, 1), ("f16n", 2, 1, 2, 1),
@@ -360,6 +405,12 @@ def main():
     ap.add_argument("--contractions", action="store_true",
                     help="only compute meson doublets and baryon triplets of 64 vectors on 32^3x64 for 4 "
                          "momenta and print their timing as one JSON line")
+    ap.add_argument("--mg", action="store_true",
+                    help="only compare the two-level multigrid with the batched FP16N solver on 32x32x32x64 "
+                         "(16 LapH sources, 1e-10) at the masses of --mg-masses; one JSON line")
+    ap.add_argument("--mg-masses", default="0.02,-0.4", help="comma-separated bare masses for --mg")
+    ap.add_argument("--mg-rhs", type=int, default=16, help="RHS for --mg (a multiple of 4)")
+    ap.add_argument("--mg-skip", action="store_true", help="--mg: time the plain solver only")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch the stage shapes whose counters are kept (and a 2 GiB copy for the "
                          "counter scale), for rocprofv3 --pmc runs")
@@ -380,6 +431,12 @@ def main():
     if args.laph_vectors:
         print(json.dumps({"workload": "LapH vectors 32x32x32x64, 64 lowest eigenpairs of -Delta per timeslice, "
                                       "tol 1e-10", **laph_vectors_run(laph, torch)}), flush=True)
+        return
+    if args.mg:
+        masses = [float(m) for m in args.mg_masses.split(",")]
+        print(json.dumps({"workload": "multigrid vs batched FP16N BiCGStab, 32x32x32x64, %d LapH sources, tol 1e-10"
+                                      % args.mg_rhs, **mg_run(laph, torch, masses, args.mg_rhs, skip_mg=args.mg_skip)}),
+              flush=True)
         return
     if args.contractions:
         print(json.dumps({"workload": "meson doublets and baryon triplets, 32x32x32x64, nev 64",

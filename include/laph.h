@@ -428,7 +428,7 @@ typedef struct {
     int maxiter;         /* outer iterations at most, >= 1 */
 } laph_mg_params;
 
-/* Defaults: nvec 12, block 4 x 4 x 4 x 4, null_passes 2, null_tol 1e-2, smooth_iters 4,
+/* Defaults: nvec 12, block 4 x 4 x 4 x 4, null_passes 4, null_tol 1e-2, smooth_iters 4,
  * coarse_iters 16, coarse_tol 0.1, restart 8, maxiter 500. */
 void laph_mg_default_params(laph_mg_params *p);
 /* Bytes of the caller's multigrid buffer (basis: nvec full FP64 fields; coarse matrix)

@@ -904,7 +904,7 @@ void laph_mg_default_params(laph_mg_params *p) {
     std::memset(p, 0, sizeof(*p));
     p->nvec = 12;
     for (int i = 0; i < 4; ++i) p->block[i] = 4;
-    p->null_passes = 2;
+    p->null_passes = 4;
     p->null_tol = 1e-2;
     p->smooth_iters = 4;
     p->coarse_iters = 16;

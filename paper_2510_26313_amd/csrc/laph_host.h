@@ -62,6 +62,8 @@ struct MgState {
     double coarse_tol = 0.1;
     char *basis = nullptr;        // nv full FP64 fields (even half, odd half)
     size_t basis_stride = 0;      // bytes per field
+    char *basis32 = nullptr;      // the same in FP32 (the cycle's restriction and prolongation)
+    size_t basis32_stride = 0;
     double2 *coarse = nullptr;    // [nc][9][ncv][ncv]
     int *flag = nullptr;          // device int: set by a failed setup step
 };

@@ -428,31 +428,163 @@ __global__ __launch_bounds__(kMB) void mg_prolong_kernel(Geom g, MgDev m, const 
     SpinorIO<P>::store(hv, g.vh, h, o);
 }
 
+// The cycle's restriction and prolongation: FP32 fields, the FP32 copy of the basis,
+// kMgRhsGroup RHS per workgroup (each basis vector is read once per group).
+constexpr int kMgRhsGroup = 4;
+
+// out[r][a][(chi, i)] = sum over the sites of a of the parities in pmask of <w_(chi,i), f_r>,
+// for the group's RHS.  Grid (nc, ceil(n / kMgRhsGroup)); one site per thread (asize <= kMB).
+__global__ __launch_bounds__(kMB) void mg_restrict32_kernel(Geom g, MgDev m, const char *basis, size_t bstride,
+                                                            size_t bhalf, Operand f, size_t fhalf, int pmask, int n,
+                                                            double2 *out) {
+    __shared__ double red[(kMB / 64) * 4 * kMgRhsGroup];
+    const int a = blockIdx.x, r0 = blockIdx.y * kMgRhsGroup;
+    const int k = threadIdx.x;
+    int x = 0, y = 0, z = 0, t = 0;
+    bool own = k < m.asize;
+    if (own) agg_site(m, a, k, x, y, z, t);
+    const int p = (x + y + z + t) & 1;
+    own = own && ((pmask >> p) & 1);
+    const int h = own ? cb_index(g, x, y, z, t) : 0;
+    cplx<float> fv[kMgRhsGroup][12];
+#pragma unroll
+    for (int rr = 0; rr < kMgRhsGroup; ++rr) {
+        if (own && r0 + rr < n) {
+            SpinorIO<F32>::load(f.at(r0 + rr) + p * fhalf, g.vh, h, fv[rr]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) fv[rr][c] = {0.f, 0.f};
+        }
+    }
+    for (int i = 0; i < m.nv; ++i) {
+        double acc[4 * kMgRhsGroup];
+#pragma unroll
+        for (int q = 0; q < 4 * kMgRhsGroup; ++q) acc[q] = 0.0;
+        if (own) {
+            cplx<float> b[12];
+            SpinorIO<F32>::load(basis + (size_t)i * bstride + p * bhalf, g.vh, h, b);
+#pragma unroll
+            for (int rr = 0; rr < kMgRhsGroup; ++rr)
+#pragma unroll
+                for (int c = 0; c < 12; ++c) {
+                    const int q = 4 * rr + 2 * (c / 6);
+                    acc[q] += (double)(b[c].re * fv[rr][c].re + b[c].im * fv[rr][c].im);
+                    acc[q + 1] += (double)(b[c].re * fv[rr][c].im - b[c].im * fv[rr][c].re);
+                }
+        }
+        block_sum_bcast<4 * kMgRhsGroup>(acc, red);
+        if (threadIdx.x < 2 * kMgRhsGroup) {
+            const int rr = threadIdx.x >> 1, chi = threadIdx.x & 1;
+            if (r0 + rr < n)
+                out[((size_t)(r0 + rr) * m.nc + a) * m.ncv + chi * m.nv + i] =
+                    make_double2(acc[4 * rr + 2 * chi], acc[4 * rr + 2 * chi + 1]);
+        }
+    }
+}
+
+// f_r (+)= P c_r on both parities for the group's RHS.  Grid (ceil(2 vh / kMB), ceil(n / kMgRhsGroup)).
+template <bool ACC>
+__global__ __launch_bounds__(kMB) void mg_prolong32_kernel(Geom g, MgDev m, const char *basis, size_t bstride,
+                                                           size_t bhalf, const double2 *cv, Operand f, size_t fhalf,
+                                                           int n) {
+    const int s = blockIdx.x * kMB + threadIdx.x;
+    const int r0 = blockIdx.y * kMgRhsGroup;
+    if (s >= 2 * g.vh) return;
+    const int p = s >= g.vh ? 1 : 0;
+    const int h = s - p * g.vh;
+    int x, y, z, t;
+    site_coords(g, p, h, x, y, z, t);
+    const int a = agg_of(m, x, y, z, t);
+    cplx<float> o[kMgRhsGroup][12];
+#pragma unroll
+    for (int rr = 0; rr < kMgRhsGroup; ++rr)
+#pragma unroll
+        for (int c = 0; c < 12; ++c) o[rr][c] = {0.f, 0.f};
+    for (int i = 0; i < m.nv; ++i) {
+        cplx<float> b[12];
+        SpinorIO<F32>::load(basis + (size_t)i * bstride + p * bhalf, g.vh, h, b);
+#pragma unroll
+        for (int rr = 0; rr < kMgRhsGroup; ++rr) {
+            const int r = min(r0 + rr, n - 1);
+            const double2 c0 = cv[((size_t)r * m.nc + a) * m.ncv + i], c1 = cv[((size_t)r * m.nc + a) * m.ncv + m.nv + i];
+            const float c0r = float(c0.x), c0i = float(c0.y), c1r = float(c1.x), c1i = float(c1.y);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const float cr = c < 6 ? c0r : c1r, ci = c < 6 ? c0i : c1i;
+                o[rr][c] = {o[rr][c].re + cr * b[c].re - ci * b[c].im, o[rr][c].im + cr * b[c].im + ci * b[c].re};
+            }
+        }
+    }
+#pragma unroll
+    for (int rr = 0; rr < kMgRhsGroup; ++rr) {
+        if (r0 + rr >= n) break;
+        char *hv = f.at(r0 + rr) + p * fhalf;
+        if (ACC) {
+            cplx<float> prev[12];
+            SpinorIO<F32>::load(hv, g.vh, h, prev);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) o[rr][c] = {o[rr][c].re + prev[c].re, o[rr][c].im + prev[c].im};
+        }
+        SpinorIO<F32>::store(hv, g.vh, h, o[rr]);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // coarse operator and coarse BiCGStab (FP64, coarse vectors [n][nc][ncv])
 // ---------------------------------------------------------------------------
-constexpr int kCoarseRhs = 8;   // RHS per coarse-apply workgroup (the block rows are read once for them)
+// out_r = D_c in_r.  Grid (nc, RHS groups), kMB threads: for each of the 9 directions the
+// block row C[a][d] and the neighbour's coarse vectors of the group's RHS are staged in
+// LDS (coalesced), then each thread accumulates up to kCoarsePairs (row, RHS) outputs, so
+// every block row is read from memory once per group.
+constexpr int kCoarsePairs = 4;
+inline int coarse_group(int ncv) { return std::min(64, kCoarsePairs * kMB / ncv); }
 
-// out_r = D_c in_r.  Grid (nc, ceil(n / 8)), block ncv * 8.
 __global__ __launch_bounds__(kMB) void mg_coarse_apply_kernel(MgDev m, const double2 *C, const double2 *in,
-                                                              double2 *out, int n, const int *frozen) {
-    const int a = blockIdx.x;
-    const int row = threadIdx.x / kCoarseRhs, rl = threadIdx.x % kCoarseRhs;
-    const int r = blockIdx.y * kCoarseRhs + rl;
-    if (row >= m.ncv || r >= n) return;
-    if (frozen && frozen[r]) return;
-    double sr = 0, si = 0;
+                                                              double2 *out, int n, int group) {
+    extern __shared__ double2 lds[];
+    double2 *ct = lds;                                    // ncv x ncv block
+    double2 *xt = lds + (size_t)m.ncv * m.ncv;            // group x ncv neighbour vectors
+    const int a = blockIdx.x, r0 = blockIdx.y * group;
+    const int g = min(group, n - r0);
+    const int npair = m.ncv * g, nblk = m.ncv * m.ncv;
+    double acc[2 * kCoarsePairs];
+#pragma unroll
+    for (int k = 0; k < 2 * kCoarsePairs; ++k) acc[k] = 0.0;
     for (int d = 0; d < 9; ++d) {
         const int nb = coarse_nbr(m, a, d);
-        const double2 *crow = C + (((size_t)a * 9 + d) * m.ncv + row) * m.ncv;
-        const double2 *v = in + ((size_t)r * m.nc + nb) * m.ncv;
-        for (int col = 0; col < m.ncv; ++col) {
-            const double2 cc = crow[col], vv = v[col];
-            sr += cc.x * vv.x - cc.y * vv.y;
-            si += cc.x * vv.y + cc.y * vv.x;
+        __syncthreads();
+        const double2 *cb = C + ((size_t)a * 9 + d) * nblk;
+        for (int i = threadIdx.x; i < nblk; i += kMB) ct[i] = cb[i];
+        for (int i = threadIdx.x; i < npair; i += kMB) {
+            const int rl = i / m.ncv, col = i - rl * m.ncv;
+            xt[i] = in[((size_t)(r0 + rl) * m.nc + nb) * m.ncv + col];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kCoarsePairs; ++k) {
+            const int pidx = threadIdx.x + k * kMB;
+            if (pidx < npair) {
+                const int rl = pidx / m.ncv, row = pidx - rl * m.ncv;
+                const double2 *crow = ct + (size_t)row * m.ncv, *x = xt + (size_t)rl * m.ncv;
+                double sr = acc[2 * k], si = acc[2 * k + 1];
+                for (int col = 0; col < m.ncv; ++col) {
+                    const double2 cc = crow[col], vv = x[col];
+                    sr += cc.x * vv.x - cc.y * vv.y;
+                    si += cc.x * vv.y + cc.y * vv.x;
+                }
+                acc[2 * k] = sr;
+                acc[2 * k + 1] = si;
+            }
         }
     }
-    out[((size_t)r * m.nc + a) * m.ncv + row] = make_double2(sr, si);
+#pragma unroll
+    for (int k = 0; k < kCoarsePairs; ++k) {
+        const int pidx = threadIdx.x + k * kMB;
+        if (pidx < npair) {
+            const int rl = pidx / m.ncv, row = pidx - rl * m.ncv;
+            out[((size_t)(r0 + rl) * m.nc + a) * m.ncv + row] = make_double2(acc[2 * k], acc[2 * k + 1]);
+        }
+    }
 }
 
 struct CgState {
@@ -896,7 +1028,9 @@ static size_t full64(const Ctx &c) { return 2 * c.hv(LAPH_F64); }
 static size_t full32(const Ctx &c) { return 2 * c.hv(LAPH_F32); }
 static size_t coarse_bytes(const MgGeom &g) { return round256((size_t)g.nc * 9 * g.ncv * g.ncv * sizeof(double2)); }
 
-size_t mg_state_bytes(const Ctx &c, const MgGeom &g) { return (size_t)g.nv * full64(c) + coarse_bytes(g) + 256; }
+size_t mg_state_bytes(const Ctx &c, const MgGeom &g) {
+    return (size_t)g.nv * full64(c) + (size_t)g.nv * full32(c) + coarse_bytes(g) + 256;
+}
 
 size_t mg_setup_workspace_bytes(const Ctx &c, const MgGeom &g, int null_passes) {
     if (null_passes <= 0) return 256;
@@ -916,8 +1050,10 @@ static laph_status attach(Ctx &c, const MgGeom &g, char *state, size_t bytes, in
     s.mass_idx = mass_idx;
     s.basis = state;
     s.basis_stride = full64(c);
-    s.coarse = reinterpret_cast<double2 *>(state + (size_t)g.nv * full64(c));
-    s.flag = reinterpret_cast<int *>(state + (size_t)g.nv * full64(c) + coarse_bytes(g));
+    s.basis32 = state + (size_t)g.nv * full64(c);
+    s.basis32_stride = full32(c);
+    s.coarse = reinterpret_cast<double2 *>(state + (size_t)g.nv * (full64(c) + full32(c)));
+    s.flag = reinterpret_cast<int *>(state + (size_t)g.nv * (full64(c) + full32(c)) + coarse_bytes(g));
     return LAPH_OK;
 }
 
@@ -962,6 +1098,10 @@ laph_status mg_setup(Ctx &c, int mass_idx, const MgGeom &g, const double *V0, in
     hipLaunchKernelGGL(mg_orth_kernel, dim3(g.nc, 2), dim3(kMB), 0, c.stream, c.g, m, s.basis, s.basis_stride,
                        c.hv(LAPH_F64), s.flag);
     LAPH_TRY(check_launch("mg_orth_kernel"));
+    hipLaunchKernelGGL((mg_convert_kernel<F64, F32>), dim3((2 * c.g.vh + kMB - 1) / kMB, g.nv), dim3(kMB), 0, c.stream,
+                       c.g.vh, c.hv(LAPH_F64), c.hv(LAPH_F32), Operand{s.basis32, s.basis32_stride},
+                       Operand{s.basis, s.basis_stride});
+    LAPH_TRY(check_launch("mg_convert_kernel"));
     hipLaunchKernelGGL(mg_coarse_build_kernel, dim3(g.nc), dim3(kMB), 0, c.stream, c.g, c.gp, m,
                        (const char *)s.basis, s.basis_stride, c.hv(LAPH_F64), c.clover_term(0), c.clover_term(1),
                        (const double *)c.mass_diag(), mass_idx, s.coarse);
@@ -1007,17 +1147,18 @@ laph_status mg_prolong_canonical(const Ctx &c, double *f, const double *cvec, in
     return unpack_spinor(c, f, fo, LAPH_F64, n, -1, 0);
 }
 
-static laph_status coarse_apply_dev(const Ctx &c, double2 *out, const double2 *in, int n, const int *frozen) {
+static laph_status coarse_apply_dev(const Ctx &c, double2 *out, const double2 *in, int n) {
     const MgState &s = c.mgs;
-    hipLaunchKernelGGL(mg_coarse_apply_kernel, dim3(s.geo.nc, (n + kCoarseRhs - 1) / kCoarseRhs),
-                       dim3(s.geo.ncv * kCoarseRhs), 0, c.stream, mg_dev(s.geo), (const double2 *)s.coarse, in, out, n,
-                       frozen);
+    const int group = coarse_group(s.geo.ncv);
+    const size_t lds = ((size_t)s.geo.ncv * s.geo.ncv + (size_t)group * s.geo.ncv) * sizeof(double2);
+    hipLaunchKernelGGL(mg_coarse_apply_kernel, dim3(s.geo.nc, (n + group - 1) / group), dim3(kMB), lds, c.stream,
+                       mg_dev(s.geo), (const double2 *)s.coarse, in, out, n, group);
     return check_launch("mg_coarse_apply_kernel");
 }
 
 laph_status mg_coarse_apply(const Ctx &c, double *out, const double *in, int n) {
     LAPH_TRY(need_mg(c));
-    return coarse_apply_dev(c, reinterpret_cast<double2 *>(out), reinterpret_cast<const double2 *>(in), n, nullptr);
+    return coarse_apply_dev(c, reinterpret_cast<double2 *>(out), reinterpret_cast<const double2 *>(in), n);
 }
 
 // ---------------------------------------------------------------------------
@@ -1228,10 +1369,10 @@ laph_status MgSolver::coarse_solve() {
     for (int it = 0; it < s.coarse_iters; ++it) {
         LAPH_TRY(dot(w.crh, w.cr, nullptr, nullptr, 1, kCgRho));
         LAPH_TRY(upd(0));
-        LAPH_TRY(coarse_apply_dev(c, w.cv, w.cp, n, nullptr));
+        LAPH_TRY(coarse_apply_dev(c, w.cv, w.cp, n));
         LAPH_TRY(dot(w.crh, w.cv, nullptr, nullptr, 1, kCgAlpha));
         LAPH_TRY(upd(1));
-        LAPH_TRY(coarse_apply_dev(c, w.ct, w.cs, n, nullptr));
+        LAPH_TRY(coarse_apply_dev(c, w.ct, w.cs, n));
         LAPH_TRY(dot(w.ct, w.cs, w.ct, w.ct, 2, kCgOmega));
         LAPH_TRY(upd(2));
         LAPH_TRY(dot(w.cr, w.cr, nullptr, nullptr, 1, kCgRes));
@@ -1245,13 +1386,14 @@ laph_status MgSolver::vcycle(Operand r, Operand e) {
     LAPH_TRY(smooth(r, e));
     // residual of the pre-smoothed e: (A_ee rho, 0)
     LAPH_TRY(clov(LAPH_F32, 0, 0, half(w.sb, 0, h32), half(w.res, 0, h32), 0, Operand{}, 0, 1.0));
-    hipLaunchKernelGGL(mg_restrict_kernel<F32>, dim3(s.geo.nc, n), dim3(kMB), 0, c.stream, c.g, m,
-                       (const char *)s.basis, s.basis_stride, h64, w.res, h32, 1, w.cb);
-    LAPH_TRY(check_launch("mg_restrict_kernel"));
+    const int ng = (n + kMgRhsGroup - 1) / kMgRhsGroup;
+    hipLaunchKernelGGL(mg_restrict32_kernel, dim3(s.geo.nc, ng), dim3(kMB), 0, c.stream, c.g, m,
+                       (const char *)s.basis32, s.basis32_stride, h32, w.res, h32, 1, n, w.cb);
+    LAPH_TRY(check_launch("mg_restrict32_kernel"));
     LAPH_TRY(coarse_solve());
-    hipLaunchKernelGGL((mg_prolong_kernel<F32, false>), grid2(2 * c.g.vh, n), dim3(kMB), 0, c.stream, c.g, m,
-                       (const char *)s.basis, s.basis_stride, h64, (const double2 *)w.cx, w.q, h32);
-    LAPH_TRY(check_launch("mg_prolong_kernel"));
+    hipLaunchKernelGGL((mg_prolong32_kernel<false>), dim3((2 * c.g.vh + kMB - 1) / kMB, ng), dim3(kMB), 0, c.stream,
+                       c.g, m, (const char *)s.basis32, s.basis32_stride, h32, (const double2 *)w.cx, w.q, h32, n);
+    LAPH_TRY(check_launch("mg_prolong32_kernel"));
     hipLaunchKernelGGL(mg_add_kernel<F32>, grid2(2 * c.g.vh, n), dim3(kMB), 0, c.stream, c.g.vh, 2, h32, e, e, w.q);
     LAPH_TRY(check_launch("mg_add_kernel"));
     // res2 = res - D q: hq = 1/2 H q; hq += res (odd residual half is zero); res2 = hq - A q
