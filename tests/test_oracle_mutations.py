@@ -6,13 +6,19 @@ flipped clover sign, a leaf built from the wrong links, a reversed leaf, a
 Laplacian sign slip, a conjugate on the wrong factor of the projection, a
 missing gamma5 in the adjoint, the doublets' conjugate or phase sign, a triplet
 epsilon sign or a conjugated triplet factor, blocked instead of interlaced noise
-dilution, noise of the wrong spin, a spin rotation by S^T instead of S^dagger) and asserts that the named pin now fails.
+dilution, noise of the wrong spin, a spin rotation by S^T instead of S^dagger;
+for the multigrid: a restriction without the conjugate, Gram-Schmidt without the
+projections or across chiralities, a coarse matrix of D^dagger, a smoother that
+reconstructs with the wrong sign, a coarse BiCGStab with a conjugated omega) and
+asserts that the named pin now fails.
 Everything runs on the CPU; nothing here touches the GPU library.
 """
 import numpy as np
 import pytest
 
 from oracle import dirac, laph
+from oracle import multigrid as omg
+import test_oracle_mg as mgpins
 import test_oracle_pins as pins
 
 _orig_hop = dirac.hop
@@ -140,6 +146,80 @@ def _spin_rotate_transpose(tau, S):
     return np.einsum("ab,...bc,cd->...ad", S, tau, S.T)
 
 
+def _restrict_no_conj(basis, f, dims, block):
+    wb = omg._to_blocks(basis, dims, block)
+    fb = omg._to_blocks(f, dims, block)
+    return np.einsum("itzyxcm,ntzyxcm->ntzyxci", wb, fb)
+
+
+def _orth_no_projection(vecs, dims, block):
+    g = omg._to_blocks(np.asarray(vecs, dtype=np.complex128), dims, block)
+    w = g / np.sqrt(np.sum(np.abs(g) ** 2, axis=-1, keepdims=True))
+    return omg._from_blocks(w, dims, block)
+
+
+def _orth_whole_spinor(vecs, dims, block):
+    # Gram-Schmidt over both chiralities at once (a non-chiral basis)
+    g = omg._to_blocks(np.asarray(vecs, dtype=np.complex128), dims, block)
+    sh = g.shape
+    h = g.reshape(sh[:-2] + (2 * sh[-1],))
+    w = np.array(h)
+    for i in range(w.shape[0]):
+        for j in range(i):
+            w[i] = w[i] - np.sum(np.conj(w[j]) * w[i], axis=-1, keepdims=True) * w[j]
+        w[i] = w[i] / np.sqrt(np.sum(np.abs(w[i]) ** 2, axis=-1, keepdims=True))
+    return omg._from_blocks(w.reshape(sh), dims, block)
+
+
+class _DaggerD:
+    def __init__(self, D):
+        self.D = D
+        self.dims = D.dims
+
+    def apply(self, psi):
+        return self.D.apply_dagger(psi)
+
+
+_orig_coarse_dense = omg.coarse_dense
+
+
+def _coarse_dense_dagger(D, basis, block):
+    return _orig_coarse_dense(_DaggerD(D), basis, block)
+
+
+def _smoother_wrong_reconstruction(D, r, iters):
+    e, rho = _orig_smoother(D, r, iters)
+    eo = dirac.EvenOdd(D)
+    e_e = eo.e * e
+    e_o = eo.o * eo.Ainv(eo.o * r - 0.5 * eo.o * D.hop(e_e))
+    return e_e + e_o, rho
+
+
+_orig_smoother = omg.smoother
+
+
+def _coarse_bicgstab_conj_omega(Dc, b, iters, tol):
+    x = np.zeros_like(b)
+    r = b.copy()
+    rh = b.copy()
+    p = np.zeros_like(b)
+    v = np.zeros_like(b)
+    rho = alpha = omega = 1.0
+    for _ in range(iters):
+        rn = np.vdot(rh, r)
+        beta = (rn / rho) * (alpha / omega)
+        rho = rn
+        p = r + beta * (p - omega * v)
+        v = Dc @ p
+        alpha = rho / np.vdot(rh, v)
+        s = r - alpha * v
+        t = Dc @ s
+        omega = np.conj(np.vdot(t, s) / np.vdot(t, t).real)
+        x = x + alpha * p + omega * s
+        r = s - omega * t
+    return x
+
+
 CASES = [
     ("hop projector sign", dirac, "hop", _hop_flipped, pins.test_free_field_plane_wave),
     ("no antiperiodic phase", dirac, "hop", _hop_periodic, pins.test_free_field_propagator_closed_form),
@@ -163,6 +243,17 @@ CASES = [
      pins.test_stochastic_perambulator_is_noise_weighted_perambulator),
     ("spin rotation by S^T instead of S^dagger", laph, "spin_rotate", _spin_rotate_transpose,
      pins.test_spin_rotate_equals_rotating_sources_and_solutions),
+    ("restriction without the conjugate", omg, "restrict", _restrict_no_conj, mgpins.test_restrict_is_adjoint_of_prolong),
+    ("Gram-Schmidt without projections", omg, "block_orthonormalize", _orth_no_projection,
+     mgpins.test_basis_orthonormal_and_spanning),
+    ("Gram-Schmidt across chiralities", omg, "block_orthonormalize", _orth_whole_spinor,
+     mgpins.test_basis_orthonormal_and_spanning),
+    ("coarse matrix of D^dagger", omg, "coarse_dense", _coarse_dense_dagger,
+     mgpins.test_galerkin_orthogonality_and_gamma5),
+    ("smoother reconstructs with the wrong sign", omg, "smoother", _smoother_wrong_reconstruction,
+     mgpins.test_smoother_residual_identity_and_monotone_mr),
+    ("coarse BiCGStab with a conjugated omega", omg, "coarse_bicgstab", _coarse_bicgstab_conj_omega,
+     mgpins.test_coarse_bicgstab_reaches_the_dense_solve),
 ]
 
 
