@@ -126,6 +126,23 @@ __device__ __forceinline__ void block_sum_bcast(double (&v)[N], double *red) {
     __syncthreads();
 }
 
+// Wave reduction of 64 values per lane that leaves lane l with the wave's sum of
+// v[l] (a transposing butterfly: each step a lane keeps half of its values and adds
+// its partner's matching half, 63 exchanges in all instead of 6 per value).
+__device__ __forceinline__ double wave_transpose_sum64(double (&v)[64], int lane) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const bool up = (lane & o) != 0;
+#pragma unroll
+        for (int i = 0; i < o; ++i) {
+            const double send = up ? v[i] : v[i + o];
+            const double keep = up ? v[i + o] : v[i];
+            v[i] = keep + __shfl_xor(send, o, 64);
+        }
+    }
+    return v[0];
+}
+
 __device__ __forceinline__ double2 ld2(const char *hv, int vh, int c, int h) {
     return reinterpret_cast<const double2 *>(hv)[(size_t)c * vh + h];
 }
@@ -330,15 +347,19 @@ __global__ __launch_bounds__(kMB) void mg_coarse_build_kernel(Geom g, GaugePtrs 
                         }
                     }
                 }
-                block_sum_bcast<4 * kMgMaxVec>(acc, red);
-                if (threadIdx.x == 0) {
-                    for (int i = 0; i < m.nv; ++i)
-                        for (int chi = 0; chi < 2; ++chi) {
-                            const size_t row = (size_t)chi * m.nv + i, col = (size_t)chi2 * m.nv + j;
-                            C[(((size_t)a * 9 + d) * m.ncv + row) * m.ncv + col] =
-                                make_double2(acc[4 * i + 2 * chi], acc[4 * i + 2 * chi + 1]);
-                        }
+                // value q = 4 i + 2 chi + (0: re, 1: im) summed over the block: lane q of
+                // every wave holds its wave's sum, thread q adds the four waves in order
+                const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+                red[wave * 64 + lane] = wave_transpose_sum64(acc, lane);
+                __syncthreads();
+                if (threadIdx.x < 4 * m.nv) {
+                    const int q = threadIdx.x, i = q >> 2, chi = (q >> 1) & 1;
+                    double sum = 0;
+                    for (int wv = 0; wv < kMB / 64; ++wv) sum += red[wv * 64 + q];
+                    const size_t row = (size_t)chi * m.nv + i, col = (size_t)chi2 * m.nv + j;
+                    reinterpret_cast<double *>(C)[((((size_t)a * 9 + d) * m.ncv + row) * m.ncv + col) * 2 + (q & 1)] = sum;
                 }
+                __syncthreads();
             }
         }
     }
