@@ -384,8 +384,8 @@ laph_status laph_mass_gradient(laph_ctx ctx, double *g_host, const double *Z, co
                                void *work, size_t work_bytes);
 
 /* Measurement: copy `bytes` (a multiple of 16) from src to dst on the device with
- * the library's streaming kernel (16-byte loads, four in flight per thread),
- * once to warm up and then reps times; *ms_host = average ms per copy (HIP events
+ * the library's streaming kernel (one 16-byte word per thread, one pass of the
+ * grid over the buffer), once to warm up and then reps times; *ms_host = average ms per copy (HIP events
  * on the context stream).  Read + written bytes / time is the HBM rate a
  * bandwidth-bound kernel of the library can reach.  dst and src must not overlap. */
 laph_status laph_stream_copy(laph_ctx ctx, void *dst, const void *src, size_t bytes, int reps, double *ms_host);

@@ -12,14 +12,15 @@ int stage_nsb(const Ctx &c, int form) {
 int partial_stride(const Ctx &c) { return stage_nsb(c, kFormLds); }
 
 // 4-D tiles of the LDS form's 64-site blocks, when 64 sites are whole y rows and
-// the tile divides the lattice: 4 z-planes x 4 timeslices (2 x 2 for FP64, whose
-// blocks hold twice the bytes); measured on 32^3 x 64 at 128 RHS: -8 % (FP16N)
-// and -5 % (FP64) per stage pair against the memory order.
+// the tile divides the lattice: 4 z-planes x 4 timeslices (8 x 8 for FP64).
+// Measured on 32^3 x 64 at 128 RHS with the items in dispatch order, per stage
+// pair: FP16N 15.59 ms (memory order 15.76, 2 x 2 15.96, 8 x 8 15.60), FP64 53.7
+// ms (2 x 2 55.8, 4 x 4 54.6, memory order 55.9).
 static void lds_block_tiles(const Ctx &c, const StageSpec &s, StageArgs &a) {
     a.nyb = a.tz = a.tt = 0;
     const int rows = kLdsSites % c.g.lxh == 0 ? kLdsSites / c.g.lxh : 0;
     if (s.form != kFormLds || rows == 0 || c.g.ly % rows != 0) return;
-    for (int t : {s.prec == LAPH_F64 ? 2 : 4, 2}) {
+    for (int t : {s.prec == LAPH_F64 ? 8 : 4, 4, 2}) {
         if (c.g.lz % t == 0 && c.g.lt % t == 0) {
             a.nyb = c.g.ly / rows;
             a.tz = a.tt = t;
@@ -54,6 +55,7 @@ laph_status launch_stage(const Ctx &c, const StageSpec &s) {
     a.site_major = s.site_major;
     a.grid_cap = s.grid_cap;
     lds_block_tiles(c, s, a);
+    a.dispatch_order = s.form == kFormLds ? 1 : 0;
     a.flag_filter = s.flagged;
     a.one = 1.0f;
     a.st = s.slots;

@@ -211,7 +211,7 @@ template <class P, int RW, bool DAG, bool CLOVER, bool PRE, int POST, int RED>
 __global__ __launch_bounds__(256) void stage_lds_kernel(StageArgs A) {
     const int nt = *A.ntiles;
     int first, end, step;
-    stage_item_range(nt * A.nsb, first, end, step);
+    stage_item_range(nt * A.nsb, A.dispatch_order, first, end, step);
     for (int w = first; w < end; w += step) {
         int sb, tile;
         stage_item(w, A.site_major, A.nsb, nt, sb, tile);

@@ -9,8 +9,6 @@ namespace laph {
 // kGradBlocks partials and one result)
 constexpr int kGradBlocks = 2048;
 constexpr size_t kGradScratchDoubles = kGradBlocks + 1;
-// workgroups of the streaming copy (a few per CU; each walks the buffer)
-constexpr size_t kCopyGrid = 4096;
 
 // out[r * 3 + q] = sum of the nsb stage partials of RHS r and quantity q < nq
 laph_status sum_stage_partials(const Ctx &c, const double *partials, int pstride, int nsb, int nrhs, int nq,

@@ -97,29 +97,20 @@ laph_status mass_gradient(const Ctx &c, double *g_host, const double *Z, const d
     return LAPH_OK;
 }
 
-// dst = src, 16-byte words, four loads in flight per thread before the stores
+// dst = src, one 16-byte word per thread, one workgroup per 4 KiB: the grid walks
+// the buffer once in dispatch order.  Measured on MI355X (4 GiB): 6.16 TB/s read +
+// write, against 4.7-5.5 TB/s for grid-stride loops of 2048-65536 workgroups with
+// 1, 4 or 8 words in flight per thread (non-temporal loads or stores changed little).
 __global__ __launch_bounds__(kRB) void stream_copy_kernel(uint4 *dst, const uint4 *src, size_t n) {
-    const size_t stride = (size_t)gridDim.x * kRB * 4;
-    for (size_t i = (size_t)blockIdx.x * kRB * 4 + threadIdx.x; i < n; i += stride) {
-        uint4 v[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const size_t j = i + (size_t)k * kRB;
-            if (j < n) v[k] = src[j];
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const size_t j = i + (size_t)k * kRB;
-            if (j < n) dst[j] = v[k];
-        }
-    }
+    const size_t i = (size_t)blockIdx.x * kRB + threadIdx.x;
+    if (i < n) dst[i] = src[i];
 }
 
 laph_status stream_copy(const Ctx &c, void *dst, const void *src, size_t bytes, int reps, double *ms_host) {
     const size_t n = bytes / 16;
-    const size_t per_block = (size_t)kRB * 4;
-    const size_t want = (n + per_block - 1) / per_block;
-    const int grid = (int)(want < kCopyGrid ? (want > 0 ? want : 1) : kCopyGrid);
+    const size_t want = (n + kRB - 1) / kRB;
+    if (want > (size_t)0x7fffffff) return set_error(LAPH_ERR_INVALID, "copy too large for one grid");
+    const unsigned grid = (unsigned)(want > 0 ? want : 1);
     auto launch = [&]() {
         hipLaunchKernelGGL(stream_copy_kernel, dim3(grid), dim3(kRB), 0, c.stream, reinterpret_cast<uint4 *>(dst),
                            reinterpret_cast<const uint4 *>(src), n);
