@@ -234,8 +234,9 @@ __device__ __forceinline__ void spin_accumulate(cplx<R> (&acc)[12], const cplx<R
     }
 }
 
-// u = L h  (ADJ: L^dagger h) for both colour vectors of the half spinor
-template <bool ADJ, class R>
+// u = L h  (ADJ: L^dagger h) for both colour vectors of the half spinor; CHAIN:
+// fused multiply-add chains (cfma) instead of sums of products (cmac)
+template <bool ADJ, class R, bool CHAIN = false>
 __device__ __forceinline__ void colour_mul(const cplx<R> (&L)[9], const cplx<R> (&h)[6], cplx<R> (&u)[6]) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
@@ -244,10 +245,17 @@ __device__ __forceinline__ void colour_mul(const cplx<R> (&L)[9], const cplx<R> 
             cplx<R> s = ADJ ? cmul1_conj(L[a], h[3 * j]) : cmul1(L[a * 3], h[3 * j]);
 #pragma unroll
             for (int b = 1; b < 3; ++b) {
-                if (ADJ)
-                    cmac_conj(s, L[b * 3 + a], h[3 * j + b]);
-                else
-                    cmac(s, L[a * 3 + b], h[3 * j + b]);
+                if (ADJ) {
+                    if (CHAIN)
+                        cfma_conj(s, L[b * 3 + a], h[3 * j + b]);
+                    else
+                        cmac_conj(s, L[b * 3 + a], h[3 * j + b]);
+                } else {
+                    if (CHAIN)
+                        cfma(s, L[a * 3 + b], h[3 * j + b]);
+                    else
+                        cmac(s, L[a * 3 + b], h[3 * j + b]);
+                }
             }
             u[3 * j + a] = s;
         }

@@ -34,8 +34,27 @@ __device__ __forceinline__ void lds_hop(const char *src, int vh, const typename 
     const R nrm = load_project<P, MU, S>(src, vh, hn, one, hs);
 #pragma unroll
     for (int k = 0; k < 9; ++k) L[k] = {lnk[hop][2 * k][lane], lnk[hop][2 * k + 1][lane]};
-    colour_mul<false>(L, hs, u);
+    colour_mul<false, R, (sizeof(R) == 4)>(L, hs, u);
     spin_accumulate<MU, S>(acc, u, nrm);
+}
+
+// Barrier between the phases of one RHS (after each hop direction and each clover
+// block).  FP32 / FP16N: the accumulator is complete here and no memory access moves
+// across, so only one direction's neighbour data is live; that keeps the stage
+// kernels at 104-109 VGPRs with every complex multiply-add a fused chain (1308 VALU
+// instructions per 64 site-RHS in stage 1 against 1608 with sums of products and a
+// scheduling barrier alone; 128 RHS: stage 1 / stage 2 6.55 / 8.49 ms against 6.67 /
+// 8.96).  FP64 keeps the scheduling barrier and sums of products.
+template <class R>
+__device__ __forceinline__ void phase_fence(cplx<R> (&a)[12]) {
+    if constexpr (sizeof(R) == 4) {
+        asm volatile("" : "+v"(a[0].re), "+v"(a[0].im), "+v"(a[1].re), "+v"(a[1].im), "+v"(a[2].re), "+v"(a[2].im),
+                     "+v"(a[3].re), "+v"(a[3].im), "+v"(a[4].re), "+v"(a[4].im), "+v"(a[5].re), "+v"(a[5].im)::"memory");
+        asm volatile("" : "+v"(a[6].re), "+v"(a[6].im), "+v"(a[7].re), "+v"(a[7].im), "+v"(a[8].re), "+v"(a[8].im),
+                     "+v"(a[9].re), "+v"(a[9].im), "+v"(a[10].re), "+v"(a[10].im), "+v"(a[11].re), "+v"(a[11].im)::"memory");
+    } else {
+        hop_fence();
+    }
 }
 
 // One work item: the 4 * RW right-hand sides of a tile on kLdsSites sites.
@@ -120,16 +139,16 @@ __device__ __forceinline__ void stage_lds_body(const StageArgs &A, int sb, int t
             // none), while the loads of later directions stay after its products
             lds_hop<P, 0, DAG, true>(src, g.vh, lnk, nbr, lane, A.one, acc);
             lds_hop<P, 0, DAG, false>(src, g.vh, lnk, nbr, lane, A.one, acc);
-            hop_fence();
+            phase_fence(acc);
             lds_hop<P, 1, DAG, true>(src, g.vh, lnk, nbr, lane, A.one, acc);
             lds_hop<P, 1, DAG, false>(src, g.vh, lnk, nbr, lane, A.one, acc);
-            hop_fence();
+            phase_fence(acc);
             lds_hop<P, 2, DAG, true>(src, g.vh, lnk, nbr, lane, A.one, acc);
             lds_hop<P, 2, DAG, false>(src, g.vh, lnk, nbr, lane, A.one, acc);
-            hop_fence();
+            phase_fence(acc);
             lds_hop<P, 3, DAG, true>(src, g.vh, lnk, nbr, lane, A.one, acc);
             lds_hop<P, 3, DAG, false>(src, g.vh, lnk, nbr, lane, A.one, acc);
-            hop_fence();
+            phase_fence(acc);
             if (PRE) {
                 cplx<R> zz[12];
                 SpinorIO<P>::load(A.z.at(slot), g.vh, h, zz);
@@ -144,10 +163,13 @@ __device__ __forceinline__ void stage_lds_body(const StageArgs &A, int sb, int t
                     R m[36];
                     CloverIO<P>::load(cl, blk, g.vh, h, m);
                     cplx<R> o[6];
-                    herm6_apply(m, &acc[6 * blk], o);
+                    if constexpr (sizeof(R) == 4)
+                        herm6_apply_fma(m, &acc[6 * blk], o);
+                    else
+                        herm6_apply(m, &acc[6 * blk], o);
 #pragma unroll
                     for (int i = 0; i < 6; ++i) acc[6 * blk + i] = o[i];
-                    hop_fence();
+                    phase_fence(acc);
                 }
             }
             cplx<R> res[12], yy[12];

@@ -74,6 +74,23 @@ __host__ __device__ __forceinline__ void cmac_conj(cplx<R> &a, cplx<R> b, cplx<R
     a.re += b.re * c.re + b.im * c.im;
     a.im += b.re * c.im - b.im * c.re;
 }
+// The same as chains of four fused multiply-adds: fewer instructions, but each
+// chain is serial, so the scheduler keeps more of them in flight; used where the
+// caller bounds the live registers (the LDS stencil form's fences).
+template <class R>
+__host__ __device__ __forceinline__ void cfma(cplx<R> &a, cplx<R> b, cplx<R> c) {
+    a.re = ffma(b.re, c.re, a.re);
+    a.re = ffma(-b.im, c.im, a.re);
+    a.im = ffma(b.re, c.im, a.im);
+    a.im = ffma(b.im, c.re, a.im);
+}
+template <class R>
+__host__ __device__ __forceinline__ void cfma_conj(cplx<R> &a, cplx<R> b, cplx<R> c) {
+    a.re = ffma(b.re, c.re, a.re);
+    a.re = ffma(b.im, c.im, a.re);
+    a.im = ffma(b.re, c.im, a.im);
+    a.im = ffma(-b.im, c.re, a.im);
+}
 // b * c and conj(b) * c (one multiply and three fused multiply-adds)
 template <class R>
 __host__ __device__ __forceinline__ cplx<R> cmul1(cplx<R> b, cplx<R> c) {
@@ -360,6 +377,24 @@ __device__ __forceinline__ void herm6_apply(const R (&m)[36], const cplx<R> *x, 
             cplx<R> l = {m[6 + 2 * k], m[7 + 2 * k]};
             cmac(y[i], l, x[j]);
             cmac_conj(y[j], l, x[i]);
+            ++k;
+        }
+    }
+}
+
+// herm6_apply with the multiply-adds as fused chains (see cfma)
+template <class R>
+__device__ __forceinline__ void herm6_apply_fma(const R (&m)[36], const cplx<R> *x, cplx<R> *y) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) y[i] = m[i] * x[i];
+    int k = 0;
+#pragma unroll
+    for (int i = 1; i < 6; ++i) {
+#pragma unroll
+        for (int j = 0; j < i; ++j) {
+            cplx<R> l = {m[6 + 2 * k], m[7 + 2 * k]};
+            cfma(y[i], l, x[j]);
+            cfma_conj(y[j], l, x[i]);
             ++k;
         }
     }
