@@ -386,6 +386,18 @@ def copy_peak(lat, torch, gib=4):
     return 2.0 * (gib << 30) / (ms * 1e-3) / 1e9, ms
 
 
+def copy_same_bytes_ms(lat, torch, nbytes, reps=10):
+    """ms of the library's streaming copy that reads and writes nbytes in all (nbytes / 2
+    each way): the ceiling for a bandwidth-bound launch moving the same bytes, launch and
+    ramp included."""
+    n = max(16, (int(nbytes) // 2) // 16 * 16) // 4
+    xa = torch.empty(n, dtype=torch.float32, device="cuda").fill_(1.0)
+    xb = torch.empty_like(xa)
+    ms = lat.stream_copy(xb, xa, reps=reps)
+    del xa, xb
+    return ms
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -549,11 +561,21 @@ def main():
 
     # the stencil at small batches: HBM-bound at one RHS, near the FP32 ridge by eight
     # (algorithmic bytes and flops / time; counter bytes where committed for this build)
+    # of_copy_same_bytes: against a copy of the same algorithmic bytes (a 0.1-1 ms launch
+    # does not reach the 4 GiB copy's rate: launch and ramp are a larger share)
     dslash = {"copy_kernel_gbs": round(copy_gbs, 1)}
     for sh in PROBE_SHAPES[1:]:
         m1, m2 = lat.time_stages(sh[0], sh[1], sh[3], 0, reps=10, stencil=sh[2], traversal=sh[4])
-        dslash["%s_nrhs%d" % (sh[0], sh[1])] = {"stage1": stage_figures(m1, 1, sh)[0],
-                                                "stage2": stage_figures(m2, 2, sh)[0]}
+        lat.release_scratch()
+        entry = {}
+        for st, ms in ((1, m1), (2, m2)):
+            f = stage_figures(ms, st, sh)[0]
+            cms = copy_same_bytes_ms(lat, torch, f["algorithmic_bytes"])
+            f["copy_same_bytes_ms"] = round(cms, 4)
+            f["of_copy_same_bytes"] = round(cms / ms, 4)
+            entry["stage%d" % st] = f
+        dslash["%s_nrhs%d" % (sh[0], sh[1])] = entry
+    torch.cuda.empty_cache()
 
     out = {
         "metric": "perambulator RHS solved/s at rel. residual 1e-10; Dslash HBM GB/s vs peak",
