@@ -432,7 +432,9 @@ typedef struct {
  * coarse_iters 16, coarse_tol 0.1, restart 8, maxiter 500. */
 void laph_mg_default_params(laph_mg_params *p);
 /* Bytes of the caller's multigrid buffer (basis: nvec full FP64 fields; coarse matrix)
- * and of the setup workspace; 0 for invalid parameters. */
+ * and of the setup workspace (the inverse-iteration solves, then an aggregate-major copy
+ * of the basis for the coarse-matrix build: at least nvec full FP64 fields); 0 for
+ * invalid parameters. */
 size_t laph_mg_state_bytes(laph_ctx ctx, const laph_mg_params *p);
 size_t laph_mg_setup_workspace_bytes(laph_ctx ctx, const laph_mg_params *p);
 /* Build the multigrid of mass mass_idx from V0 (device, nvec canonical complex128 spinor

@@ -944,7 +944,7 @@ laph_status laph_mg_setup(laph_ctx h, int mass_idx, const laph_mg_params *p, con
     MgGeom g;
     LAPH_TRY(mg_params_geo(c, p, g));
     if (!V0 || !state) return set_error(LAPH_ERR_INVALID, "null start vectors or multigrid buffer");
-    if (!work && p->null_passes > 0) return set_error(LAPH_ERR_WORKSPACE, "multigrid setup needs a workspace");
+    if (!work) return set_error(LAPH_ERR_WORKSPACE, "multigrid setup needs a workspace");
     LAPH_TRY(mg_setup(c, mass_idx, g, V0, p->null_passes, p->null_tol, reinterpret_cast<char *>(state), state_bytes,
                       reinterpret_cast<char *>(work), work ? work_bytes : 0));
     c.mgs.smooth_iters = p->smooth_iters;

@@ -126,12 +126,14 @@ __device__ __forceinline__ void block_sum_bcast(double (&v)[N], double *red) {
     __syncthreads();
 }
 
-// Wave reduction of 64 values per lane that leaves lane l with the wave's sum of
-// v[l] (a transposing butterfly: each step a lane keeps half of its values and adds
-// its partner's matching half, 63 exchanges in all instead of 6 per value).
-__device__ __forceinline__ double wave_transpose_sum64(double (&v)[64], int lane) {
+// Wave reduction of N values per lane (N a power of two, <= 64) that leaves lane l
+// with the wave's sum of v[l % N]: a transposing butterfly inside groups of N lanes
+// (each step a lane keeps half of its values and adds its partner's matching half,
+// N - 1 exchanges instead of log2(64) per value), then plain steps add the 64 / N groups.
+template <int N>
+__device__ __forceinline__ double wave_transpose_sum(double (&v)[N], int lane) {
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
+    for (int o = N / 2; o >= 1; o >>= 1) {
         const bool up = (lane & o) != 0;
 #pragma unroll
         for (int i = 0; i < o; ++i) {
@@ -140,7 +142,10 @@ __device__ __forceinline__ double wave_transpose_sum64(double (&v)[64], int lane
             v[i] = keep + __shfl_xor(send, o, 64);
         }
     }
-    return v[0];
+    double s = v[0];
+#pragma unroll
+    for (int o = 32; o >= N; o >>= 1) s += __shfl_xor(s, o, 64);
+    return s;
 }
 
 __device__ __forceinline__ double2 ld2(const char *hv, int vh, int c, int h) {
@@ -280,6 +285,16 @@ __device__ __forceinline__ void coarse_hop(const Geom &g, const GaugePtrs &gp, c
     spin_accumulate<MU, S>(y, u, -0.5 * eta);
 }
 
+// Compiler barrier of the coarse build: y is complete here and no memory access moves
+// across, so the loads of one hop direction are live at a time (without it the kernel
+// kept every direction's link and neighbour in flight: 492 VGPRs and spills).
+__device__ __forceinline__ void build_fence(cplx<double> (&y)[12]) {
+    asm volatile("" : "+v"(y[0].re), "+v"(y[0].im), "+v"(y[1].re), "+v"(y[1].im), "+v"(y[2].re), "+v"(y[2].im),
+                 "+v"(y[3].re), "+v"(y[3].im), "+v"(y[4].re), "+v"(y[4].im), "+v"(y[5].re), "+v"(y[5].im)::"memory");
+    asm volatile("" : "+v"(y[6].re), "+v"(y[6].im), "+v"(y[7].re), "+v"(y[7].im), "+v"(y[8].re), "+v"(y[8].im),
+                 "+v"(y[9].re), "+v"(y[9].im), "+v"(y[10].re), "+v"(y[10].im), "+v"(y[11].re), "+v"(y[11].im)::"memory");
+}
+
 template <int MU>
 __device__ __forceinline__ void coarse_dir(const Geom &g, const GaugePtrs &gp, const MgDev &m, const char *bj,
                                            size_t half, int chi, const int (&xs)[4], int p, int h, int d,
@@ -287,16 +302,36 @@ __device__ __forceinline__ void coarse_dir(const Geom &g, const GaugePtrs &gp, c
     const int b = MU == 0 ? m.bx : (MU == 1 ? m.by : (MU == 2 ? m.bz : m.bt));
     const bool cross_f = (xs[MU] % b) == b - 1, cross_b = (xs[MU] % b) == 0;
     if ((d == 0 && !cross_f) || (d == 1 + 2 * MU && cross_f)) coarse_hop<MU, true>(g, gp, bj, half, chi, xs, p, h, y);
+    build_fence(y);
     if ((d == 0 && !cross_b) || (d == 2 + 2 * MU && cross_b)) coarse_hop<MU, false>(g, gp, bj, half, chi, xs, p, h, y);
+}
+
+// Aggregate-major copy of the basis for the coarse build:
+// wagg[((a nv + i) 12 + c) asize + k] = component c of w_i at site k of aggregate a, so that
+// the build's dot products read each (i, c) as one contiguous row across the aggregate's
+// threads (the field layout scatters an aggregate's sites over many cache lines).
+// Grid (nc, nv); one thread per site of the aggregate (asize <= kMB).
+__global__ __launch_bounds__(kMB) void mg_agg_pack_kernel(Geom g, MgDev m, const char *basis, size_t bstride,
+                                                          size_t half, double2 *wagg) {
+    const int a = blockIdx.x, i = blockIdx.y, k = threadIdx.x;
+    if (k >= m.asize) return;
+    int x, y, z, t;
+    agg_site(m, a, k, x, y, z, t);
+    const int p = (x + y + z + t) & 1;
+    const int h = cb_index(g, x, y, z, t);
+    const char *bi = basis + (size_t)i * bstride + p * half;
+    double2 *out = wagg + ((size_t)a * m.nv + i) * 12 * m.asize + k;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) out[(size_t)c * m.asize] = ld2(bi, g.vh, c, h);
 }
 
 // D_c[a][d][(chi, i)][(chi', j)] = sum_{x in a} <w_(chi,i)(x), (D^(d) P_chi' w_j)(x)>, where D^(0)
 // holds the clover term and the hops inside the aggregate and D^(d) (d > 0) the hop
 // that leaves it in direction d.  Grid nc; one thread per fine site (asize <= kMB).
 __global__ __launch_bounds__(kMB) void mg_coarse_build_kernel(Geom g, GaugePtrs gp, MgDev m, const char *basis,
-                                                              size_t bstride, size_t half, const char *cterm0,
-                                                              const char *cterm1, const double *diag, int mass,
-                                                              double2 *C) {
+                                                              size_t bstride, size_t half, const double2 *wagg,
+                                                              const char *cterm0, const char *cterm1,
+                                                              const double *diag, int mass, double2 *C) {
     __shared__ double red[(kMB / 64) * 4 * kMgMaxVec];
     const int a = blockIdx.x;
     const int k = threadIdx.x;
@@ -308,10 +343,17 @@ __global__ __launch_bounds__(kMB) void mg_coarse_build_kernel(Geom g, GaugePtrs 
         h = cb_index(g, xs[0], xs[1], xs[2], xs[3]);
     }
     const double dg = diag[mass];
+#pragma unroll 1
     for (int j = 0; j < m.nv; ++j) {
         const char *bj = basis + (size_t)j * bstride;
+#pragma unroll 1
         for (int chi2 = 0; chi2 < 2; ++chi2) {
+#pragma unroll 1
             for (int d = 0; d < 9; ++d) {
+                // the site's coordinates are opaque per iteration: the neighbour and link
+                // addresses derived from them are recomputed here instead of being hoisted
+                // out of the loops and held in registers (hundreds of VGPRs)
+                asm volatile("" : "+v"(h), "+v"(p), "+v"(xs[0]), "+v"(xs[1]), "+v"(xs[2]), "+v"(xs[3]));
                 cplx<double> y[12];
 #pragma unroll
                 for (int c = 0; c < 12; ++c) y[c] = {0.0, 0.0};
@@ -321,45 +363,64 @@ __global__ __launch_bounds__(kMB) void mg_coarse_build_kernel(Geom g, GaugePtrs 
                         load_chiral(bj, half, g.vh, p, h, chi2, v);
                         double mm[36];
                         CloverIO<F64>::load(p == 0 ? cterm0 : cterm1, chi2, g.vh, h, mm);
-                        herm6_apply(mm, &v[6 * chi2], &y[6 * chi2], dg);
+                        // constant offsets keep v and y in registers
+                        if (chi2 == 0)
+                            herm6_apply(mm, &v[0], &y[0], dg);
+                        else
+                            herm6_apply(mm, &v[6], &y[6], dg);
                     }
+                    build_fence(y);
                     coarse_dir<0>(g, gp, m, bj, half, chi2, xs, p, h, d, y);
+                    build_fence(y);
                     coarse_dir<1>(g, gp, m, bj, half, chi2, xs, p, h, d, y);
+                    build_fence(y);
                     coarse_dir<2>(g, gp, m, bj, half, chi2, xs, p, h, d, y);
+                    build_fence(y);
                     coarse_dir<3>(g, gp, m, bj, half, chi2, xs, p, h, d, y);
+                    build_fence(y);
                 }
-                // dots with every basis vector i, both chiralities: [i][chi][re, im]
-                double acc[4 * kMgMaxVec];
+                // dots with every basis vector i, both chiralities, four vectors at a time
+                // (16 values [i][chi][re, im] per lane keep the register count low): lane
+                // q < 16 of every wave holds its wave's sum of value q, thread q adds the
+                // four waves in order
+                const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+                const double2 *wa = wagg + (size_t)a * m.nv * 12 * m.asize + k;
+#pragma unroll 1
+                for (int i0 = 0; i0 < m.nv; i0 += 4) {
+                    double acc[16];
 #pragma unroll
-                for (int q = 0; q < 4 * kMgMaxVec; ++q) acc[q] = 0.0;
-                if (own) {
+                    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+                    if (own) {
 #pragma unroll
-                    for (int i = 0; i < kMgMaxVec; ++i) {
-                        if (i < m.nv) {
-                            const char *bi = basis + (size_t)i * bstride + p * half;
+                        for (int ii = 0; ii < 4; ++ii) {
+                            if (i0 + ii < m.nv) {
 #pragma unroll
-                            for (int c = 0; c < 12; ++c) {
-                                const double2 w = ld2(bi, g.vh, c, h);
-                                const int q = 4 * i + 2 * (c / 6);
-                                acc[q] += w.x * y[c].re + w.y * y[c].im;
-                                acc[q + 1] += w.x * y[c].im - w.y * y[c].re;
+                                for (int c = 0; c < 12; ++c) {
+                                    const double2 w = wa[((size_t)(i0 + ii) * 12 + c) * m.asize];
+                                    const int q = 4 * ii + 2 * (c / 6);
+                                    acc[q] += w.x * y[c].re + w.y * y[c].im;
+                                    acc[q + 1] += w.x * y[c].im - w.y * y[c].re;
+                                }
                             }
+                            // one basis vector's loads in flight at a time
+                            asm volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]),
+                                         "+v"(acc[5]), "+v"(acc[6]), "+v"(acc[7])::"memory");
+                            asm volatile("" : "+v"(acc[8]), "+v"(acc[9]), "+v"(acc[10]), "+v"(acc[11]),
+                                         "+v"(acc[12]), "+v"(acc[13]), "+v"(acc[14]), "+v"(acc[15])::"memory");
                         }
                     }
+                    red[wave * 64 + lane] = wave_transpose_sum<16>(acc, lane);
+                    __syncthreads();
+                    if (threadIdx.x < 16 && i0 + (threadIdx.x >> 2) < m.nv) {
+                        const int q = threadIdx.x, i = i0 + (q >> 2), chi = (q >> 1) & 1;
+                        double sum = 0;
+                        for (int wv = 0; wv < kMB / 64; ++wv) sum += red[wv * 64 + q];
+                        const size_t row = (size_t)chi * m.nv + i, col = (size_t)chi2 * m.nv + j;
+                        reinterpret_cast<double *>(C)[((((size_t)a * 9 + d) * m.ncv + row) * m.ncv + col) * 2 +
+                                                      (q & 1)] = sum;
+                    }
+                    __syncthreads();
                 }
-                // value q = 4 i + 2 chi + (0: re, 1: im) summed over the block: lane q of
-                // every wave holds its wave's sum, thread q adds the four waves in order
-                const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-                red[wave * 64 + lane] = wave_transpose_sum64(acc, lane);
-                __syncthreads();
-                if (threadIdx.x < 4 * m.nv) {
-                    const int q = threadIdx.x, i = q >> 2, chi = (q >> 1) & 1;
-                    double sum = 0;
-                    for (int wv = 0; wv < kMB / 64; ++wv) sum += red[wv * 64 + q];
-                    const size_t row = (size_t)chi * m.nv + i, col = (size_t)chi2 * m.nv + j;
-                    reinterpret_cast<double *>(C)[((((size_t)a * 9 + d) * m.ncv + row) * m.ncv + col) * 2 + (q & 1)] = sum;
-                }
-                __syncthreads();
             }
         }
     }
@@ -1053,9 +1114,11 @@ size_t mg_state_bytes(const Ctx &c, const MgGeom &g) {
     return (size_t)g.nv * full64(c) + (size_t)g.nv * full32(c) + coarse_bytes(g) + 256;
 }
 
+// The inverse-iteration solves, then (reusing the same bytes) the aggregate-major
+// basis copy of the coarse build, nv full fields of FP64.
 size_t mg_setup_workspace_bytes(const Ctx &c, const MgGeom &g, int null_passes) {
-    if (null_passes <= 0) return 256;
     const size_t canon = round256((size_t)g.nv * 2 * c.g.vh * 12 * sizeof(double2));
+    if (null_passes <= 0) return canon;
     laph_solve_params p;
     laph_default_params(&p);
     p.inner_prec = LAPH_F32;
@@ -1123,9 +1186,14 @@ laph_status mg_setup(Ctx &c, int mass_idx, const MgGeom &g, const double *V0, in
                        c.g.vh, c.hv(LAPH_F64), c.hv(LAPH_F32), Operand{s.basis32, s.basis32_stride},
                        Operand{s.basis, s.basis_stride});
     LAPH_TRY(check_launch("mg_convert_kernel"));
+    // the solves are done: the workspace now holds the aggregate-major basis copy
+    double2 *wagg = reinterpret_cast<double2 *>(work);
+    hipLaunchKernelGGL(mg_agg_pack_kernel, dim3(g.nc, g.nv), dim3(kMB), 0, c.stream, c.g, m, (const char *)s.basis,
+                       s.basis_stride, c.hv(LAPH_F64), wagg);
+    LAPH_TRY(check_launch("mg_agg_pack_kernel"));
     hipLaunchKernelGGL(mg_coarse_build_kernel, dim3(g.nc), dim3(kMB), 0, c.stream, c.g, c.gp, m,
-                       (const char *)s.basis, s.basis_stride, c.hv(LAPH_F64), c.clover_term(0), c.clover_term(1),
-                       (const double *)c.mass_diag(), mass_idx, s.coarse);
+                       (const char *)s.basis, s.basis_stride, c.hv(LAPH_F64), (const double2 *)wagg,
+                       c.clover_term(0), c.clover_term(1), (const double *)c.mass_diag(), mass_idx, s.coarse);
     LAPH_TRY(check_launch("mg_coarse_build_kernel"));
     int flag = 0;
     LAPH_HIP(hipMemcpyAsync(&flag, s.flag, sizeof(int), hipMemcpyDeviceToHost, c.stream));
