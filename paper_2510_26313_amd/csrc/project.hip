@@ -53,15 +53,18 @@ __global__ void laph_sources_kernel(Geom g, Operand E, Operand O, const double2 
     site_coords(g, p, h, x, y, z, t);
     const int r = r_begin + s;
     const int alpha = r & 3;
-    cplx<double> out[12];
-#pragma unroll
-    for (int c = 0; c < 12; ++c) out[c] = {0.0, 0.0};
+    cplx<double> col[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
     if (t == t0) {
         const size_t site3 = (size_t)x + (size_t)g.lx * (y + (size_t)g.ly * z);
         const size_t v3 = (size_t)g.lx * g.ly * g.lz;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) out[3 * alpha + a] = source_colour(V, rho, nev, n_dil, v3, t0, site3, r, a);
+        for (int a = 0; a < 3; ++a) col[a] = source_colour(V, rho, nev, n_dil, v3, t0, site3, r, a);
     }
+    // spin alpha carries the colours (selected per component: a runtime index into the
+    // spinor would put it in scratch memory)
+    cplx<double> out[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) out[c] = (c / 3 == alpha) ? col[c % 3] : cplx<double>{0.0, 0.0};
     SpinorIO<F64>::store((p == 0 ? E : O).at(s), g.vh, h, out);
 }
 
