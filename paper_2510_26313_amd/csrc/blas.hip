@@ -208,12 +208,14 @@ __global__ __launch_bounds__(kB) void lower_kernel(BlasArgs A, int mode, int ini
     }
 }
 
-// |v|^2 of one or two FP64 half-vectors per slot (partials q = 0)
+// |v|^2 of one or two FP64 half-vectors per slot (partials q = 0); sites outside
+// the window are not read (the vectors are zero there)
 __global__ __launch_bounds__(kB) void norm2_kernel(BlasArgs A, Operand v1, Operand v2, int mode) {
     const int h = blockIdx.x * kB + threadIdx.x;
+    const bool live = h < A.vh && in_window(A.win, h, A.vh);
     LAPH_FOR_SLOTS(A, mode, s) {
         double part[1] = {0};
-        if (h < A.vh) {
+        if (live) {
             cplx<double> y[12];
             SpinorIO<F64>::load(v1.at(s), A.vh, h, y);
             double n2 = 0;
@@ -230,13 +232,19 @@ __global__ __launch_bounds__(kB) void norm2_kernel(BlasArgs A, Operand v1, Opera
     }
 }
 
-// dst = src (FP64 half-vectors) per slot
+// dst = src (FP64 half-vectors) per slot; outside the window src is zero and not read
 __global__ __launch_bounds__(kB) void copy64_kernel(BlasArgs A, Operand dst, Operand src, int mode) {
     const int h = blockIdx.x * kB + threadIdx.x;
     if (h >= A.vh) return;
+    const bool live = in_window(A.win, h, A.vh);
     LAPH_FOR_SLOTS(A, mode, s) {
         cplx<double> y[12];
-        SpinorIO<F64>::load(src.at(s), A.vh, h, y);
+        if (live) {
+            SpinorIO<F64>::load(src.at(s), A.vh, h, y);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) y[c] = {0.0, 0.0};
+        }
         SpinorIO<F64>::store(dst.at(s), A.vh, h, y);
     }
 }

@@ -56,12 +56,15 @@ laph_status launch_stage(const Ctx &c, const StageSpec &s) {
     a.grid_cap = s.grid_cap;
     lds_block_tiles(c, s, a);
     a.dispatch_order = s.form == kFormLds ? 1 : 0;
+    a.win = s.win;
     a.flag_filter = s.flagged;
     a.one = 1.0f;
     a.st = s.slots;
     a.partials = s.partials;
     if (a.ntiles_max <= 0) return LAPH_OK;
     if (s.red && s.pstride < a.nsb) return set_error(LAPH_ERR_INVALID, "partial-sum stride too small");
+    // a skipped site block would leave its partial sums unwritten
+    if (s.red && s.win.n > 0) return set_error(LAPH_ERR_INVALID, "site window on a reducing stage");
     bool ok = false;
     if (s.form == kFormLds) {
         if (s.prec == LAPH_F64)
@@ -96,6 +99,7 @@ struct CloverArgs {
     const int *slot_mass;
     int mass_idx;
     int n;
+    SiteWindow win;            // sites computed (the others untouched)
 };
 
 // One thread per site; a block row takes kCloverRhs RHS in turn, so the clover
@@ -107,7 +111,7 @@ template <class P, bool POST>
 __global__ __launch_bounds__(kBlock) void clover_kernel(CloverArgs A) {
     using R = typename P::real;
     const int h = blockIdx.x * kBlock + threadIdx.x;
-    if (h >= A.vh) return;
+    if (h >= A.vh || !in_window(A.win, h, A.vh)) return;
 #pragma unroll 1
     for (int jj = 0; jj < kCloverRhs; ++jj) {
         const int j = blockIdx.y * kCloverRhs + jj;
@@ -162,6 +166,7 @@ laph_status launch_clover(const Ctx &c, const CloverSpec &s) {
     a.slot_mass = s.slot_mass;
     a.mass_idx = s.mass_idx;
     a.n = s.n;
+    a.win = s.win;
     dim3 grid((c.g.vh + kBlock - 1) / kBlock, (s.n + kCloverRhs - 1) / kCloverRhs);
 #define LAPH_CL(PT)                                                                                   \
     if (s.post)                                                                                       \

@@ -54,6 +54,7 @@ struct StageArgs {
     // tz z-planes x tt timeslices); tz == 0: memory order
     int nyb, tz, tt;
     int dispatch_order;   // 1: items in dispatch order (see stage_item_range); 0: per-XCD ranges
+    SiteWindow win;       // output sites computed; the others are neither read nor written
 };
 
 // Work items of a stage launch are (site block, tile) pairs of the live tiles:
@@ -356,9 +357,10 @@ __device__ __forceinline__ void stage_body(const StageArgs &A, int sb, int tile)
     }
     if (!any) return;
     const Geom &g = A.g;
+    if (block_outside(A.win, sb * kBlock, min(kBlock, g.vh - sb * kBlock), g.vh)) return;   // uniform
     const int p = A.out_parity;
     const int h = sb * kBlock + threadIdx.x;
-    const bool valid = h < g.vh;
+    const bool valid = h < g.vh && in_window(A.win, h, g.vh);
     constexpr int NQ = RED == 1 ? 2 : (RED == 2 ? 3 : (RED == 3 ? 1 : 0));
     double part[NR][NQ > 0 ? NQ : 1];
 #pragma unroll

@@ -68,7 +68,7 @@ __device__ __forceinline__ void stage_lds_body(const StageArgs &A, int sb, int t
     const int p = A.out_parity;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int h = sb * kLdsSites + lane;
-    const bool valid = h < g.vh;
+    const bool valid = h < g.vh && in_window(A.win, h, g.vh);
     // ---- phase 1: neighbours and links of the 64 sites (wave w: hops 2w, 2w+1 = mu w fwd / bwd)
     {
         int x = 0, y = 0, z = 0, t = 0;
@@ -237,7 +237,9 @@ __global__ __launch_bounds__(256) void stage_lds_kernel(StageArgs A) {
     for (int w = first; w < end; w += step) {
         int sb, tile;
         stage_item(w, A.site_major, A.nsb, nt, sb, tile);
-        stage_lds_body<P, RW, DAG, CLOVER, PRE, POST, RED>(A, tiled_block(sb, A.nyb, A.tz, A.tt, A.g.lz), tile);
+        sb = tiled_block(sb, A.nyb, A.tz, A.tt, A.g.lz);
+        if (block_outside(A.win, sb * kLdsSites, min(kLdsSites, A.g.vh - sb * kLdsSites), A.g.vh)) continue;
+        stage_lds_body<P, RW, DAG, CLOVER, PRE, POST, RED>(A, sb, tile);
         __syncthreads();   // the next item stages its links in the same LDS
     }
 }

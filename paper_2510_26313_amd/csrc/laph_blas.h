@@ -21,6 +21,7 @@ struct BlasArgs {
     Operand x64, r64;            // FP64 solution and residual
     const int *flist = nullptr;  // flagged mode: slots taking a reliable update
     const int *nflist = nullptr; // device scalar: entries of flist
+    SiteWindow win;              // norm2 / copy64: the sources are zero outside it (not read)
 };
 
 // Input / output of the flagged-slot compaction (blas_flag_tiles).

@@ -160,6 +160,7 @@ struct StageSpec {
     const SlotState *slots = nullptr;   // may be null when flagged == 0
     double *partials = nullptr;         // [slot][3][pstride]
     int pstride = 0;                    // partials per quantity per slot (>= stage_nsb)
+    SiteWindow win;                     // output sites computed (the others untouched); red == 0 only
 };
 // site blocks of a stage launch (= partial sums it writes per quantity and slot)
 int stage_nsb(const Ctx &c, int form);
@@ -180,6 +181,7 @@ struct CloverSpec {
     const int *slot_mass = nullptr;   // [slot] mass index (null: mass_idx for all)
     int mass_idx = 0;
     int n = 0;
+    SiteWindow win;                   // sites computed (the others untouched)
 };
 laph_status launch_clover(const Ctx &c, const CloverSpec &s);
 

@@ -131,6 +131,38 @@ __device__ __forceinline__ int cb_index(const Geom &g, int x, int y, int z, int 
     return (x + g.lx * (y + g.ly * (z + g.lz * t))) >> 1;
 }
 
+// A cyclic range [lo, lo + n) mod vh of checkerboard site indices.  In either parity
+// the sites of one timeslice t are h = t vs_h .. (t + 1) vs_h - 1, so a slab of
+// consecutive timeslices is one such range.  n <= 0: every site.
+struct SiteWindow {
+    int lo = 0;
+    int n = 0;
+};
+
+__host__ __device__ inline bool in_window(const SiteWindow &w, int h, int vh) {
+    if (w.n <= 0) return true;
+    int d = h - w.lo;
+    if (d < 0) d += vh;
+    return d < w.n;
+}
+
+// no site of [h0, h0 + cnt) (all inside 0 .. vh-1) lies in the window
+__host__ __device__ inline bool block_outside(const SiteWindow &w, int h0, int cnt, int vh) {
+    if (w.n <= 0) return false;
+    int d = h0 - w.lo;
+    if (d < 0) d += vh;
+    return d >= w.n && d + cnt <= vh;
+}
+
+// the timeslices t0 - k .. t0 + k (periodic in t); every site when they cover the lattice
+inline SiteWindow slab_window(const Geom &g, int t0, int k) {
+    SiteWindow w;
+    if (2 * k + 1 >= g.lt) return w;
+    w.lo = ((t0 - k) % g.lt + g.lt) % g.lt * g.vs_h;
+    w.n = (2 * k + 1) * g.vs_h;
+    return w;
+}
+
 // ---------------------------------------------------------------------------
 // precisions
 // ---------------------------------------------------------------------------

@@ -116,9 +116,10 @@ class Solver {
     laph_status download_state();
     laph_status upload_state();
     laph_status stage(int sprec, int out_parity, Operand in, Operand out, int clover, int pre, Operand z, double cz,
-                      int post, Operand y, double a, Operand y2, double a2, double b, int red, Operand w, int flagged);
+                      int post, Operand y, double a, Operand y2, double a2, double b, int red, Operand w, int flagged,
+                      SiteWindow win = SiteWindow());
     laph_status clover(int parity, int inverse, Operand in, Operand out, int post, Operand y, double a, double b,
-                       int nlist);
+                       int nlist, SiteWindow win = SiteWindow());
     laph_status iteration();
     laph_status run_iterations(int k);
     laph_status load_sources(const SourceSpec &src);

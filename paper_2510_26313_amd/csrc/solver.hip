@@ -305,7 +305,7 @@ constexpr int kFlaggedGrid = 2048;
 
 laph_status Solver::stage(int sprec, int out_parity, Operand in, Operand out, int clover, int pre, Operand z,
                           double cz, int post, Operand y, double a, Operand y2, double a2, double b, int red,
-                          Operand w, int flagged) {
+                          Operand w, int flagged, SiteWindow win) {
     StageSpec s;
     s.prec = sprec;
     s.out_parity = out_parity;
@@ -334,11 +334,12 @@ laph_status Solver::stage(int sprec, int out_parity, Operand in, Operand out, in
     s.slots = ws.st;
     s.partials = ws.partials;
     s.pstride = pstride;
+    s.win = win;
     return launch_stage(*c, s);
 }
 
 laph_status Solver::clover(int parity, int inverse, Operand in, Operand out, int post, Operand y, double a, double b,
-                           int nlist) {
+                           int nlist, SiteWindow win) {
     CloverSpec s;
     s.prec = LAPH_F64;
     s.parity = parity;
@@ -352,6 +353,7 @@ laph_status Solver::clover(int parity, int inverse, Operand in, Operand out, int
     s.slot_list = ws.list;
     s.slot_mass = ws.slot_mass;
     s.n = nlist;
+    s.win = win;
     return launch_clover(*c, s);
 }
 
@@ -467,9 +469,19 @@ laph_status Solver::solve(const SourceSpec &src, const std::vector<int> &slot_ma
     LAPH_TRY(upload_state());
     BlasArgs a = blas(n);
     FinArgs f = fin(n);
+    // LapH and noise sources live on timeslice t0 alone, so the source preparation
+    // touches only a slab around it: A_oo^-1 b_o is computed on t0 +- 2 (the slices the
+    // next stage reads; zero but for t0), b_hat on t0 +- 1 (E0 keeps the zeros the
+    // sources put elsewhere), and |B|^2 and the copy r64 = b_hat read only those slices
+    const bool slab = src.B == nullptr && src.V != nullptr;
+    const SiteWindow w_src = slab ? slab_window(c->g, src.t0, 0) : SiteWindow();
+    const SiteWindow w_hat = slab ? slab_window(c->g, src.t0, 1) : SiteWindow();
+    const SiteWindow w_clv = slab ? slab_window(c->g, src.t0, 2) : SiteWindow();
     // |B|^2 and the stopping threshold on the even-odd residual
     LAPH_TRY(load_sources(src));
-    LAPH_TRY(blas_norm2(*c, a, ws.E0, ws.O1, kModeAll));
+    BlasArgs a_src = a;
+    a_src.win = w_src;
+    LAPH_TRY(blas_norm2(*c, a_src, ws.E0, ws.O1, kModeAll));
     LAPH_TRY(blas_finalize(*c, f, kFinBnorm));
     LAPH_TRY(download_state());
     // |B - D X| = |A_ee r_e| for an exactly reconstructed odd half; 0.2 covers |A_ee| <~ 5
@@ -491,15 +503,17 @@ laph_status Solver::solve(const SourceSpec &src, const std::vector<int> &slot_ma
         a = blas(ncur);
         f = fin(ncur);
         // prepared source b_hat = A_ee^-1 (b_e + 1/2 H_eo A_oo^-1 b_o) in E0 (O0 scratch)
-        LAPH_TRY(clover(1, 1, ws.O1, ws.O0, 0, none, 0, 1.0, ncur));
-        LAPH_TRY(stage(LAPH_F64, 0, ws.O0, ws.E0, 1, 1, ws.E0, 2.0, 0, none, 0, none, 0, 0.5, 0, none, 0));
+        LAPH_TRY(clover(1, 1, ws.O1, ws.O0, 0, none, 0, 1.0, ncur, w_clv));
+        LAPH_TRY(stage(LAPH_F64, 0, ws.O0, ws.E0, 1, 1, ws.E0, 2.0, 0, none, 0, none, 0, 0.5, 0, none, 0, w_hat));
         // r64 = b_hat - M_hat x64
         if (have_x) {
             LAPH_TRY(stage(LAPH_F64, 1, ws.E1, ws.O0, 1, 0, none, 0, 0, none, 0, none, 0, 1.0, 0, none, 0));
             LAPH_TRY(stage(LAPH_F64, 0, ws.O0, ws.E2, 1, 0, none, 0, 2, ws.E0, 1.0, ws.E1, -1.0, 0.25, 3, none, 0));
         } else {
-            LAPH_TRY(blas_copy64(*c, a, ws.E2, ws.E0, kModeActive));
-            LAPH_TRY(blas_norm2(*c, a, ws.E2, none, kModeActive));
+            BlasArgs a_hat = a;
+            a_hat.win = w_hat;
+            LAPH_TRY(blas_copy64(*c, a_hat, ws.E2, ws.E0, kModeActive));
+            LAPH_TRY(blas_norm2(*c, a_hat, ws.E2, none, kModeActive));
         }
         // partials of the FP64 stage (warm start) or of the norm kernel
         LAPH_TRY(blas_finalize(*c, have_x ? fin(ncur, nsb64) : f, kFinR64));

@@ -356,14 +356,17 @@ def test_perambulator_4x4x4x4():
         assert rel(host(tau), tau_ref) < 1e-8
 
 
-def test_perambulator_ragged_chunks(ragged):
-    """nev = 5 (20 RHS) in chunks of 8: chunk boundaries cut a spin quartet."""
+@pytest.mark.parametrize("t0", [3, 9])
+def test_perambulator_ragged_chunks(ragged, t0):
+    """nev = 5 (20 RHS) in chunks of 8: chunk boundaries cut a spin quartet.  The source
+    preparation works on the timeslices around t0 only; t0 = 9 (the last of 10) takes
+    that slab across the periodic boundary."""
     import paper_2510_26313_amd as pl
     U, lat = ragged
     V = ls.orthonormal_laph_vectors(DIMS_RAGGED, 5, 2100)
-    tau_ref, _ = laph.perambulator(U, V, 3, 0.1, tol=1e-13)
-    log_case("perambulator_chunks")
-    tau, st = lat.perambulator_raw(dev(V), 3, 0, 1e-10, pl.default_params(inner_prec="f16n", chunk=8))
+    tau_ref, _ = laph.perambulator(U, V, t0, 0.1, tol=1e-13)
+    log_case("perambulator_chunks", t0=t0)
+    tau, st = lat.perambulator_raw(dev(V), t0, 0, 1e-10, pl.default_params(inner_prec="f16n", chunk=8))
     assert rel(host(tau), tau_ref) < 1e-8
     assert len(st) == 20 and all(s["status"] == "converged" for s in st)
 
