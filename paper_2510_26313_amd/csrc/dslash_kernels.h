@@ -55,6 +55,10 @@ struct StageArgs {
     int nyb, tz, tt;
     int dispatch_order;   // 1: items in dispatch order (see stage_item_range); 0: per-XCD ranges
     SiteWindow win;       // output sites computed; the others are neither read nor written
+    // reduction 4 (FP64 LDS form): the clover term of the output parity and the per-mass
+    // diagonal 4 + m0, for |v - A out|^2
+    const char *clover_term;
+    const double *diag;
 };
 
 // Work items of a stage launch are (site block, tile) pairs of the live tiles:

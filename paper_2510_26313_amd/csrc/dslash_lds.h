@@ -120,7 +120,8 @@ __device__ __forceinline__ void stage_lds_body(const StageArgs &A, int sb, int t
     }
     __syncthreads();
     // ---- phase 2: one RHS per wave per round
-    constexpr int NQ = RED == 1 ? 2 : (RED == 2 ? 3 : (RED == 3 ? 1 : 0));
+    constexpr int NQ = RED == 1 ? 2 : (RED == 2 ? 3 : (RED == 3 || RED == 4 ? 1 : 0));
+    static_assert(RED != 4 || (CLOVER && POST == 0 && sizeof(R) == 8), "reduction 4: FP64 clover stages");
 #pragma unroll 1
     for (int rw = 0; rw < RW; ++rw) {
         const int slot = A.tile_slots[tile * NT + rw * 4 + wave];
@@ -156,6 +157,7 @@ __device__ __forceinline__ void stage_lds_body(const StageArgs &A, int sb, int t
 #pragma unroll
                 for (int c = 0; c < 12; ++c) acc[c] = acc[c] + cz * zz[c];
             }
+            R n2res = R(0);   // reduction 4
             if (CLOVER) {
                 const char *cl = A.clover + (size_t)A.tile_mass[tile] * A.clover_mass_stride;
 #pragma unroll
@@ -167,6 +169,29 @@ __device__ __forceinline__ void stage_lds_body(const StageArgs &A, int sb, int t
                         herm6_apply_fma(m, &acc[6 * blk], o);
                     else
                         herm6_apply(m, &acc[6 * blk], o);
+                    if constexpr (RED == 4) {
+                        // this block of v = b (c z + H in) and of the output b A^-1 (c z + H in),
+                        // then |v - A out|^2 with the clover term A = (4 + m0) + C of the output
+                        // parity: the residual of a half reconstructed as out = A^-1 v
+                        // an opaque site index keeps the term's loads inside the RHS loop
+                        int ht = h;
+                        asm volatile("" : "+v"(ht));
+                        R mt[36];
+                        CloverIO<F64>::load(A.clover_term, blk, g.vh, ht, mt);
+                        const R bv = R(A.b), dg = R(A.diag[A.tile_mass[tile]]);
+                        cplx<R> vb[6], ob[6], q[6];
+#pragma unroll
+                        for (int i = 0; i < 6; ++i) {
+                            vb[i] = bv * acc[6 * blk + i];
+                            ob[i] = bv * o[i];
+                        }
+                        herm6_apply(mt, ob, q, dg);
+#pragma unroll
+                        for (int i = 0; i < 6; ++i) {
+                            const cplx<R> d = vb[i] - q[i];
+                            n2res += d.re * d.re + d.im * d.im;
+                        }
+                    }
 #pragma unroll
                     for (int i = 0; i < 6; ++i) acc[6 * blk + i] = o[i];
                     phase_fence(acc);
@@ -215,6 +240,8 @@ __device__ __forceinline__ void stage_lds_body(const StageArgs &A, int sb, int t
 #pragma unroll
                 for (int c = 0; c < 12; ++c) n2 += res[c].re * res[c].re + res[c].im * res[c].im;
                 part[0] = n2;
+            } else if (RED == 4) {
+                part[0] = n2res;
             }
         }
         if constexpr (NQ > 0) {
@@ -272,6 +299,7 @@ inline bool launch_lds_combo(const StageSpec &s, const StageArgs &a, hipStream_t
             case 13: launch_lds_t<P, RW, DAG, false, false, 1, 3>(a, st); return true;     // residual part
             case 1023: launch_lds_t<P, RW, DAG, true, false, 2, 3>(a, st); return true;    // r64, |r64|^2
             case 1100: launch_lds_t<P, RW, DAG, true, true, 0, 0>(a, st); return true;     // A^-1 (c z + H in)
+            case 1104: launch_lds_t<P, RW, DAG, true, true, 0, 4>(a, st); return true;     // same, |v - A out|^2
             default: break;
         }
     }

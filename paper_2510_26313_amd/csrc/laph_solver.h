@@ -24,8 +24,10 @@ struct SourceSpec {
 // b^(r)(x, t)_(s, a) = delta_{t,t0} delta_{s,alpha} V_k(x, t0)_a, r = 4k + alpha, for
 // r = r_begin .. r_begin + n - 1, into FP64 even (E) and odd (O) half-vectors; with
 // noise rho, r = 4j + alpha and V_k becomes sum_{k = j mod n_dil} rho[alpha][k] V_k.
+// parity 0 / 1: that half only; sites outside win are not written.
 laph_status make_laph_sources(const Ctx &c, Operand E, Operand O, const double *V, int nev, int t0, int r_begin,
-                              int n, const double *rho = nullptr, int n_dil = 0);
+                              int n, const double *rho = nullptr, int n_dil = 0, int parity = -1,
+                              SiteWindow win = SiteWindow());
 
 // Projection of FP64 internal solutions onto the LapH vectors of every sink
 // timeslice, accumulated into tau[t][l][k][beta][alpha] for RHS r = r_begin + s.
@@ -123,6 +125,7 @@ class Solver {
     laph_status iteration();
     laph_status run_iterations(int k);
     laph_status load_sources(const SourceSpec &src);
+    laph_status load_even_source(const SourceSpec &src, SiteWindow win);
 };
 
 }  // namespace laph

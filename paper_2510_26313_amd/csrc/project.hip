@@ -44,11 +44,11 @@ __device__ __forceinline__ cplx<double> source_colour(const double2 *V, const do
 }
 
 __global__ void laph_sources_kernel(Geom g, Operand E, Operand O, const double2 *V, int nev, int t0, int r_begin,
-                                    const double2 *rho, int n_dil) {
+                                    const double2 *rho, int n_dil, int p0, SiteWindow win) {
     const int h = blockIdx.x * 256 + threadIdx.x;
     const int s = blockIdx.y;
-    const int p = blockIdx.z;
-    if (h >= g.vh) return;
+    const int p = p0 + blockIdx.z;
+    if (h >= g.vh || !in_window(win, h, g.vh)) return;
     int x, y, z, t;
     site_coords(g, p, h, x, y, z, t);
     const int r = r_begin + s;
@@ -69,12 +69,12 @@ __global__ void laph_sources_kernel(Geom g, Operand E, Operand O, const double2 
 }
 
 laph_status make_laph_sources(const Ctx &c, Operand E, Operand O, const double *V, int nev, int t0, int r_begin,
-                              int n, const double *rho, int n_dil) {
+                              int n, const double *rho, int n_dil, int parity, SiteWindow win) {
     if (n <= 0) return LAPH_OK;
-    dim3 grid((c.g.vh + 255) / 256, n, 2);
+    dim3 grid((c.g.vh + 255) / 256, n, parity < 0 ? 2 : 1);
     hipLaunchKernelGGL(laph_sources_kernel, grid, dim3(256), 0, c.stream, c.g, E, O,
                        reinterpret_cast<const double2 *>(V), nev, t0, r_begin, reinterpret_cast<const double2 *>(rho),
-                       n_dil);
+                       n_dil, parity < 0 ? 0 : parity, win);
     return check_launch("laph_sources_kernel");
 }
 

@@ -442,6 +442,13 @@ laph_status Solver::load_sources(const SourceSpec &src) {
     return make_laph_sources(*c, ws.E0, ws.O1, src.V, src.nev, src.t0, src.r_begin, src.n, src.rho, src.n_dil);
 }
 
+// b_e into E0 (sites outside win are left as they are)
+laph_status Solver::load_even_source(const SourceSpec &src, SiteWindow win) {
+    if (src.B) return pack_spinor(*c, ws.E0, src.B, LAPH_F64, src.n, 0, src.B_stride);
+    return make_laph_sources(*c, ws.E0, ws.O1, src.V, src.nev, src.t0, src.r_begin, src.n, src.rho, src.n_dil, 0,
+                             win);
+}
+
 // ---- the full solve of n slots ----------------------------------------------------
 laph_status Solver::solve(const SourceSpec &src, const std::vector<int> &slot_mass, double tol, const double *X0,
                           size_t X0_stride) {
@@ -545,19 +552,30 @@ laph_status Solver::solve(const SourceSpec &src, const std::vector<int> &slot_ma
         f = fin(n);
         // any slot still active (host guard): fold x_lo into x64
         LAPH_TRY(blas_accumulate(*c, a, prec, kModeActive));
-        // reconstruct x_o = A_oo^-1 (b_o + 1/2 H_oe x_e) into O0
-        LAPH_TRY(stage(LAPH_F64, 1, ws.E1, ws.O0, 1, 1, ws.O1, 2.0, 0, none, 0, none, 0, 0.5, 0, none, 0));
-        // true residual |B - D X|^2: even part in E0, odd part in O1
+        // reconstruct x_o = A_oo^-1 v, v = b_o + 1/2 H_oe x_e, into O0, and the true
+        // residual |B - D X|^2.  Its odd part is |v - A_oo x_o|^2: the LDS form takes it in
+        // the reconstructing pass (b_o stays in O1); otherwise it is built in O1 afterwards
+        const bool fused_odd = form64 == kFormLds;
+        if (!fused_odd)
+            LAPH_TRY(stage(LAPH_F64, 1, ws.E1, ws.O0, 1, 1, ws.O1, 2.0, 0, none, 0, none, 0, 0.5, 0, none, 0));
         LAPH_TRY(download_state());
         for (int s = 0; s < n; ++s) host_st[s].true_res2 = 0;
         LAPH_TRY(upload_state());
-        LAPH_TRY(load_sources(src));
+        if (fused_odd) {
+            LAPH_TRY(stage(LAPH_F64, 1, ws.E1, ws.O0, 1, 1, ws.O1, 2.0, 0, none, 0, none, 0, 0.5, 4, none, 0));
+            LAPH_TRY(blas_finalize(*c, fin(n, nsb64), kFinTrueRes));
+        }
+        // even part in E0: b_e again (E0 held b_hat, which LapH sources leave zero outside
+        // t0 +- 1), b_e - A_ee x_e + 1/2 H_eo x_o
+        LAPH_TRY(load_even_source(src, w_hat));
         LAPH_TRY(clover(0, 0, ws.E1, ws.E0, 1, ws.E0, 1.0, -1.0, n));
         LAPH_TRY(stage(LAPH_F64, 0, ws.O0, ws.E0, 0, 0, none, 0, 1, ws.E0, 1.0, none, 0, 0.5, 3, none, 0));
         LAPH_TRY(blas_finalize(*c, fin(n, nsb64), kFinTrueRes));
-        LAPH_TRY(clover(1, 0, ws.O0, ws.O1, 1, ws.O1, 1.0, -1.0, n));
-        LAPH_TRY(stage(LAPH_F64, 1, ws.E1, ws.O1, 0, 0, none, 0, 1, ws.O1, 1.0, none, 0, 0.5, 3, none, 0));
-        LAPH_TRY(blas_finalize(*c, fin(n, nsb64), kFinTrueRes));
+        if (!fused_odd) {
+            LAPH_TRY(clover(1, 0, ws.O0, ws.O1, 1, ws.O1, 1.0, -1.0, n));
+            LAPH_TRY(stage(LAPH_F64, 1, ws.E1, ws.O1, 0, 0, none, 0, 1, ws.O1, 1.0, none, 0, 0.5, 3, none, 0));
+            LAPH_TRY(blas_finalize(*c, fin(n, nsb64), kFinTrueRes));
+        }
         LAPH_TRY(download_state());
         // slots that converged on the even-odd residual but miss tol on the full one go again
         std::vector<int> redo;
