@@ -57,7 +57,7 @@ laph_status launch_stage(const Ctx &c, const StageSpec &s) {
     lds_block_tiles(c, s, a);
     a.dispatch_order = s.form == kFormLds ? 1 : 0;
     a.win = s.win;
-    a.clover_term = s.red == 4 ? c.clover_term(s.out_parity) : nullptr;
+    a.clover_term = (s.red == 4 || s.red == 5) ? c.clover_term(s.out_parity) : nullptr;
     a.diag = c.mass_diag();
     a.flag_filter = s.flagged;
     a.one = 1.0f;

@@ -55,8 +55,8 @@ struct StageArgs {
     int nyb, tz, tt;
     int dispatch_order;   // 1: items in dispatch order (see stage_item_range); 0: per-XCD ranges
     SiteWindow win;       // output sites computed; the others are neither read nor written
-    // reduction 4 (FP64 LDS form): the clover term of the output parity and the per-mass
-    // diagonal 4 + m0, for |v - A out|^2
+    // reductions 4 and 5 (FP64 LDS form): the clover term of the output parity and the
+    // per-mass diagonal 4 + m0 (|v - A out|^2; a y + b H in - A y2)
     const char *clover_term;
     const double *diag;
 };

@@ -120,8 +120,9 @@ __device__ __forceinline__ void stage_lds_body(const StageArgs &A, int sb, int t
     }
     __syncthreads();
     // ---- phase 2: one RHS per wave per round
-    constexpr int NQ = RED == 1 ? 2 : (RED == 2 ? 3 : (RED == 3 || RED == 4 ? 1 : 0));
+    constexpr int NQ = RED == 1 ? 2 : (RED == 2 ? 3 : (RED >= 3 ? 1 : 0));
     static_assert(RED != 4 || (CLOVER && POST == 0 && sizeof(R) == 8), "reduction 4: FP64 clover stages");
+    static_assert(RED != 5 || (!CLOVER && POST == 2 && sizeof(R) == 8), "reduction 5: FP64 residual stages");
 #pragma unroll 1
     for (int rw = 0; rw < RW; ++rw) {
         const int slot = A.tile_slots[tile * NT + rw * 4 + wave];
@@ -207,7 +208,23 @@ __device__ __forceinline__ void stage_lds_body(const StageArgs &A, int sb, int t
 #pragma unroll
                 for (int c = 0; c < 12; ++c) res[c] = res[c] + aa * yy[c];
             }
-            if (POST >= 2) {
+            if constexpr (RED == 5) {
+                // res -= A y2, the clover term A = (4 + m0) + C of the output parity, one
+                // chiral block at a time (with the reduction: y - D y2 of the full operator)
+                int ht = h;
+                asm volatile("" : "+v"(ht));
+                const R dg = R(A.diag[A.tile_mass[tile]]);
+#pragma unroll
+                for (int blk = 0; blk < 2; ++blk) {
+                    cplx<R> y2[6], q[6];
+                    R mt[36];
+                    SpinorIO<P>::load_block(A.y2.at(slot), g.vh, ht, blk, y2);
+                    CloverIO<F64>::load(A.clover_term, blk, g.vh, ht, mt);
+                    herm6_apply(mt, y2, q, dg);
+#pragma unroll
+                    for (int i = 0; i < 6; ++i) res[6 * blk + i] = res[6 * blk + i] - q[i];
+                }
+            } else if (POST >= 2) {
                 cplx<R> y2[12];
                 SpinorIO<P>::load(A.y2.at(slot), g.vh, h, y2);
                 const R aa2 = R(A.a2);
@@ -235,7 +252,7 @@ __device__ __forceinline__ void stage_lds_body(const StageArgs &A, int sb, int t
                 part[0] = d.re;
                 part[1] = d.im;
                 part[2] = n2;
-            } else if (RED == 3) {
+            } else if (RED == 3 || RED == 5) {
                 R n2 = R(0);
 #pragma unroll
                 for (int c = 0; c < 12; ++c) n2 += res[c].re * res[c].re + res[c].im * res[c].im;
@@ -300,6 +317,7 @@ inline bool launch_lds_combo(const StageSpec &s, const StageArgs &a, hipStream_t
             case 1023: launch_lds_t<P, RW, DAG, true, false, 2, 3>(a, st); return true;    // r64, |r64|^2
             case 1100: launch_lds_t<P, RW, DAG, true, true, 0, 0>(a, st); return true;     // A^-1 (c z + H in)
             case 1104: launch_lds_t<P, RW, DAG, true, true, 0, 4>(a, st); return true;     // same, |v - A out|^2
+            case 25: launch_lds_t<P, RW, DAG, false, false, 2, 5>(a, st); return true;      // a y + b H in - A y2
             default: break;
         }
     }

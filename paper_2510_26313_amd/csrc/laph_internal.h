@@ -214,6 +214,15 @@ struct SpinorIO<F64> {
             s[c] = {v.x, v.y};
         }
     }
+    // one chiral block: components 6 blk .. 6 blk + 5 (spins 2 blk and 2 blk + 1)
+    static __device__ __forceinline__ void load_block(const char *hv, int vh, int h, int blk, cplx<double> (&s)[6]) {
+        const double2 *p = reinterpret_cast<const double2 *>(hv) + (size_t)6 * blk * vh;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            double2 v = p[(size_t)c * vh + h];
+            s[c] = {v.x, v.y};
+        }
+    }
     static __device__ __forceinline__ void store(char *hv, int vh, int h, const cplx<double> (&s)[12]) {
         double2 *p = reinterpret_cast<double2 *>(hv);
 #pragma unroll

@@ -554,7 +554,8 @@ laph_status Solver::solve(const SourceSpec &src, const std::vector<int> &slot_ma
         LAPH_TRY(blas_accumulate(*c, a, prec, kModeActive));
         // reconstruct x_o = A_oo^-1 v, v = b_o + 1/2 H_oe x_e, into O0, and the true
         // residual |B - D X|^2.  Its odd part is |v - A_oo x_o|^2: the LDS form takes it in
-        // the reconstructing pass (b_o stays in O1); otherwise it is built in O1 afterwards
+        // the reconstructing pass (b_o stays in O1) and the even part in one more stage;
+        // otherwise each part is built by a clover pass and a stage
         const bool fused_odd = form64 == kFormLds;
         if (!fused_odd)
             LAPH_TRY(stage(LAPH_F64, 1, ws.E1, ws.O0, 1, 1, ws.O1, 2.0, 0, none, 0, none, 0, 0.5, 0, none, 0));
@@ -568,8 +569,13 @@ laph_status Solver::solve(const SourceSpec &src, const std::vector<int> &slot_ma
         // even part in E0: b_e again (E0 held b_hat, which LapH sources leave zero outside
         // t0 +- 1), b_e - A_ee x_e + 1/2 H_eo x_o
         LAPH_TRY(load_even_source(src, w_hat));
-        LAPH_TRY(clover(0, 0, ws.E1, ws.E0, 1, ws.E0, 1.0, -1.0, n));
-        LAPH_TRY(stage(LAPH_F64, 0, ws.O0, ws.E0, 0, 0, none, 0, 1, ws.E0, 1.0, none, 0, 0.5, 3, none, 0));
+        if (fused_odd) {
+            // one pass: b_e + 1/2 H_eo x_o - A_ee x_e
+            LAPH_TRY(stage(LAPH_F64, 0, ws.O0, ws.E0, 0, 0, none, 0, 2, ws.E0, 1.0, ws.E1, 0, 0.5, 5, none, 0));
+        } else {
+            LAPH_TRY(clover(0, 0, ws.E1, ws.E0, 1, ws.E0, 1.0, -1.0, n));
+            LAPH_TRY(stage(LAPH_F64, 0, ws.O0, ws.E0, 0, 0, none, 0, 1, ws.E0, 1.0, none, 0, 0.5, 3, none, 0));
+        }
         LAPH_TRY(blas_finalize(*c, fin(n, nsb64), kFinTrueRes));
         if (!fused_odd) {
             LAPH_TRY(clover(1, 0, ws.O0, ws.O1, 1, ws.O1, 1.0, -1.0, n));
