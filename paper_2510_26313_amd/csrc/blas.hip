@@ -102,7 +102,8 @@ __global__ __launch_bounds__(kB) void s_update_kernel(BlasArgs A) {
     }
 }
 
-// x_lo += alpha p + omega s;  r = s - omega t;  partials <r^, r>, |r|^2
+// x_lo += alpha p + omega s (x_lo = ... after a fold or at the start);  r = s - omega t;
+// partials <r^, r>, |r|^2
 template <class P, class PX>
 __global__ __launch_bounds__(kB) void xr_update_kernel(BlasArgs A) {
     using R = typename P::real;
@@ -117,7 +118,12 @@ __global__ __launch_bounds__(kB) void xr_update_kernel(BlasArgs A) {
             SpinorIO<P>::load(A.p.at(s), A.vh, h, p);
             SpinorIO<P>::load(A.r.at(s), A.vh, h, r);
             SpinorIO<P>::load(A.t.at(s), A.vh, h, t);
-            SpinorIO<PX>::load(A.x.at(s), A.vh, h, x);
+            if (A.st[s].xlo_zero) {
+#pragma unroll
+                for (int c = 0; c < 12; ++c) x[c] = {RX(0), RX(0)};
+            } else {
+                SpinorIO<PX>::load(A.x.at(s), A.vh, h, x);
+            }
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 cplx<R> dx = al * p[c] + om * r[c];
@@ -142,28 +148,26 @@ __global__ __launch_bounds__(kB) void xr_update_kernel(BlasArgs A) {
     }
 }
 
-// reliable update, part 1: x64 += x_lo; x_lo = 0   (flagged slots)
+// reliable update, part 1: x64 += x_lo (flagged slots).  x_lo is not cleared here: the
+// update's finalize marks it zero (xlo_zero) and the next x/r update overwrites it.
 template <class PX>
 __global__ __launch_bounds__(kB) void accumulate_kernel(BlasArgs A, int mode) {
     using RX = typename PX::real;
     const int h = blockIdx.x * kB + threadIdx.x;
     if (h >= A.vh) return;
     LAPH_FOR_SLOTS(A, mode, s) {
+        if (A.st[s].xlo_zero) continue;   // uniform: nothing to fold
         cplx<RX> x[12];
         cplx<double> y[12];
         SpinorIO<PX>::load(A.x.at(s), A.vh, h, x);
         SpinorIO<F64>::load(A.x64.at(s), A.vh, h, y);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            y[c] = y[c] + cplx<double>{(double)x[c].re, (double)x[c].im};
-            x[c] = {RX(0), RX(0)};
-        }
+        for (int c = 0; c < 12; ++c) y[c] = y[c] + cplx<double>{(double)x[c].re, (double)x[c].im};
         SpinorIO<F64>::store(A.x64.at(s), A.vh, h, y);
-        SpinorIO<PX>::store(A.x.at(s), A.vh, h, x);
     }
 }
 
-// r = lo(r64); restart (flag 2) or init: r^ = r; init also zeroes x_lo.
+// r = lo(r64); restart (flag 2) or init: r^ = r (the init finalize marks x_lo zero).
 // partials <r^, r>, |r|^2
 template <class P, class PX>
 __global__ __launch_bounds__(kB) void lower_kernel(BlasArgs A, int mode, int init) {
@@ -186,12 +190,6 @@ __global__ __launch_bounds__(kB) void lower_kernel(BlasArgs A, int mode, int ini
                 SpinorIO<P>::load(A.rh.at(s), A.vh, h, rh);
             } else {
                 SpinorIO<P>::load(A.rh.at(s), A.vh, h, rh);
-            }
-            if (init) {
-                cplx<typename PX::real> z[12];
-#pragma unroll
-                for (int c = 0; c < 12; ++c) z[c] = {0, 0};
-                SpinorIO<PX>::store(A.x.at(s), A.vh, h, z);
             }
             cplx<R> d = {R(0), R(0)};
             R n2 = R(0);
@@ -295,9 +293,18 @@ __global__ __launch_bounds__(kB) void flag_tiles_kernel(FlagArgs A) {
 // ---------------------------------------------------------------------------
 // finalize kernels: one 64-thread wave per slot sums the partials in fixed order
 // ---------------------------------------------------------------------------
+// Eight independent loads in flight per lane: the partials were just written by
+// workgroups on every XCD, and a loop that waits for each load in turn spends ~0.1 ms
+// of latency per slot and quantity.  The summation order is still fixed.
 __device__ __forceinline__ double wave_sum_partials(const double *p, int nsb) {
-    double s = 0;
-    for (int i = threadIdx.x; i < nsb; i += 64) s += p[i];
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int i = threadIdx.x;
+    for (; i + 7 * 64 < nsb; i += 8 * 64) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) a[k] += p[i + 64 * k];
+    }
+    for (; i < nsb; i += 64) a[0] += p[i];
+    double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
     return s;
@@ -363,6 +370,7 @@ __global__ void finalize_kernel(FinArgs A, int what) {
             }
             st.rho_prev = st.rho;
             st.rho = rn;
+            st.xlo_zero = 0;   // the x/r update just wrote x_lo
             if (r2 <= st.stop2 || r2 < st.delta2 * st.r2_upd || st.iters >= st.maxiter) st.flag |= 1;
             return;
         }
@@ -372,6 +380,7 @@ __global__ void finalize_kernel(FinArgs A, int what) {
             if (threadIdx.x) return;
             st.updates += 1;
             st.r2_upd = r2;
+            st.xlo_zero = 1;   // folded into x64 by the accumulate before the FP64 stages
             if (!isfinite(r2)) {
                 st.status = LAPH_RHS_NONFINITE;
             } else if (r2 <= st.stop2) {
@@ -402,6 +411,7 @@ __global__ void finalize_kernel(FinArgs A, int what) {
             }
             st.rho = rn;
             st.flag = 0;
+            if (init) st.xlo_zero = 1;
             return;
         }
         case kFinBnorm: {  // |B|^2 of the full-lattice source; zero or non-finite sources end here

@@ -29,6 +29,7 @@ struct SlotState {
     int status;       // LAPH_RHS_*
     int flag;         // 1: reliable update requested, 2: update + restart (breakdown)
     int iters, updates, restarts, maxiter;
+    int xlo_zero;     // 1: x_lo is zero (its memory is stale and not read) until the next x/r update
 };
 
 // Two forms of the stencil stage kernel: RHS tiles held in registers by one
