@@ -212,6 +212,19 @@ __device__ __forceinline__ typename P::real load_project(const char *hv, int vh,
     }
 }
 
+// An FP32 half-vector into FP64 arithmetic: the values are widened before the spin
+// projection, so the FP64 stage is exact to FP64 rounding in its FP32 inputs.
+template <int MU, int S>
+__device__ __forceinline__ double load_project_widened(const char *hv, int vh, int h, cplx<double> (&hs)[6]) {
+    cplx<float> pf[12];
+    SpinorIO<F32>::load(hv, vh, h, pf);
+    cplx<double> psi[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) psi[c] = {double(pf[c].re), double(pf[c].im)};
+    spin_project<MU, S>(psi, hs);
+    return 1.0;
+}
+
 // acc += sc * (u, row2(u), row3(u)): the lower spin components of (1 + S gamma_mu)
 // follow from the upper ones; the scale sc (FP16 site norm, time-boundary sign)
 // is folded into the fused multiply-adds.

@@ -21,8 +21,9 @@ constexpr int kLdsSites = 64;
 
 // One hop for one RHS: neighbour index and link (already L or L^dagger, times the
 // boundary sign) come from LDS; an FP16N neighbour is projected from its codes
-// and scaled by its norm after the colour product.
-template <class P, int MU, bool DAG, bool FWD>
+// and scaled by its norm after the colour product.  WIDEN: an FP32 input half-vector
+// in an FP64 stage.
+template <class P, int MU, bool DAG, bool FWD, bool WIDEN = false>
 __device__ __forceinline__ void lds_hop(const char *src, int vh, const typename P::real (&lnk)[8][18][kLdsSites],
                                         const int (&nbr)[8][kLdsSites], int lane, float one,
                                         cplx<typename P::real> (&acc)[12]) {
@@ -31,7 +32,11 @@ __device__ __forceinline__ void lds_hop(const char *src, int vh, const typename 
     constexpr int S = (FWD != DAG) ? -1 : 1;
     const int hn = nbr[hop][lane];
     cplx<R> hs[6], u[6], L[9];
-    const R nrm = load_project<P, MU, S>(src, vh, hn, one, hs);
+    R nrm;
+    if constexpr (WIDEN)
+        nrm = load_project_widened<MU, S>(src, vh, hn, hs);
+    else
+        nrm = load_project<P, MU, S>(src, vh, hn, one, hs);
 #pragma unroll
     for (int k = 0; k < 9; ++k) L[k] = {lnk[hop][2 * k][lane], lnk[hop][2 * k + 1][lane]};
     colour_mul<false, R, (sizeof(R) == 4)>(L, hs, u);
@@ -120,9 +125,14 @@ __device__ __forceinline__ void stage_lds_body(const StageArgs &A, int sb, int t
     }
     __syncthreads();
     // ---- phase 2: one RHS per wave per round
-    constexpr int NQ = RED == 1 ? 2 : (RED == 2 ? 3 : (RED >= 3 ? 1 : 0));
+    // RED: 0 none, 1 <w, out>, 2 <out, y> and |out|^2, 3 |out|^2; FP64 modes: 4 |v - A out|^2
+    // (v the clover input), 5 out = a y + b H in - A y2 with |out|^2, 6 the hop input is an
+    // FP32 half-vector (no reduction), 7 y2 is an FP32 half-vector, with |out|^2
+    constexpr int NQ = RED == 1 ? 2 : (RED == 2 ? 3 : (RED == 6 ? 0 : (RED >= 3 ? 1 : 0)));
+    constexpr bool WIDEN_IN = RED == 6, WIDEN_Y2 = RED == 7;
     static_assert(RED != 4 || (CLOVER && POST == 0 && sizeof(R) == 8), "reduction 4: FP64 clover stages");
     static_assert(RED != 5 || (!CLOVER && POST == 2 && sizeof(R) == 8), "reduction 5: FP64 residual stages");
+    static_assert(RED < 6 || (sizeof(R) == 8 && (RED == 6 ? POST == 0 : POST == 2)), "modes 6, 7: FP64 stages");
 #pragma unroll 1
     for (int rw = 0; rw < RW; ++rw) {
         const int slot = A.tile_slots[tile * NT + rw * 4 + wave];
@@ -139,17 +149,17 @@ __device__ __forceinline__ void stage_lds_body(const StageArgs &A, int sb, int t
             // a scheduling fence per direction: the loads of a direction's forward and
             // backward hops overlap (3 % faster than a fence per hop, 1.5 % faster than
             // none), while the loads of later directions stay after its products
-            lds_hop<P, 0, DAG, true>(src, g.vh, lnk, nbr, lane, A.one, acc);
-            lds_hop<P, 0, DAG, false>(src, g.vh, lnk, nbr, lane, A.one, acc);
+            lds_hop<P, 0, DAG, true, WIDEN_IN>(src, g.vh, lnk, nbr, lane, A.one, acc);
+            lds_hop<P, 0, DAG, false, WIDEN_IN>(src, g.vh, lnk, nbr, lane, A.one, acc);
             phase_fence(acc);
-            lds_hop<P, 1, DAG, true>(src, g.vh, lnk, nbr, lane, A.one, acc);
-            lds_hop<P, 1, DAG, false>(src, g.vh, lnk, nbr, lane, A.one, acc);
+            lds_hop<P, 1, DAG, true, WIDEN_IN>(src, g.vh, lnk, nbr, lane, A.one, acc);
+            lds_hop<P, 1, DAG, false, WIDEN_IN>(src, g.vh, lnk, nbr, lane, A.one, acc);
             phase_fence(acc);
-            lds_hop<P, 2, DAG, true>(src, g.vh, lnk, nbr, lane, A.one, acc);
-            lds_hop<P, 2, DAG, false>(src, g.vh, lnk, nbr, lane, A.one, acc);
+            lds_hop<P, 2, DAG, true, WIDEN_IN>(src, g.vh, lnk, nbr, lane, A.one, acc);
+            lds_hop<P, 2, DAG, false, WIDEN_IN>(src, g.vh, lnk, nbr, lane, A.one, acc);
             phase_fence(acc);
-            lds_hop<P, 3, DAG, true>(src, g.vh, lnk, nbr, lane, A.one, acc);
-            lds_hop<P, 3, DAG, false>(src, g.vh, lnk, nbr, lane, A.one, acc);
+            lds_hop<P, 3, DAG, true, WIDEN_IN>(src, g.vh, lnk, nbr, lane, A.one, acc);
+            lds_hop<P, 3, DAG, false, WIDEN_IN>(src, g.vh, lnk, nbr, lane, A.one, acc);
             phase_fence(acc);
             if (PRE) {
                 cplx<R> zz[12];
@@ -226,7 +236,14 @@ __device__ __forceinline__ void stage_lds_body(const StageArgs &A, int sb, int t
                 }
             } else if (POST >= 2) {
                 cplx<R> y2[12];
-                SpinorIO<P>::load(A.y2.at(slot), g.vh, h, y2);
+                if constexpr (WIDEN_Y2) {
+                    cplx<float> yf[12];
+                    SpinorIO<F32>::load(A.y2.at(slot), g.vh, h, yf);
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) y2[c] = {R(yf[c].re), R(yf[c].im)};
+                } else {
+                    SpinorIO<P>::load(A.y2.at(slot), g.vh, h, y2);
+                }
                 const R aa2 = R(A.a2);
 #pragma unroll
                 for (int c = 0; c < 12; ++c) res[c] = res[c] + aa2 * y2[c];
@@ -252,7 +269,7 @@ __device__ __forceinline__ void stage_lds_body(const StageArgs &A, int sb, int t
                 part[0] = d.re;
                 part[1] = d.im;
                 part[2] = n2;
-            } else if (RED == 3 || RED == 5) {
+            } else if (RED == 3 || RED == 5 || RED == 7) {
                 R n2 = R(0);
 #pragma unroll
                 for (int c = 0; c < 12; ++c) n2 += res[c].re * res[c].re + res[c].im * res[c].im;
@@ -318,6 +335,8 @@ inline bool launch_lds_combo(const StageSpec &s, const StageArgs &a, hipStream_t
             case 1100: launch_lds_t<P, RW, DAG, true, true, 0, 0>(a, st); return true;     // A^-1 (c z + H in)
             case 1104: launch_lds_t<P, RW, DAG, true, true, 0, 4>(a, st); return true;     // same, |v - A out|^2
             case 25: launch_lds_t<P, RW, DAG, false, false, 2, 5>(a, st); return true;      // a y + b H in - A y2
+            case 1006: launch_lds_t<P, RW, DAG, true, false, 0, 6>(a, st); return true;    // A^-1 H in, in FP32
+            case 1027: launch_lds_t<P, RW, DAG, true, false, 2, 7>(a, st); return true;    // r64 with y2 FP32
             default: break;
         }
     }
