@@ -127,7 +127,8 @@ __device__ __forceinline__ void stage_lds_body(const StageArgs &A, int sb, int t
     // ---- phase 2: one RHS per wave per round
     // RED: 0 none, 1 <w, out>, 2 <out, y> and |out|^2, 3 |out|^2; FP64 modes: 4 |v - A out|^2
     // (v the clover input), 5 out = a y + b H in - A y2 with |out|^2, 6 the hop input is an
-    // FP32 half-vector (no reduction), 7 y2 is an FP32 half-vector, with |out|^2
+    // FP32 half-vector (no reduction), 7 y2 is an FP32 half-vector, added to w as well, with
+    // |out|^2
     constexpr int NQ = RED == 1 ? 2 : (RED == 2 ? 3 : (RED == 6 ? 0 : (RED >= 3 ? 1 : 0)));
     constexpr bool WIDEN_IN = RED == 6, WIDEN_Y2 = RED == 7;
     static_assert(RED != 4 || (CLOVER && POST == 0 && sizeof(R) == 8), "reduction 4: FP64 clover stages");
@@ -250,6 +251,19 @@ __device__ __forceinline__ void stage_lds_body(const StageArgs &A, int sb, int t
             }
             SpinorIO<P>::store(A.out.at(slot), g.vh, h, res);
             hop_fence();
+            if constexpr (WIDEN_Y2) {
+                // fold the correction y2 into x64 (w) as well (no other site reads w here);
+                // y2 is loaded again (a cache hit) rather than kept live across the store
+                int hw = h;
+                asm volatile("" : "+v"(hw));
+                cplx<float> yf[12];
+                cplx<R> xw[12];
+                SpinorIO<F32>::load(A.y2.at(slot), g.vh, hw, yf);
+                SpinorIO<P>::load(A.w.at(slot), g.vh, hw, xw);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) xw[c] = xw[c] + cplx<R>{R(yf[c].re), R(yf[c].im)};
+                SpinorIO<P>::store(A.w.at(slot), g.vh, hw, xw);
+            }
             if (RED == 1) {
                 cplx<R> ww[12];
                 SpinorIO<P>::load(A.w.at(slot), g.vh, h, ww);
@@ -336,7 +350,7 @@ inline bool launch_lds_combo(const StageSpec &s, const StageArgs &a, hipStream_t
             case 1104: launch_lds_t<P, RW, DAG, true, true, 0, 4>(a, st); return true;     // same, |v - A out|^2
             case 25: launch_lds_t<P, RW, DAG, false, false, 2, 5>(a, st); return true;      // a y + b H in - A y2
             case 1006: launch_lds_t<P, RW, DAG, true, false, 0, 6>(a, st); return true;    // A^-1 H in, in FP32
-            case 1027: launch_lds_t<P, RW, DAG, true, false, 2, 7>(a, st); return true;    // r64 with y2 FP32
+            case 1027: launch_lds_t<P, RW, DAG, true, false, 2, 7>(a, st); return true;    // r64, y2 FP32, w += y2
             default: break;
         }
     }

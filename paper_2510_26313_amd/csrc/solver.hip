@@ -392,12 +392,15 @@ laph_status Solver::iteration() {
     // reliable update of the flagged slots: x64 += x_lo and the FP64 residual of x64.
     // With an FP32 x_lo and the LDS form the residual follows the same exact correction,
     // r64 -= M_hat x_lo in FP64 arithmetic on the widened x_lo (the stages read x_lo, half
-    // the bytes of x64, and r64 in place of b_hat); otherwise r64 = b_hat - M_hat x64
-    LAPH_TRY(blas_accumulate(*c, a, prec, kModeFlagged));
+    // the bytes of x64, and r64 in place of b_hat), and the second stage also folds x_lo
+    // into x64 (x_lo of a flagged slot is never marked zero here: every iteration's x/r
+    // update writes it before the update decision); otherwise x64 += x_lo, then
+    // r64 = b_hat - M_hat x64
     if (prec != LAPH_F64 && form64 == kFormLds) {
         LAPH_TRY(stage(LAPH_F64, 1, ws.x, ws.O0, 1, 0, none, 0, 0, none, 0, none, 0, 1.0, 6, none, 1));
-        LAPH_TRY(stage(LAPH_F64, 0, ws.O0, ws.E2, 1, 0, none, 0, 2, ws.E2, 1.0, ws.x, -1.0, 0.25, 7, none, 1));
+        LAPH_TRY(stage(LAPH_F64, 0, ws.O0, ws.E2, 1, 0, none, 0, 2, ws.E2, 1.0, ws.x, -1.0, 0.25, 7, ws.E1, 1));
     } else {
+        LAPH_TRY(blas_accumulate(*c, a, prec, kModeFlagged));
         LAPH_TRY(stage(LAPH_F64, 1, ws.E1, ws.O0, 1, 0, none, 0, 0, none, 0, none, 0, 1.0, 0, none, 1));
         LAPH_TRY(stage(LAPH_F64, 0, ws.O0, ws.E2, 1, 0, none, 0, 2, ws.E0, 1.0, ws.E1, -1.0, 0.25, 3, none, 1));
     }
