@@ -380,7 +380,7 @@ __global__ void finalize_kernel(FinArgs A, int what) {
             if (threadIdx.x) return;
             st.updates += 1;
             st.r2_upd = r2;
-            st.xlo_zero = 1;   // folded into x64 by the accumulate before the FP64 stages
+            st.xlo_zero = 1;   // folded into x64 by this update (accumulate, or the FP64 stage forming r64)
             if (!isfinite(r2)) {
                 st.status = LAPH_RHS_NONFINITE;
             } else if (r2 <= st.stop2) {
